@@ -1,0 +1,667 @@
+/*
+ * FP64 CPU oracle for the manifold-based P-NDF (arXiv 2505.08985).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the GPU
+ * library is checked against.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the library never does, and the two
+ * share no code, headers, tables or constants.
+ *
+ * Everything here is double precision, evaluated from the float32 inputs
+ * (converted exactly).  The few quantities that the method's definition fixes in
+ * the query's own float32 precision (support half-width, support box, cut
+ * threshold) are computed in float, as the definition below states.
+ *
+ * Definitions followed (section / equation names of the paper):
+ *   - mesh: two triangles per texel cell, Eq. (interpolation) and Fig. normal_map;
+ *     lower triangle (u0,u1,u2) with normals (n0,n1,n2), upper triangle
+ *     (u3,u2,u1) with normals (n3,n2,n1); the map is periodic (a torus).
+ *   - Jacobian: twice the normal-space triangle area, Eq. (jacobian).
+ *   - clamp: triangles with Jacobian below eps are replaced by an equilateral
+ *     triangle of area eps/2 centred at n(floor(u)+1/2), section "Preventing
+ *     Jacobian singularity" and Eq. (debias).
+ *   - evaluation: D(m,x) = sum over triangles in the footprint of
+ *     k(a l0 + b l1 + c l2 - x) 1[m in n(tri)] / (2 |n(tri)|), Eq. (ndf_eval),
+ *     with barycentrics as signed-area ratios (Table notation, "bary").
+ *   - footprint kernel: normalised Gaussian of standard deviation sigma with
+ *     support half-width r = 3 sigma (Results: "(6 sigma)^2 footprint"), truncated
+ *     at texel-cell granularity: every triangle of every periodic cell image whose
+ *     closed unit square meets [x-r, x+r] is included.
+ *   - cluster hierarchy: four vertex normals per 2^l x 2^l node minimising the
+ *     inverse-Jacobian-weighted L2 distance, Eq. (normal_optimization) and its
+ *     supplement derivation; e^l is the minimised objective value.
+ *   - cut: starting at the entry level ceil(log2 max(r)) (supplement, "Entry
+ *     level"), descend until a node satisfies e^l <= r_x r_y tau (section
+ *     "Acceleration by mesh clustering").
+ *
+ * Status of the pins: every function here is pinned by the CPU tests (flat map,
+ * tilted triangle pair, linear field, mass invariant, Monte Carlo normal
+ * histogram, the supplement's printed coefficient matrices, transpose
+ * invariance) except the orientation of the equilateral replacement triangle,
+ * which the paper leaves free ("any other shape"): parity unpinned, fixed by
+ * convention (vertices at 90, 210, 330 degrees in (a, b, c) order).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_PI 3.14159265358979323846
+
+/* ---------------------------------------------------------------- helpers -- */
+
+static int ilog2_exact(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) l++;
+    return ((1 << l) == n) ? l : -1;
+}
+
+static long floor_div(long a, long b) /* b > 0 */
+{
+    long q = a / b;
+    if ((a % b != 0) && (a < 0)) q -= 1;
+    return q;
+}
+
+static long ceil_div(long a, long b) /* b > 0 */
+{
+    return -floor_div(-a, b);
+}
+
+static long wrap(long a, long n) { long r = a % n; return r < 0 ? r + n : r; }
+
+/* normal of texel (i, j), periodic */
+static void texel(const float* nrm, int n, long i, long j, double out[2])
+{
+    long ii = wrap(i, n), jj = wrap(j, n);
+    out[0] = (double)nrm[2 * (jj * n + ii) + 0];
+    out[1] = (double)nrm[2 * (jj * n + ii) + 1];
+}
+
+/* |(c - a) x (b - a)|, the Jacobian of Eq. (jacobian).  Products are rounded
+ * before the difference (no fused multiply-add) so the clamp decision is a
+ * fixed function of the float inputs. */
+static double jac(const double a[2], const double b[2], const double c[2])
+{
+    double p = (c[0] - a[0]) * (b[1] - a[1]);
+    double q = (c[1] - a[1]) * (b[0] - a[0]);
+    return fabs(p - q);
+}
+
+/* vertices of the equilateral replacement triangle: circumradius rho around
+ * centre, vertices at 90, 210, 330 degrees assigned to (a, b, c) */
+static void eqtri(const double centre[2], double rho, double v[3][2])
+{
+    static const double ang[3] = {90.0, 210.0, 330.0};
+    for (int k = 0; k < 3; k++) {
+        double t = ang[k] * OR_PI / 180.0;
+        v[k][0] = centre[0] + rho * cos(t);
+        v[k][1] = centre[1] + rho * sin(t);
+    }
+}
+
+/* circumradius of an equilateral triangle of the given area */
+static double eq_rho(double area) { return sqrt(4.0 * area / (3.0 * sqrt(3.0))); }
+
+/* signed double area of (p, q, r) */
+static double sarea2(const double p[2], const double q[2], const double r[2])
+{
+    return (q[0] - p[0]) * (r[1] - p[1]) - (q[1] - p[1]) * (r[0] - p[0]);
+}
+
+static double seg_dist(const double h[2], const double a[2], const double b[2])
+{
+    double ex = b[0] - a[0], ey = b[1] - a[1];
+    double px = h[0] - a[0], py = h[1] - a[1];
+    double ee = ex * ex + ey * ey;
+    double t = ee > 0 ? (px * ex + py * ey) / ee : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    double dx = px - t * ex, dy = py - t * ey;
+    return sqrt(dx * dx + dy * dy);
+}
+
+/* ------------------------------------------------------------------ mesh -- */
+
+/* Per cell (i, j): Jacobians of the lower and upper triangle and the clamp bits.
+ * det[2*(j*n+i)+0] lower, +1 upper; deg bit0 = lower clamped, bit1 = upper. */
+int or_mesh(int n, const float* nrm, float eps, double* det, uint8_t* deg)
+{
+    if (ilog2_exact(n) < 0 || n < 2) return 1;
+    const double e = (double)eps;
+    for (long j = 0; j < n; j++)
+        for (long i = 0; i < n; i++) {
+            double n0[2], n1[2], n2[2], n3[2];
+            texel(nrm, n, i, j, n0);
+            texel(nrm, n, i + 1, j, n1);
+            texel(nrm, n, i, j + 1, n2);
+            texel(nrm, n, i + 1, j + 1, n3);
+            double dl = jac(n0, n1, n2);
+            double du = jac(n3, n2, n1);
+            det[2 * (j * n + i) + 0] = dl;
+            det[2 * (j * n + i) + 1] = du;
+            deg[j * n + i] = (uint8_t)((dl < e ? 1 : 0) | (du < e ? 2 : 0));
+        }
+    return 0;
+}
+
+/* --------------------------------------------------------------- cluster -- */
+
+/* cluster barycentric basis lambda^l at node-local normalised coords (U, V) for
+ * the cluster half `chalf` (0 lower: U+V<=1, 1 upper) */
+static void clu_basis(double U, double V, int chalf, double lam[4])
+{
+    if (chalf == 0) {
+        lam[0] = 1.0 - U - V; lam[1] = U; lam[2] = V; lam[3] = 0.0;
+    } else {
+        lam[0] = 0.0; lam[1] = 1.0 - V; lam[2] = 1.0 - U; lam[3] = U + V - 1.0;
+    }
+}
+
+/* fine triangle `half` of local cell (li, lj) inside a node of side s: its uv
+ * vertices (node-local), its normals, and which cluster half it lies in */
+static int fine_tri(int s, int li, int lj, int half, const double nv[4][2],
+                    double uv[3][2], double nn[3][2])
+{
+    if (half == 0) {
+        uv[0][0] = li;     uv[0][1] = lj;
+        uv[1][0] = li + 1; uv[1][1] = lj;
+        uv[2][0] = li;     uv[2][1] = lj + 1;
+        memcpy(nn[0], nv[0], sizeof nn[0]);
+        memcpy(nn[1], nv[1], sizeof nn[1]);
+        memcpy(nn[2], nv[2], sizeof nn[2]);
+        return (li + lj <= s - 1) ? 0 : 1;
+    }
+    uv[0][0] = li + 1; uv[0][1] = lj + 1;
+    uv[1][0] = li;     uv[1][1] = lj + 1;
+    uv[2][0] = li + 1; uv[2][1] = lj;
+    memcpy(nn[0], nv[3], sizeof nn[0]);
+    memcpy(nn[1], nv[2], sizeof nn[1]);
+    memcpy(nn[2], nv[1], sizeof nn[2]);
+    return (li + lj <= s - 2) ? 0 : 1;
+}
+
+/* Contribution of one fine triangle to the gradient terms of the cluster
+ * objective: A += w 2 int(lam lam^T), B += -w 2 int(lam n^T), C += w int(|n|^2),
+ * by the three-edge-midpoint rule (exact for quadratics on a triangle; area 1/2).
+ * With w = 1 these are the supplement's A_ij, B_ij matrices. */
+static void fine_contrib(int s, const double uv[3][2], const double nn[3][2], int chalf,
+                         double w, double A[4][4], double B[4][2], double* C)
+{
+    for (int k = 0; k < 3; k++) {
+        int k2 = (k + 1) % 3;
+        double mu = 0.5 * (uv[k][0] + uv[k2][0]) / s;
+        double mv = 0.5 * (uv[k][1] + uv[k2][1]) / s;
+        double mn[2] = {0.5 * (nn[k][0] + nn[k2][0]), 0.5 * (nn[k][1] + nn[k2][1])};
+        double lam[4];
+        clu_basis(mu, mv, chalf, lam);
+        /* quadrature weight area/3 = 1/6; A and B carry the factor 2 */
+        for (int a = 0; a < 4; a++) {
+            for (int b = 0; b < 4; b++) A[a][b] += w * (2.0 / 6.0) * lam[a] * lam[b];
+            B[a][0] += -w * (2.0 / 6.0) * lam[a] * mn[0];
+            B[a][1] += -w * (2.0 / 6.0) * lam[a] * mn[1];
+        }
+        *C += w * (1.0 / 6.0) * (mn[0] * mn[0] + mn[1] * mn[1]);
+    }
+}
+
+/* Exposed for the pin against the supplement's printed matrices: the fine cell
+ * (i, j) of a node of side a, triangle `half` (0 = (i,j),(i+1,j),(i,j+1)),
+ * corner normals nv = n0..n3 (x,y pairs), weight 1.  Returns the cluster half. */
+int or_fine_contrib(int a, int i, int j, int half, const double* nv8,
+                    double* A16, double* B8, double* C1)
+{
+    double nv[4][2], uv[3][2], nn[3][2], A[4][4] = {{0}}, B[4][2] = {{0}}, C = 0;
+    for (int k = 0; k < 4; k++) { nv[k][0] = nv8[2 * k]; nv[k][1] = nv8[2 * k + 1]; }
+    int ch = fine_tri(a, i, j, half, nv, uv, nn);
+    fine_contrib(a, uv, nn, ch, 1.0, A, B, &C);
+    memcpy(A16, A, sizeof A);
+    memcpy(B8, B, sizeof B);
+    *C1 = C;
+    return ch;
+}
+
+/* plain Gaussian elimination with partial pivoting, A x = rhs (4 x 2) */
+static int solve4(double A[4][4], double R[4][2], double X[4][2])
+{
+    double M[4][6];
+    for (int r = 0; r < 4; r++) {
+        for (int c = 0; c < 4; c++) M[r][c] = A[r][c];
+        M[r][4] = R[r][0];
+        M[r][5] = R[r][1];
+    }
+    for (int c = 0; c < 4; c++) {
+        int p = c;
+        for (int r = c + 1; r < 4; r++)
+            if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+        if (M[p][c] == 0.0) return 1;
+        if (p != c)
+            for (int k = 0; k < 6; k++) { double t = M[c][k]; M[c][k] = M[p][k]; M[p][k] = t; }
+        for (int r = c + 1; r < 4; r++) {
+            double f = M[r][c] / M[c][c];
+            for (int k = c; k < 6; k++) M[r][k] -= f * M[c][k];
+        }
+    }
+    for (int r = 3; r >= 0; r--)
+        for (int q = 0; q < 2; q++) {
+            double v = M[r][4 + q];
+            for (int k = r + 1; k < 4; k++) v -= M[r][k] * X[k][q];
+            X[r][q] = v / M[r][r];
+        }
+    return 0;
+}
+
+/* Cluster fit of node (level, I, J): argmin of Eq. (normal_optimization) with
+ * weight 1 / max(Jacobian, eps), solved from A N = -B; e = objective at the
+ * optimum, integrated again over every fine triangle.  nstar: N0..N3 (x, y). */
+static int cluster_node(int n, const float* nrm, double eps, int level, long I, long J,
+                        double nstar[8], double* e_out)
+{
+    const int s = 1 << level;
+    double A[4][4] = {{0}}, B[4][2] = {{0}}, C = 0.0;
+    for (int lj = 0; lj < s; lj++)
+        for (int li = 0; li < s; li++) {
+            double nv[4][2];
+            long gi = I * s + li, gj = J * s + lj;
+            texel(nrm, n, gi, gj, nv[0]);
+            texel(nrm, n, gi + 1, gj, nv[1]);
+            texel(nrm, n, gi, gj + 1, nv[2]);
+            texel(nrm, n, gi + 1, gj + 1, nv[3]);
+            for (int half = 0; half < 2; half++) {
+                double uv[3][2], nn[3][2];
+                int ch = fine_tri(s, li, lj, half, nv, uv, nn);
+                double d = jac(nn[0], nn[1], nn[2]);
+                double w = 1.0 / (d < eps ? eps : d);
+                fine_contrib(s, uv, nn, ch, w, A, B, &C);
+            }
+        }
+    double R[4][2], X[4][2];
+    for (int a = 0; a < 4; a++) { R[a][0] = -B[a][0]; R[a][1] = -B[a][1]; }
+    if (solve4(A, R, X)) return 1;
+    double E = 0.0;
+    for (int lj = 0; lj < s; lj++)
+        for (int li = 0; li < s; li++) {
+            double nv[4][2];
+            long gi = I * s + li, gj = J * s + lj;
+            texel(nrm, n, gi, gj, nv[0]);
+            texel(nrm, n, gi + 1, gj, nv[1]);
+            texel(nrm, n, gi, gj + 1, nv[2]);
+            texel(nrm, n, gi + 1, gj + 1, nv[3]);
+            for (int half = 0; half < 2; half++) {
+                double uv[3][2], nn[3][2];
+                int ch = fine_tri(s, li, lj, half, nv, uv, nn);
+                double d = jac(nn[0], nn[1], nn[2]);
+                double w = 1.0 / (d < eps ? eps : d);
+                for (int k = 0; k < 3; k++) {
+                    int k2 = (k + 1) % 3;
+                    double mu = 0.5 * (uv[k][0] + uv[k2][0]) / s;
+                    double mv = 0.5 * (uv[k][1] + uv[k2][1]) / s;
+                    double lam[4];
+                    clu_basis(mu, mv, ch, lam);
+                    double fx = -0.5 * (nn[k][0] + nn[k2][0]);
+                    double fy = -0.5 * (nn[k][1] + nn[k2][1]);
+                    for (int a = 0; a < 4; a++) { fx += lam[a] * X[a][0]; fy += lam[a] * X[a][1]; }
+                    E += w * (1.0 / 6.0) * (fx * fx + fy * fy);
+                }
+            }
+        }
+    for (int a = 0; a < 4; a++) { nstar[2 * a] = X[a][0]; nstar[2 * a + 1] = X[a][1]; }
+    *e_out = E;
+    return 0;
+}
+
+/* Cluster fits for `count` nodes of one level (node id = J * (n >> level) + I).
+ * Parallel over nodes. */
+int or_cluster_nodes(int n, const float* nrm, float eps, int level, const int64_t* ids,
+                     int64_t count, double* nstar, double* e)
+{
+    int L = ilog2_exact(n);
+    if (L < 1 || level < 1 || level > L) return 1;
+    const long m = n >> level;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+    for (int64_t k = 0; k < count; k++) {
+        long id = (long)ids[k];
+        if (id < 0 || id >= m * m) { bad |= 1; continue; }
+        bad |= cluster_node(n, nrm, (double)eps, level, id % m, id / m, nstar + 8 * k, e + k);
+    }
+    return bad;
+}
+
+/* -------------------------------------------------------------- evaluate -- */
+
+typedef struct {
+    int n, L;
+    const float* nrm;
+    double eps;
+    const float* clu_n; /* all levels 1..L packed, 8 floats per node (oracle's own fit, rounded) */
+    const float* clu_e; /* all levels 1..L packed, 1 float per node */
+} map_t;
+
+static long level_offset(int n, int level) /* first node of `level` in packed arrays */
+{
+    long off = 0;
+    for (int l = 1; l < level; l++) off += (long)(n >> l) * (n >> l);
+    return off;
+}
+
+typedef struct {
+    double x, y, sx, sy, h[2];
+    long cxlo, cxhi, cylo, cyhi;
+    int l0;
+    float t; /* cut threshold (float, as fixed by the definition) */
+    int use_cut;
+    double band;
+} query_t;
+
+typedef struct {
+    double D;
+    long nhit, namb;
+    int flags; /* bit0: a cut decision sits within rounding of the threshold */
+    /* optional record buffers (NULL = count only) */
+    uint64_t* hid; double* hterm;
+    uint64_t* aid; double* aterm; uint8_t* ahit;
+} acc_t;
+
+#define OR_ID(l, I, J, half) \
+    (((uint64_t)(l) << 58) | ((uint64_t)(J) << 29) | ((uint64_t)(I) << 1) | (uint64_t)(half))
+
+/* images p along one axis for a node of side s starting at torus cell `start`:
+ * the node's closed square [start + pN, start + s + pN] meets the box iff one of
+ * its unit cells lies in the included cell range [clo, chi] */
+static void image_range(long start, long s, long clo, long chi, long n, long* p0, long* p1)
+{
+    *p0 = ceil_div(clo - start - s + 1, n);
+    *p1 = floor_div(chi - start, n);
+}
+
+static double gauss_sum(double ucoord, long start, long s, long clo, long chi, long n,
+                        double x, double sig)
+{
+    long p0, p1;
+    image_range(start, s, clo, chi, n, &p0, &p1);
+    double g = 0.0;
+    for (long p = p0; p <= p1; p++) {
+        double d = ucoord + (double)p * (double)n - x;
+        g += exp(-d * d / (2.0 * sig * sig));
+    }
+    return g;
+}
+
+/* Test one triangle with normal-space vertices nv (a, b, c) and uv vertices
+ * (a, b, c); Jacobian det_used; node (level, I, J) of side s for the images. */
+static void test_tri(const map_t* m, const query_t* q, acc_t* acc, uint64_t id,
+                     const double nv[3][2], const double uv[3][2], double det_used,
+                     long I, long J, long s)
+{
+    double S = sarea2(nv[0], nv[1], nv[2]);
+    double l0 = sarea2(q->h, nv[1], nv[2]) / S;
+    double l1 = sarea2(nv[0], q->h, nv[2]) / S;
+    double l2 = sarea2(nv[0], nv[1], q->h) / S;
+    int hit = (l0 >= 0 && l0 <= 1 && l1 >= 0 && l1 <= 1 && l2 >= 0 && l2 <= 1);
+    int amb = 0;
+    double dmin = seg_dist(q->h, nv[0], nv[1]);
+    double d1 = seg_dist(q->h, nv[1], nv[2]);
+    double d2 = seg_dist(q->h, nv[2], nv[0]);
+    if (d1 < dmin) dmin = d1;
+    if (d2 < dmin) dmin = d2;
+    amb = dmin < q->band;
+    if (!hit && !amb) return;
+    double ux = uv[0][0] * l0 + uv[1][0] * l1 + uv[2][0] * l2;
+    double uy = uv[0][1] * l0 + uv[1][1] * l1 + uv[2][1] * l2;
+    double gx = gauss_sum(ux, I * s, s, q->cxlo, q->cxhi, m->n, q->x, q->sx);
+    double gy = gauss_sum(uy, J * s, s, q->cylo, q->cyhi, m->n, q->y, q->sy);
+    double term = gx * gy / (2.0 * OR_PI * q->sx * q->sy) / det_used;
+    if (hit) {
+        if (acc->hid) { acc->hid[acc->nhit] = id; acc->hterm[acc->nhit] = term; }
+        acc->nhit++;
+        acc->D += term;
+    }
+    if (amb) {
+        if (acc->aid) {
+            acc->aid[acc->namb] = id; acc->aterm[acc->namb] = term;
+            acc->ahit[acc->namb] = (uint8_t)hit;
+        }
+        acc->namb++;
+    }
+}
+
+/* the two triangles of torus cell (i, j), clamp applied */
+static void test_cell(const map_t* m, const query_t* q, acc_t* acc, long i, long j)
+{
+    double nv4[4][2];
+    texel(m->nrm, m->n, i, j, nv4[0]);
+    texel(m->nrm, m->n, i + 1, j, nv4[1]);
+    texel(m->nrm, m->n, i, j + 1, nv4[2]);
+    texel(m->nrm, m->n, i + 1, j + 1, nv4[3]);
+    double centre[2] = {0.5 * (nv4[1][0] + nv4[2][0]), 0.5 * (nv4[1][1] + nv4[2][1])};
+    for (int half = 0; half < 2; half++) {
+        double nv[3][2], uv[3][2];
+        if (half == 0) {
+            memcpy(nv[0], nv4[0], sizeof nv[0]); memcpy(nv[1], nv4[1], sizeof nv[0]);
+            memcpy(nv[2], nv4[2], sizeof nv[0]);
+            uv[0][0] = i; uv[0][1] = j; uv[1][0] = i + 1; uv[1][1] = j; uv[2][0] = i; uv[2][1] = j + 1;
+        } else {
+            memcpy(nv[0], nv4[3], sizeof nv[0]); memcpy(nv[1], nv4[2], sizeof nv[0]);
+            memcpy(nv[2], nv4[1], sizeof nv[0]);
+            uv[0][0] = i + 1; uv[0][1] = j + 1; uv[1][0] = i; uv[1][1] = j + 1; uv[2][0] = i + 1; uv[2][1] = j;
+        }
+        double d = jac(nv[0], nv[1], nv[2]);
+        double du = d;
+        if (d < m->eps) {
+            eqtri(centre, eq_rho(0.5 * m->eps), nv);
+            du = m->eps;
+        }
+        test_tri(m, q, acc, OR_ID(0, i, j, half), nv, uv, du, i, j, 1);
+    }
+}
+
+/* the two cluster triangles of node (level, I, J): corners at spacing s, normals
+ * from the cluster fit; Jacobian with respect to u is 2 area_n / s^2, clamped at
+ * eps with an equilateral triangle of area eps s^2 / 2 */
+static void test_cluster(const map_t* m, const query_t* q, acc_t* acc, int level, long I, long J)
+{
+    const long s = 1L << level;
+    const long mm = m->n >> level;
+    const float* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * mm + I);
+    double N[4][2];
+    for (int k = 0; k < 4; k++) { N[k][0] = cn[2 * k]; N[k][1] = cn[2 * k + 1]; }
+    double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
+    for (int half = 0; half < 2; half++) {
+        double nv[3][2], uv[3][2];
+        double X0 = (double)(I * s), Y0 = (double)(J * s), X1 = X0 + s, Y1 = Y0 + s;
+        if (half == 0) {
+            memcpy(nv[0], N[0], sizeof nv[0]); memcpy(nv[1], N[1], sizeof nv[0]);
+            memcpy(nv[2], N[2], sizeof nv[0]);
+            uv[0][0] = X0; uv[0][1] = Y0; uv[1][0] = X1; uv[1][1] = Y0; uv[2][0] = X0; uv[2][1] = Y1;
+        } else {
+            memcpy(nv[0], N[3], sizeof nv[0]); memcpy(nv[1], N[2], sizeof nv[0]);
+            memcpy(nv[2], N[1], sizeof nv[0]);
+            uv[0][0] = X1; uv[0][1] = Y1; uv[1][0] = X0; uv[1][1] = Y1; uv[2][0] = X1; uv[2][1] = Y0;
+        }
+        double du = jac(nv[0], nv[1], nv[2]) / ((double)s * (double)s);
+        if (du < m->eps) {
+            eqtri(centre, eq_rho(0.5 * m->eps * (double)s * (double)s), nv);
+            du = m->eps;
+        }
+        test_tri(m, q, acc, OR_ID(level, I, J, half), nv, uv, du, I, J, s);
+    }
+}
+
+/* does node (level, I, J) overlap the box in some periodic image (per axis) */
+static int node_in(const query_t* q, int n, int level, long I, long J)
+{
+    long s = 1L << level, p0, p1;
+    image_range(I * s, s, q->cxlo, q->cxhi, n, &p0, &p1);
+    if (p0 > p1) return 0;
+    image_range(J * s, s, q->cylo, q->cyhi, n, &p0, &p1);
+    return p0 <= p1;
+}
+
+/* top-down cut: from a node at or below the entry level, stop at the first node
+ * with e^l <= t (levels >= 1), else descend; cells represent themselves */
+static void descend(const map_t* m, const query_t* q, acc_t* acc, int level, long I, long J)
+{
+    if (!node_in(q, m->n, level, I, J)) return;
+    if (level == 0) { test_cell(m, q, acc, I, J); return; }
+    long mm = m->n >> level;
+    float e = m->clu_e[level_offset(m->n, level) + J * mm + I];
+    double de = (double)e - (double)q->t;
+    if (fabs(de) <= 1e-5 * fabs((double)q->t)) acc->flags |= 1;
+    if (e <= q->t) { test_cluster(m, q, acc, level, I, J); return; }
+    for (int dj = 0; dj < 2; dj++)
+        for (int di = 0; di < 2; di++) descend(m, q, acc, level - 1, 2 * I + di, 2 * J + dj);
+}
+
+static int setup_query(const map_t* m, const float* qr, float tau, float s2r, double band,
+                       query_t* q)
+{
+    float x = qr[0], y = qr[1], sx = qr[2], sy = qr[3], hx = qr[4], hy = qr[5];
+    const float lim = 16777216.0f; /* 2^24 */
+    if (!(isfinite(x) && isfinite(y) && isfinite(sx) && isfinite(sy) && isfinite(hx) &&
+          isfinite(hy)))
+        return 1;
+    if (!(sx > 0.0f && sy > 0.0f)) return 1;
+    float rx = s2r * sx, ry = s2r * sy; /* float products */
+    if (!(fabsf(x) <= lim && fabsf(y) <= lim && rx <= lim && ry <= lim)) return 1;
+    float lox = x - rx, hix = x + rx, loy = y - ry, hiy = y + ry;
+    q->x = x; q->y = y; q->sx = sx; q->sy = sy; q->h[0] = hx; q->h[1] = hy;
+    q->cxlo = (long)ceilf(lox) - 1; q->cxhi = (long)floorf(hix);
+    q->cylo = (long)ceilf(loy) - 1; q->cyhi = (long)floorf(hiy);
+    float rmax = rx > ry ? rx : ry;
+    int l0 = 0;
+    while (l0 < m->L && (float)(1L << l0) < rmax) l0++;
+    q->l0 = l0;
+    float rr = rx * ry;
+    q->t = rr * tau;
+    q->use_cut = tau > 0.0f;
+    q->band = band;
+    return 0;
+}
+
+/* included torus indices along one axis: all of them when the cell range is at
+ * least one period long, else the range itself (each unrolled cell is then a
+ * distinct torus cell) */
+static long axis_cells(long clo, long chi, long n, long* idx)
+{
+    long cnt = 0;
+    if (chi - clo + 1 >= n) {
+        for (long i = 0; i < n; i++) idx[cnt++] = i;
+    } else {
+        for (long c = clo; c <= chi; c++) idx[cnt++] = wrap(c, n);
+    }
+    return cnt;
+}
+
+static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
+{
+    const long n = m->n;
+    long* xi = (long*)malloc(sizeof(long) * (size_t)n);
+    long* yj = (long*)malloc(sizeof(long) * (size_t)n);
+    long nx = axis_cells(q->cxlo, q->cxhi, n, xi);
+    long ny = axis_cells(q->cylo, q->cyhi, n, yj);
+    if (!q->use_cut) {
+        /* brute force over every included periodic cell (Eq. ndf_eval) */
+        for (long b = 0; b < ny; b++)
+            for (long a = 0; a < nx; a++) test_cell(m, q, acc, xi[a], yj[b]);
+    } else {
+        /* roots: every node of the entry level that overlaps the box */
+        const long mm = n >> q->l0;
+        uint8_t* rx = (uint8_t*)calloc((size_t)mm, 1);
+        uint8_t* ry = (uint8_t*)calloc((size_t)mm, 1);
+        for (long a = 0; a < nx; a++) rx[xi[a] >> q->l0] = 1;
+        for (long b = 0; b < ny; b++) ry[yj[b] >> q->l0] = 1;
+        for (long J = 0; J < mm; J++)
+            for (long I = 0; I < mm; I++)
+                if (rx[I] && ry[J]) descend(m, q, acc, q->l0, I, J);
+        free(rx);
+        free(ry);
+    }
+    free(xi);
+    free(yj);
+}
+
+/*
+ * Evaluate nq queries (6 floats each: x, y, sx, sy, hx, hy).
+ *  D[k]      the P-NDF value (NaN for an invalid query: non-finite input, sigma <= 0,
+ *            |x|, |y| or r above 2^24)
+ *  nhit[k]   number of hit triangles, namb[k] number of triangles within `band` of h
+ *  flags[k]  bit0 = some cut decision is within 1e-5 relative of the threshold
+ * If hoff/aoff (prefix offsets from a previous counting call) are given, the
+ * records are written: hit ids + terms, ambiguous ids + terms + hit flags.
+ * tau > 0 requires clu_n / clu_e (all levels packed).
+ */
+int or_eval(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+            const float* queries, int64_t nq, float tau, float s2r, double band,
+            double* D, int64_t* nhit, int64_t* namb, int32_t* flags,
+            const int64_t* hoff, uint64_t* hid, double* hterm,
+            const int64_t* aoff, uint64_t* aid, double* aterm, uint8_t* ahit)
+{
+    map_t m;
+    m.n = n;
+    m.L = ilog2_exact(n);
+    if (m.L < 1) return 1;
+    m.nrm = nrm;
+    m.eps = (double)eps;
+    m.clu_n = clu_n;
+    m.clu_e = clu_e;
+    if (tau > 0.0f && (!clu_n || !clu_e)) return 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nq; k++) {
+        query_t q;
+        acc_t acc;
+        memset(&acc, 0, sizeof acc);
+        if (setup_query(&m, queries + 6 * k, tau, s2r, band, &q)) {
+            D[k] = NAN;
+            if (nhit) nhit[k] = 0;
+            if (namb) namb[k] = 0;
+            if (flags) flags[k] = 0;
+            continue;
+        }
+        if (hoff && hid) { acc.hid = hid + hoff[k]; acc.hterm = hterm + hoff[k]; }
+        if (aoff && aid) { acc.aid = aid + aoff[k]; acc.aterm = aterm + aoff[k]; acc.ahit = ahit + aoff[k]; }
+        eval_one(&m, &q, &acc);
+        D[k] = acc.D;
+        if (nhit) nhit[k] = acc.nhit;
+        if (namb) namb[k] = acc.namb;
+        if (flags) flags[k] = acc.flags;
+    }
+    return 0;
+}
+
+/* the normal field n(u) of Eq. (interpolation) at texture coordinates u (periodic),
+ * and the clamp-consistent sampling map of Eq. (debias) for clamped triangles:
+ * a point of a clamped triangle goes to the same barycentric point of its
+ * equilateral replacement.  Used by the Monte Carlo histogram pin. */
+int or_sample_normals(int n, const float* nrm, float eps, const double* u, int64_t count,
+                      double* mout)
+{
+    if (ilog2_exact(n) < 0) return 1;
+    for (int64_t k = 0; k < count; k++) {
+        double fx = floor(u[2 * k]), fy = floor(u[2 * k + 1]);
+        double a = u[2 * k] - fx, b = u[2 * k + 1] - fy;
+        long i = (long)fx, j = (long)fy;
+        double nv4[4][2];
+        texel(nrm, n, i, j, nv4[0]);
+        texel(nrm, n, i + 1, j, nv4[1]);
+        texel(nrm, n, i, j + 1, nv4[2]);
+        texel(nrm, n, i + 1, j + 1, nv4[3]);
+        double nv[3][2], w[3];
+        if (a + b < 1.0) {
+            memcpy(nv[0], nv4[0], sizeof nv[0]); memcpy(nv[1], nv4[1], sizeof nv[0]);
+            memcpy(nv[2], nv4[2], sizeof nv[0]);
+            w[0] = 1.0 - a - b; w[1] = a; w[2] = b;
+        } else {
+            memcpy(nv[0], nv4[3], sizeof nv[0]); memcpy(nv[1], nv4[2], sizeof nv[0]);
+            memcpy(nv[2], nv4[1], sizeof nv[0]);
+            w[0] = a + b - 1.0; w[1] = 1.0 - a; w[2] = 1.0 - b;
+        }
+        if (jac(nv[0], nv[1], nv[2]) < (double)eps) {
+            double centre[2] = {0.5 * (nv4[1][0] + nv4[2][0]), 0.5 * (nv4[1][1] + nv4[2][1])};
+            eqtri(centre, eq_rho(0.5 * (double)eps), nv);
+        }
+        mout[2 * k] = w[0] * nv[0][0] + w[1] * nv[1][0] + w[2] * nv[2][0];
+        mout[2 * k + 1] = w[0] * nv[0][1] + w[1] * nv[1][1] + w[2] * nv[2][1];
+    }
+    return 0;
+}

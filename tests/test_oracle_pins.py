@@ -1,0 +1,569 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+(flat map, tilted triangle pair, linear field), an invariant (footprint mass of
+the change of variables), a Monte Carlo normal histogram ("binning"), the
+supplement's printed coefficient matrices, and symmetries of the triangulation.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+EPS = float(np.float32(1e-6))  # eps is a float32 parameter of the method
+RHO = math.sqrt(2.0 * EPS / (3.0 * math.sqrt(3.0)))  # EqTri circumradius, area eps/2
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def qrow(x, y, sx, sy, hx, hy):
+    return np.array([[x, y, sx, sy, hx, hy]], dtype=np.float32)
+
+
+def cell_range(x, s, s2r=3.0):
+    """Included unrolled cell range [lo, hi] of one axis (float32 box, cell granular)."""
+    r = np.float32(s2r) * np.float32(s)
+    lo = np.float32(x) - r
+    hi = np.float32(x) + r
+    return int(math.ceil(float(lo))) - 1, int(math.floor(float(hi)))
+
+
+def gauss(dx, dy, sx, sy):
+    return math.exp(-dx * dx / (2 * sx * sx) - dy * dy / (2 * sy * sy)) / (2 * math.pi * sx * sy)
+
+
+def random_disk_map(n, seed, radius=0.5):
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.uniform(size=(n, n)))
+    t = rng.uniform(0, 2 * np.pi, size=(n, n))
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=-1).astype(np.float32)
+
+
+# ------------------------------------------------------------------ P1 flat map
+def test_flat_map_is_a_delta_at_its_normal(oracle_mod):
+    """A flat map has only zero-area normal triangles: all are clamped to EqTri of
+    Jacobian eps around the map normal (section 'Preventing Jacobian singularity').
+    At the EqTri centroid the barycentrics are (1/3,1/3,1/3), so every cell adds
+    k at (c+1/3, d+1/3) and (c+2/3, d+2/3), divided by eps."""
+    n = 16
+    ns = np.array([0.125, -0.0625], dtype=np.float32)
+    nrm = np.broadcast_to(ns, (n, n, 2)).copy()
+    det, deg = oracle_mod.mesh(nrm)
+    assert (deg == 3).all() and (det == 0).all()
+    x, y, s = np.float32(7.3), np.float32(8.6), np.float32(1.25)
+    res = oracle_mod.evaluate(nrm, qrow(x, y, s, s, ns[0], ns[1]))
+    (clo, chi), (dlo, dhi) = cell_range(x, s), cell_range(y, s)
+    ref = 0.0
+    for c in range(clo, chi + 1):
+        for d in range(dlo, dhi + 1):
+            for o in (1.0 / 3.0, 2.0 / 3.0):
+                ref += gauss(c + o - float(x), d + o - float(y), float(s), float(s))
+    ref /= EPS
+    assert res["nhit"][0] == 2 * (chi - clo + 1) * (dhi - dlo + 1)
+    assert res["D"][0] == pytest.approx(ref, rel=1e-10)
+    # outside the EqTri: nothing
+    out = oracle_mod.evaluate(nrm, qrow(x, y, s, s, ns[0] + np.float32(2 * RHO), ns[1]))
+    assert out["D"][0] == 0.0 and out["nhit"][0] == 0
+
+
+def test_flat_map_mass(oracle_mod):
+    """Integral of D over the EqTri equals the footprint mass of the included cells."""
+    n = 8
+    ns = np.array([0.25, 0.125], dtype=np.float32)
+    nrm = np.broadcast_to(ns, (n, n, 2)).copy()
+    x, y, s = np.float32(3.2), np.float32(4.45), np.float32(0.7)
+    k = 240
+    g = (np.arange(k) + 0.5) / k * 2 - 1
+    mx, my = np.meshgrid(float(ns[0]) + RHO * g, float(ns[1]) + RHO * g)
+    qs = np.zeros((k * k, 6), dtype=np.float32)
+    qs[:, 0], qs[:, 1], qs[:, 2], qs[:, 3] = x, y, s, s
+    qs[:, 4], qs[:, 5] = mx.ravel(), my.ravel()
+    D = oracle_mod.evaluate(nrm, qs)["D"]
+    # the grid is float32-rounded; use the rounded cell size
+    hx = np.diff(np.unique(qs[:, 4].astype(np.float64))).mean()
+    hy = np.diff(np.unique(qs[:, 5].astype(np.float64))).mean()
+    integral = D.sum() * hx * hy
+    assert integral == pytest.approx(footprint_mass(x, y, s, s), rel=2e-2)
+
+
+def footprint_mass(x, y, sx, sy):
+    (clo, chi), (dlo, dhi) = cell_range(x, sx), cell_range(y, sy)
+    fx = 0.5 * (math.erf((chi + 1 - float(x)) / (math.sqrt(2) * float(sx)))
+                - math.erf((clo - float(x)) / (math.sqrt(2) * float(sx))))
+    fy = 0.5 * (math.erf((dhi + 1 - float(y)) / (math.sqrt(2) * float(sy)))
+                - math.erf((dlo - float(y)) / (math.sqrt(2) * float(sy))))
+    return fx * fy
+
+
+# ---------------------------------------------------------- P2a tilted pair
+def test_tilted_triangle_pair(oracle_mod):
+    """Flat map except texels (i0,j0) and (i0+1,j0).  The normal triangle
+    (n*+d1, n*+d2, n*) then appears twice: cell (i0,j0) lower and cell (i0,j0-1)
+    upper; every other triangle is clamped.  D is the sum of k over the two
+    preimages, found here by solving each triangle's affine map u -> n directly
+    (Eq. interpolation), divided by |d1 x d2| (Eq. jacobian)."""
+    n = 16
+    i0, j0 = 6, 7
+    ns = np.array([0.0625, -0.125], dtype=np.float32)
+    d1 = np.array([0.25, 0.0], dtype=np.float32)
+    d2 = np.array([0.125, 0.25], dtype=np.float32)
+    nrm = np.broadcast_to(ns, (n, n, 2)).copy()
+    nrm[j0, i0] = ns + d1
+    nrm[j0, i0 + 1] = ns + d2
+    h = (ns + np.array([0.125, 0.0625], dtype=np.float32)).astype(np.float32)
+    det_t = abs(float(d1[0]) * float(d2[1]) - float(d1[1]) * float(d2[0]))
+
+    def nn(i, j):
+        return nrm[j % n, i % n].astype(np.float64)
+
+    # lower triangle of cell (i0, j0): u = (i0, j0) + s (1,0) + t (0,1)
+    G = np.column_stack([nn(i0 + 1, j0) - nn(i0, j0), nn(i0, j0 + 1) - nn(i0, j0)])
+    st = np.linalg.solve(G, h.astype(np.float64) - nn(i0, j0))
+    assert st.min() >= 0 and st.sum() <= 1
+    uA = np.array([i0, j0]) + st
+    # upper triangle of cell (i0, j0-1): u = (i0+1, j0) + s (-1,0) + t (0,-1)
+    G = np.column_stack([nn(i0, j0) - nn(i0 + 1, j0), nn(i0 + 1, j0 - 1) - nn(i0 + 1, j0)])
+    st = np.linalg.solve(G, h.astype(np.float64) - nn(i0 + 1, j0))
+    assert st.min() >= 0 and st.sum() <= 1
+    uB = np.array([i0 + 1, j0]) - st
+    x, y, s = np.float32(7.1), np.float32(6.8), np.float32(1.5)
+    ref = (gauss(uA[0] - float(x), uA[1] - float(y), float(s), float(s)) +
+           gauss(uB[0] - float(x), uB[1] - float(y), float(s), float(s))) / det_t
+    res = oracle_mod.evaluate(nrm, qrow(x, y, s, s, h[0], h[1]), records=True)
+    assert res["nhit"][0] == 2
+    assert res["D"][0] == pytest.approx(ref, rel=1e-12)
+    level, I, J, half = oracle_mod.decode_id(res["hit_id"])
+    got = sorted(zip(I.tolist(), J.tolist(), half.tolist()))
+    assert got == sorted([(i0, j0, 0), (i0, j0 - 1, 1)])
+    assert (level == 0).all()
+
+
+# ----------------------------------------------------------- P2b linear field
+def linear_map(n=64):
+    G = np.array([[1 / 128, 1 / 512], [-1 / 256, 1 / 128]])
+    nc = np.array([1 / 16, -1 / 32])
+    uc = np.array([32.0, 32.0])
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    u = np.stack([ii, jj], axis=-1).astype(np.float64) - uc
+    nrm = (nc + u @ G.T).astype(np.float32)
+    assert np.array_equal(nrm.astype(np.float64), nc + u @ G.T)  # exactly representable
+    return nrm, G, nc, uc
+
+
+def test_linear_field_closed_form(oracle_mod):
+    """n(u) = n_c + G (u - u_c): every triangle has Jacobian |det G| and h has the
+    single preimage u_c + G^-1 (h - n_c) (footprint kept off the wrap seam)."""
+    nrm, G, nc, uc = linear_map()
+    det, deg = oracle_mod.mesh(nrm)
+    dG = abs(np.linalg.det(G))
+    assert np.allclose(det[:63, :63], dG, rtol=0, atol=1e-18)
+    assert not deg[:63, :63].any()
+    rng = np.random.default_rng(7)
+    qs = []
+    refs = []
+    for _ in range(40):
+        x, y = np.float32(rng.uniform(26, 38)), np.float32(rng.uniform(26, 38))
+        s = np.float32(rng.uniform(0.6, 4.0))
+        upre = np.array([x, y], dtype=np.float64) + rng.uniform(-2 * s, 2 * s, 2)
+        h = (nc + G @ (upre - uc)).astype(np.float32)
+        u = uc + np.linalg.solve(G, h.astype(np.float64) - nc)
+        (clo, chi), (dlo, dhi) = cell_range(x, s), cell_range(y, s)
+        inside = clo <= u[0] <= chi + 1 and dlo <= u[1] <= dhi + 1
+        refs.append(gauss(u[0] - float(x), u[1] - float(y), float(s), float(s)) / dG if inside else 0.0)
+        qs.append([x, y, s, s, h[0], h[1]])
+    qs = np.array(qs, dtype=np.float32)
+    res = oracle_mod.evaluate(nrm, qs)
+    ok = res["namb"] == 0
+    assert ok.sum() >= 30
+    np.testing.assert_allclose(res["D"][ok], np.array(refs)[ok], rtol=1e-9, atol=0)
+
+
+def test_linear_field_cluster_exact(oracle_mod):
+    """A linear field is reproduced exactly by every cluster away from the seam:
+    N* are the field's values at the node corners and e^l = 0; the cut result then
+    equals the exact result."""
+    nrm, G, nc, uc = linear_map()
+    n = nrm.shape[0]
+    for level in range(1, 6):
+        m = n >> level
+        s = 1 << level
+        ids = [J * m + I for J in range(m - 1) for I in range(m - 1)]  # skip seam nodes
+        ns, e = oracle_mod.cluster_level(nrm, level, ids=ids)
+        scale = 1.0 / float(np.abs(np.linalg.det(G)))  # weight 1/det
+        assert np.abs(e).max() <= 1e-18 * scale * s * s
+        for k, nid in enumerate(ids):
+            I, J = nid % m, nid // m
+            for c, (di, dj) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+                want = nc + G @ (np.array([(I + di) * s, (J + dj) * s]) - uc)
+                assert np.allclose(ns[k, c], want, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(8)
+    qs = []
+    for _ in range(32):
+        x, y = np.float32(rng.uniform(28, 36)), np.float32(rng.uniform(28, 36))
+        s = np.float32(rng.uniform(1.0, 3.5))
+        upre = np.array([x, y], dtype=np.float64) + rng.uniform(-1.5 * s, 1.5 * s, 2)
+        h = (nc + G @ (upre - uc)).astype(np.float32)
+        qs.append([x, y, s, s, h[0], h[1]])
+    qs = np.array(qs, dtype=np.float32)
+    exact = oracle_mod.evaluate(nrm, qs)
+    cut = oracle_mod.evaluate(nrm, qs, tau=1e-3)
+    ok = (exact["namb"] == 0) & (cut["namb"] == 0)
+    assert ok.sum() >= 24
+    assert (cut["nhit"][ok] >= 1).all()
+    np.testing.assert_allclose(cut["D"][ok], exact["D"][ok], rtol=1e-6)
+
+
+# ------------------------------------------------------------ P3 mass invariant
+@pytest.mark.parametrize("n,x,y,s", [(8, 3.3, 4.6, 0.5), (4, 1.7, 2.2, 3.0)])
+def test_mass_invariant(oracle_mod, n, x, y, s):
+    """Change of variables (Eq. gndf): the integral of D over the normal plane is the
+    footprint kernel's mass over the included cell images.  The second case has a
+    footprint several periods wide (periodic images)."""
+    nrm = random_disk_map(n, 11)
+    det, deg = oracle_mod.mesh(nrm)
+    assert not deg.any()
+    x, y, s = np.float32(x), np.float32(y), np.float32(s)
+    k = 1400
+    g = ((np.arange(k) + 0.5) / k * 1.2 - 0.6).astype(np.float32)
+    mx, my = np.meshgrid(g, g)
+    qs = np.zeros((k * k, 6), dtype=np.float32)
+    qs[:, 0], qs[:, 1], qs[:, 2], qs[:, 3] = x, y, s, s
+    qs[:, 4], qs[:, 5] = mx.ravel(), my.ravel()
+    D = oracle_mod.evaluate(nrm, qs)["D"]
+    integral = D.sum() * (1.2 / k) ** 2
+    assert integral == pytest.approx(footprint_mass(x, y, s, s), rel=1e-2)
+
+
+# ------------------------------------------------- P4 Monte Carlo normal histogram
+def interp_normals(nrm, u):
+    """Eq. (interpolation), written out independently: lower u+v<1 uses (n0,n1,n2),
+    otherwise (n3,n2,n1); texels wrap around the map."""
+    n = nrm.shape[0]
+    i = np.floor(u[:, 0]).astype(np.int64)
+    j = np.floor(u[:, 1]).astype(np.int64)
+    a = (u[:, 0] - i)[:, None]
+    b = (u[:, 1] - j)[:, None]
+    f = nrm.astype(np.float64)
+    n0 = f[j % n, i % n]
+    n1 = f[j % n, (i + 1) % n]
+    n2 = f[(j + 1) % n, i % n]
+    n3 = f[(j + 1) % n, (i + 1) % n]
+    lower = n0 * (1 - a - b) + n1 * a + n2 * b
+    upper = n3 * (a + b - 1) + n2 * (1 - a) + n1 * (1 - b)
+    return np.where((a + b) < 1, lower, upper)
+
+
+def test_binning_histogram_matches_ndf(oracle_mod):
+    """Fig. ndf_comparison: the analytic evaluation matches binning.  Sample u from
+    the footprint kernel restricted to the included cells, histogram m = n(u), and
+    compare each bin's frequency with the integral of D over the bin / mass."""
+    from scipy.stats import truncnorm
+    n = 8
+    nrm = random_disk_map(n, 5, radius=0.45)
+    x, y, s = np.float32(4.1), np.float32(3.7), np.float32(0.9)
+    (clo, chi), (dlo, dhi) = cell_range(x, s), cell_range(y, s)
+    rng = np.random.default_rng(3)
+    ns = 2_000_000
+    ux = truncnorm.rvs((clo - x) / s, (chi + 1 - x) / s, loc=x, scale=s, size=ns, random_state=rng)
+    uy = truncnorm.rvs((dlo - y) / s, (dhi + 1 - y) / s, loc=y, scale=s, size=ns, random_state=rng)
+    m = interp_normals(nrm, np.stack([ux, uy], axis=1))
+    nb = 12
+    edges = np.linspace(-0.48, 0.48, nb + 1)
+    hist, _, _ = np.histogram2d(m[:, 0], m[:, 1], bins=[edges, edges])
+    freq = hist / ns
+    sub = 24
+    w = edges[1] - edges[0]
+    cx = (edges[:-1, None] + (np.arange(sub)[None, :] + 0.5) * w / sub).ravel()
+    mx, my = np.meshgrid(cx, cx, indexing="ij")
+    qs = np.zeros((mx.size, 6), dtype=np.float32)
+    qs[:, 0], qs[:, 1], qs[:, 2], qs[:, 3] = x, y, s, s
+    qs[:, 4], qs[:, 5] = mx.ravel(), my.ravel()
+    D = oracle_mod.evaluate(nrm, qs)["D"].reshape(nb * sub, nb * sub)
+    binint = D.reshape(nb, sub, nb, sub).sum(axis=(1, 3)) * (w / sub) ** 2
+    mass = footprint_mass(x, y, s, s)
+    p = binint / mass
+    assert abs(p.sum() - freq.sum()) < 0.02
+    big = p > 2e-3
+    assert big.sum() >= 20
+    rel = np.abs(freq[big] - p[big]) / p[big]
+    assert np.median(rel) < 0.03
+    assert rel.max() < 0.15
+
+
+# -------------------------------------------- P6 printed coefficient matrices
+def test_supplement_coefficient_matrices(oracle_mod):
+    """The per-fine-triangle gradient matrices of the cluster objective equal the
+    supplement's printed closed forms for a = 1, 2, 4, 8 and every fine cell."""
+    import sympy
+    gold = json.load(open(os.path.join(HERE, "golden", "cluster_coefficients.json")))
+    a_, i_, j_ = sympy.symbols("a i j")
+    n_sym = sympy.symbols("n0 n1 n2 n3")
+    loc = {"a": a_, "i": i_, "j": j_, "Rational": sympy.Rational,
+           **{f"n{k}": n_sym[k] for k in range(4)}}
+    cases = {}
+    for name, c in gold["cases"].items():
+        A = [[sympy.lambdify((a_, i_, j_), sympy.sympify(e, locals=loc)) for e in row]
+             for row in c["A"]]
+        B = [sympy.lambdify((a_, i_, j_) + n_sym, sympy.sympify(e, locals=loc)) for e in c["B"]]
+        cases[name] = (A, B)
+    rng = np.random.default_rng(1)
+    seen = set()
+    for a in (1, 2, 4, 8):
+        for i in range(a):
+            for j in range(a):
+                for half in (0, 1):
+                    nv = rng.uniform(-0.5, 0.5, (4, 2))
+                    A, B, C, ch = oracle_mod.fine_contrib(a, i, j, half, nv)
+                    name = ("plus" if half == 0 else "minus") + "_in_" + ("plus" if ch == 0 else "minus")
+                    seen.add(name)
+                    # the case condition: the fine triangle lies in the cluster half
+                    if half == 0:
+                        assert ch == (0 if i + j <= a - 1 else 1)
+                    else:
+                        assert ch == (0 if i + j <= a - 2 else 1)
+                    PA, PB = cases[name]
+                    want_A = np.array([[float(f(a, i, j)) for f in row] for row in PA])
+                    np.testing.assert_allclose(A, want_A, rtol=0, atol=1e-13)
+                    for comp in range(2):
+                        want_B = np.array([float(f(a, i, j, *nv[:, comp])) for f in PB])
+                        np.testing.assert_allclose(B[:, comp], want_B, rtol=0, atol=1e-13)
+                    # C = int |n|^2 over a linear triangle (textbook closed form)
+                    tri = [0, 1, 2] if half == 0 else [3, 2, 1]
+                    f = nv[tri]
+                    want_C = (0.5 / 6.0) * sum(f[p] @ f[q] for p in range(3) for q in range(p, 3))
+                    assert C == pytest.approx(want_C, rel=1e-12)
+    assert seen == {"plus_in_plus", "plus_in_minus", "minus_in_plus", "minus_in_minus"}
+
+
+# ------------------------------------------------ cluster optimality (numeric)
+def objective_numeric(nrm, level, I, J, N, eps=EPS, K=24):
+    """Eq. (normal_optimization) for cluster normals N (4,2) by a K x K sub-triangle
+    centroid rule on every fine triangle (independent of the oracle's rule)."""
+    n = nrm.shape[0]
+    s = 1 << level
+    f = nrm.astype(np.float64)
+    # sub-triangle centroids of the reference triangle (0,0),(1,0),(0,1)
+    pts = []
+    for p in range(K):
+        for q in range(K - p):
+            pts.append(((p + 1 / 3) / K, (q + 1 / 3) / K))
+            if p + q < K - 1:
+                pts.append(((p + 2 / 3) / K, (q + 2 / 3) / K))
+    pts = np.array(pts)
+    wq = 0.5 / len(pts)
+    total = 0.0
+    for lj in range(s):
+        for li in range(s):
+            gi, gj = I * s + li, J * s + lj
+            c = [f[gj % n, gi % n], f[gj % n, (gi + 1) % n], f[(gj + 1) % n, gi % n],
+                 f[(gj + 1) % n, (gi + 1) % n]]
+            for half in (0, 1):
+                if half == 0:
+                    ua, nb = np.array([li, lj]), (c[0], c[1], c[2])
+                    uvp = ua + pts
+                else:
+                    ua, nb = np.array([li + 1, lj + 1]), (c[3], c[2], c[1])
+                    uvp = ua - pts
+                nf = nb[0] * (1 - pts[:, :1] - pts[:, 1:]) + nb[1] * pts[:, :1] + nb[2] * pts[:, 1:]
+                d = abs((nb[2][0] - nb[0][0]) * (nb[1][1] - nb[0][1]) -
+                        (nb[2][1] - nb[0][1]) * (nb[1][0] - nb[0][0]))
+                w = 1.0 / max(d, eps)
+                U, V = uvp[:, 0] / s, uvp[:, 1] / s
+                low = (U + V) <= 1
+                lam = np.where(low[:, None], np.stack([1 - U - V, U, V, 0 * U], 1),
+                               np.stack([0 * U, 1 - V, 1 - U, U + V - 1], 1))
+                nl = lam @ N
+                total += w * wq * np.sum((nl - nf) ** 2)
+    return total
+
+
+def test_cluster_fit_is_the_minimiser(oracle_mod):
+    nrm = random_disk_map(8, 21, radius=0.4)
+    for level, (I, J) in ((1, (1, 2)), (2, (1, 0)), (3, (0, 0))):
+        m = 8 >> level
+        ns, e = oracle_mod.cluster_level(nrm, level, ids=[J * m + I])
+        N = ns[0]
+        E0 = objective_numeric(nrm, level, I, J, N)
+        assert E0 == pytest.approx(e[0], rel=2e-3)
+        rng = np.random.default_rng(level)
+        for _ in range(6):
+            v = rng.normal(size=(4, 2))
+            v *= 0.02 / np.abs(v).max()
+            assert objective_numeric(nrm, level, I, J, N + v) > E0
+
+
+# ------------------------------------------------------------- invariants
+def test_transpose_invariance(oracle_mod):
+    """Swapping u and v (and the normal components) maps the anti-diagonal
+    triangulation onto itself, so D is unchanged."""
+    nrm = random_disk_map(16, 4)
+    nT = np.ascontiguousarray(np.transpose(nrm, (1, 0, 2))[:, :, ::-1])
+    rng = np.random.default_rng(2)
+    qs = np.zeros((300, 6), dtype=np.float32)
+    qs[:, 0:2] = rng.uniform(0, 16, (300, 2))
+    qs[:, 2] = rng.uniform(0.4, 6, 300)
+    qs[:, 3] = rng.uniform(0.4, 6, 300)
+    qs[:, 4:6] = rng.uniform(-0.45, 0.45, (300, 2))
+    qT = qs[:, [1, 0, 3, 2, 5, 4]].copy()
+    a = oracle_mod.evaluate(nrm, qs)
+    b = oracle_mod.evaluate(nT, qT)
+    ok = (a["namb"] == 0) & (b["namb"] == 0)
+    np.testing.assert_array_equal(a["nhit"][ok], b["nhit"][ok])
+    np.testing.assert_allclose(a["D"][ok], b["D"][ok], rtol=1e-12, atol=0)
+    assert (a["D"] > 0).sum() > 100
+
+
+def test_periodicity(oracle_mod):
+    """Moving the footprint by one period (exactly representable shift) leaves D unchanged."""
+    nrm = random_disk_map(16, 9)
+    rng = np.random.default_rng(4)
+    qs = np.zeros((200, 6), dtype=np.float32)
+    qs[:, 0:2] = np.round(rng.uniform(0, 16, (200, 2)) * 64) / 64
+    qs[:, 2:4] = np.round(rng.uniform(0.5, 20, (200, 2)) * 64) / 64
+    qs[:, 4:6] = rng.uniform(-0.45, 0.45, (200, 2))
+    q2 = qs.copy()
+    q2[:, 0] += 16
+    q2[:, 1] -= 32
+    a = oracle_mod.evaluate(nrm, qs)
+    b = oracle_mod.evaluate(nrm, q2)
+    np.testing.assert_array_equal(a["nhit"], b["nhit"])
+    np.testing.assert_allclose(a["D"], b["D"], rtol=1e-12, atol=0)
+
+
+def test_cut_path_without_cuts_equals_brute_force(oracle_mod):
+    """With a vanishing tau no node is cut, so the top-down descent from the entry
+    level (roots, periodic overlap tests) must find exactly the brute-force set."""
+    nrm = random_disk_map(32, 13)
+    rng = np.random.default_rng(5)
+    qs = np.zeros((400, 6), dtype=np.float32)
+    qs[:, 0:2] = rng.uniform(-40, 70, (400, 2))
+    qs[:, 2:4] = np.exp(rng.uniform(np.log(0.2), np.log(30), (400, 2)))
+    qs[:, 4:6] = rng.uniform(-0.45, 0.45, (400, 2))
+    a = oracle_mod.evaluate(nrm, qs, records=True)
+    b = oracle_mod.evaluate(nrm, qs, tau=1e-30, records=True)
+    np.testing.assert_array_equal(a["nhit"], b["nhit"])
+    np.testing.assert_allclose(a["D"], b["D"], rtol=1e-12, atol=0)
+    for k in range(0, 400, 7):
+        sa = sorted(a["hit_id"][a["hit_off"][k]:a["hit_off"][k + 1]].tolist())
+        sb = sorted(b["hit_id"][b["hit_off"][k]:b["hit_off"][k + 1]].tolist())
+        assert sa == sb
+
+
+def test_shared_edge_is_ambiguous(oracle_mod):
+    """h exactly on the edge shared by a cell's two triangles is flagged for both."""
+    nrm = random_disk_map(8, 17)
+    f = nrm.astype(np.float64)
+    n1, n2 = f[3, 4], f[4, 3]  # cell (3,3): u1 = (4,3), u2 = (3,4)
+    h = (0.5 * (n1 + n2)).astype(np.float32)
+    res = oracle_mod.evaluate(nrm, qrow(3.5, 3.5, 0.2, 0.2, h[0], h[1]), records=True)
+    level, I, J, half = oracle_mod.decode_id(res["amb_id"])
+    pairs = set(zip(I.tolist(), J.tolist(), half.tolist()))
+    assert {(3, 3, 0), (3, 3, 1)} <= pairs
+
+
+def test_invalid_queries_give_nan(oracle_mod):
+    nrm = random_disk_map(8, 1)
+    bad = np.array([[1, 1, 0, 1, 0, 0], [1, 1, 1, -1, 0, 0], [np.nan, 1, 1, 1, 0, 0],
+                    [1, 1, 1, 1, np.inf, 0], [3e7, 1, 1, 1, 0, 0]], dtype=np.float32)
+    res = oracle_mod.evaluate(nrm, bad)
+    assert np.isnan(res["D"]).all()
+    ok = oracle_mod.evaluate(nrm, np.array([[1, 1, 1, 1, 2.0, 0]], dtype=np.float32))
+    assert ok["D"][0] == 0.0
+
+
+def test_clamped_triangles_centre_on_the_cell_centre_normal(oracle_mod):
+    """Eq. (debias): a clamped triangle is replaced around n(floor(u)+1/2), the
+    interpolated normal at the cell centre, which is (n1+n2)/2.  On a checkerboard
+    map of two normals A, B every triangle is degenerate; cells with i+j even have
+    centre normal B, odd cells A.  At h = B only the even cells contribute, each
+    with its two triangles at barycentrics (1/3,1/3,1/3)."""
+    n = 8
+    A = np.array([0.125, 0.0625], dtype=np.float32)
+    B = np.array([-0.25, 0.125], dtype=np.float32)
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    nrm = np.where(((ii + jj) % 2 == 0)[..., None], A, B).astype(np.float32)
+    det, deg = oracle_mod.mesh(nrm)
+    assert (deg == 3).all()
+    x, y, s = np.float32(3.4), np.float32(4.3), np.float32(0.8)
+    res = oracle_mod.evaluate(nrm, qrow(x, y, s, s, B[0], B[1]))
+    (clo, chi), (dlo, dhi) = cell_range(x, s), cell_range(y, s)
+    ref = 0.0
+    cells = 0
+    for c in range(clo, chi + 1):
+        for d in range(dlo, dhi + 1):
+            if (c + d) % 2 == 0:
+                cells += 1
+                for o in (1.0 / 3.0, 2.0 / 3.0):
+                    ref += gauss(c + o - float(x), d + o - float(y), float(s), float(s))
+    assert res["nhit"][0] == 2 * cells
+    assert res["D"][0] == pytest.approx(ref / EPS, rel=1e-10)
+
+
+def test_entry_level_and_roots(oracle_mod):
+    """Supplement, 'Entry level': traversal starts at l = ceil(log2 max(r_x, r_y))
+    (capped at the root).  With a huge tau every root node satisfies the cut, so
+    every hit is a cluster triangle of exactly that level, and the roots are the
+    entry-level nodes whose periodic images meet the support box."""
+    n = 64
+    nrm = random_disk_map(n, 31, radius=0.3)
+    clusters = oracle_mod.cluster_all(nrm)
+    rng = np.random.default_rng(12)
+    qs = np.zeros((300, 6), dtype=np.float32)
+    qs[:, 0:2] = rng.uniform(0, n, (300, 2))
+    qs[:, 2] = np.exp(rng.uniform(np.log(0.2), np.log(40.0), 300))
+    qs[:, 3] = qs[:, 2] * np.exp(rng.uniform(-0.5, 0.5, 300)).astype(np.float32)
+    qs[:, 4:6] = rng.uniform(-0.1, 0.1, (300, 2))
+    res = oracle_mod.evaluate(nrm, qs, tau=1e30, clusters=clusters, records=True)
+    L = 6
+    for k in range(300):
+        r = max(float(np.float32(3) * qs[k, 2]), float(np.float32(3) * qs[k, 3]))
+        l0 = min(L, max(0, math.ceil(math.log2(r))))
+        lev, I, J, half = oracle_mod.decode_id(res["hit_id"][res["hit_off"][k]:res["hit_off"][k + 1]])
+        assert (lev == l0).all(), (k, r, l0, set(lev.tolist()))
+        if l0 >= 1:
+            s = 1 << l0
+            (clo, chi), (dlo, dhi) = cell_range(qs[k, 0], qs[k, 2]), cell_range(qs[k, 1], qs[k, 3])
+            for a, b in zip(I.tolist(), J.tolist()):
+                # some periodic image of the node's cells meets the cell range
+                assert any(clo <= a * s + t + p * n <= chi for t in range(s) for p in range(-4, 5))
+                assert any(dlo <= b * s + t + p * n <= dhi for t in range(s) for p in range(-4, 5))
+    assert (res["nhit"] > 0).sum() > 150
+
+
+def test_cut_threshold_rule(oracle_mod):
+    """Section 'Acceleration by mesh clustering': a node is used as a cluster when
+    e^l <= r_x r_y tau.  With r = 1.5 the entry level is 1; tau is set so that the
+    threshold falls in a wide gap between the level-1 residuals (recomputed here by
+    independent quadrature at the oracle's optimum).  Scanning h over the normal
+    range shows which nodes answered with cluster triangles."""
+    n = 8
+    nrm = random_disk_map(n, 41, radius=0.35)
+    clusters = oracle_mod.cluster_all(nrm)
+    ns, e = clusters["levels"][1]
+    m = n // 2
+    e_num = np.array([objective_numeric(nrm, 1, k % m, k // m, ns[k], K=24) for k in range(m * m)])
+    np.testing.assert_allclose(e_num, e, rtol=5e-3)
+    x = y = np.float32(4.0)
+    s = np.float32(0.5)                       # r = 1.5: entry level 1, cells 2..5
+    roots = [(I, J) for J in (1, 2) for I in (1, 2)]
+    ev = sorted(e_num[J * m + I] for I, J in roots)
+    gaps = [(ev[k + 1] / ev[k], k) for k in range(3)]
+    ratio, k = max(gaps)
+    assert ratio > 1.3
+    t = np.sqrt(ev[k] * ev[k + 1])            # geometric middle of the widest gap
+    r = float(np.float32(3) * s)
+    tau = np.float32(t / (r * r))
+    g = np.linspace(-0.34, 0.34, 90).astype(np.float32)
+    hx, hy = np.meshgrid(g, g)
+    qs = np.zeros((hx.size, 6), dtype=np.float32)
+    qs[:, 0], qs[:, 1], qs[:, 2], qs[:, 3] = x, y, s, s
+    qs[:, 4], qs[:, 5] = hx.ravel(), hy.ravel()
+    res = oracle_mod.evaluate(nrm, qs, tau=float(tau), clusters=clusters, records=True)
+    lev, I, J, half = oracle_mod.decode_id(res["hit_id"])
+    cut_nodes = set(zip(I[lev == 1].tolist(), J[lev == 1].tolist()))
+    cell_nodes = set(zip((I[lev == 0] // 2).tolist(), (J[lev == 0] // 2).tolist()))
+    for (a, b) in roots:
+        want_cut = e_num[b * m + a] <= t
+        assert ((a, b) in cut_nodes) == want_cut
+        assert ((a, b) in cell_nodes) == (not want_cut)
