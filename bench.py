@@ -1,0 +1,223 @@
+"""Benchmark: P-NDF queries/s on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload powerlaw2048]
+                    [--algo plain|brute] [--no-cpu-baseline] [--no-octaves]
+
+A step is one pndf_eval_batch over the whole query batch (queries and the mesh /
+hierarchy already resident in HBM).  Prints one JSON line.
+
+Roofline: the dominant (and only) kernel of a step is the evaluation kernel.  Its
+algorithmic bytes per launch are the per-query work units counted by an
+instrumented launch (nodes, leaf cells, clusters, hits) times the bytes each unit
+must read, plus the query record and the output:
+    B = 28 + (16 + 4 [tau > 0]) nodes + 9 cells + 41 clusters + 4 hits
+and its duration is measured with HIP events on the stream the kernel runs on.
+HBM traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded under
+profiles/ (null when the kernel source changed since they were taken).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "P-NDF queries/sec at 1 MI355X vs footprint size; p99 tile latency (serving)"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_plain_powerlaw2048.json")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2505_08985_amd", "csrc", f)
+              for f in ("eval.hip", "pndf_internal.h")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(counts, tau):
+    c = counts.astype(np.float64)
+    per_node = 16.0 + (4.0 if tau > 0 else 0.0)
+    return float(np.sum(28.0 + per_node * c[:, 0] + 9.0 * c[:, 1] + 41.0 * c[:, 2] + 4.0 * c[:, 3]))
+
+
+def load_traffic(workload, algo):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload or t.get("algo") != algo:
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(nrm, q, tau, budget_s=15.0):
+    """The FP64 oracle, as it stands, on a bounded prefix of the same (randomly
+    ordered) query stream, all host threads."""
+    import oracle
+    oracle.load()
+    threads = oracle.num_threads()
+    k = 256
+    t0 = time.perf_counter()
+    oracle.evaluate(nrm, q[:k], tau=tau)
+    dt = time.perf_counter() - t0
+    k2 = int(min(len(q), max(k, budget_s / max(dt, 1e-6) * k)))
+    t0 = time.perf_counter()
+    oracle.evaluate(nrm, q[:k2], tau=tau)
+    dt2 = time.perf_counter() - t0
+    return {"value": k2 / dt2, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d queries of the same seeded stream (%.1f s, FP64 brute force over "
+                      "every included cell)" % (k2, dt2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="powerlaw2048")
+    ap.add_argument("--algo", default="plain")
+    ap.add_argument("--queries", type=int, default=0, help="override the batch size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-octaves", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (3 times), to scale the "
+                         "FETCH_SIZE / WRITE_SIZE counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(queries are independent; see the sharding note in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}), flush=True)
+        return
+    import paper_2505_08985_amd as P
+    import workloads
+
+    cfg = workloads.CONFIGS[args.workload]
+    mc, qc, tau = cfg["map"], cfg["queries"], float(cfg["tau"])
+    n = mc["n"]
+    t0 = time.perf_counter()
+    nrm = workloads.make_map(**mc)
+    count = args.queries or qc["count"]
+    q = workloads.uniform_queries(n, count, qc["seed"], qc["sigma"], qc["radius"])
+    gen_s = time.perf_counter() - t0
+    print("[bench] workload %s: map %d^2, %d queries (generated in %.1f s)" % (args.workload, n, count, gen_s),
+          file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    dev_map = torch.from_numpy(nrm).cuda()
+    t0 = time.perf_counter()
+    mesh = P.build_mesh(dev_map)
+    hier = P.build_hierarchy(mesh, cluster=True)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    del dev_map
+    tq = torch.from_numpy(q).cuda()
+    out = torch.empty(count, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    print("[bench] timed %d steps: %.3f ms/step (events %.3f ms)" % (args.steps, 1e3 * wall / args.steps,
+                                                                     kernel_ms), file=sys.stderr, flush=True)
+    value = count * args.steps / wall
+    d = out.cpu().numpy()
+    assert np.isfinite(d).all() and (d >= 0).all()
+
+    # instrumented launch: work units for the algorithmic byte count
+    _, counts = P.eval_counts(hier, tq, tau=tau, algo=args.algo)
+    counts = counts.cpu().numpy()
+    abytes = algorithmic_bytes(counts, tau)
+    achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, args.algo)
+    work = {"nodes_per_query": float(counts[:, 0].mean()), "cells_per_query": float(counts[:, 1].mean()),
+            "clusters_per_query": float(counts[:, 2].mean()), "hits_per_query": float(counts[:, 3].mean()),
+            "algorithmic_bytes_per_launch": abytes}
+
+    octaves = None
+    if not args.no_octaves and isinstance(qc["sigma"], tuple):
+        octaves = {}
+        lo, hi = qc["sigma"]
+        o = 0
+        while lo * 2 ** o < hi:
+            a, b = lo * 2 ** o, min(hi, lo * 2 ** (o + 1))
+            sel = np.where((q[:, 2] >= a) & (q[:, 2] < b))[0]
+            if len(sel):
+                sq = tq[torch.from_numpy(sel).cuda()]
+                so = torch.empty(len(sel), dtype=torch.float32, device="cuda")
+                P.eval_batch(hier, sq, tau=tau, algo=args.algo, out=so)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                reps = 3
+                for _ in range(reps):
+                    P.eval_batch(hier, sq, tau=tau, algo=args.algo, out=so)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                octaves["sigma %g-%g" % (a, b)] = len(sel) * reps / (e0.elapsed_time(e1) * 1e-3)
+            o += 1
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(nrm, q, tau)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "map": "%s %dx%d" % (mc["kind"], n, n), "queries": count,
+                   "sigma": list(qc["sigma"]) if isinstance(qc["sigma"], tuple) else qc["sigma"],
+                   "h_radius": qc["radius"], "tau": tau, "algo": args.algo, "sigma_to_r": 3.0},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "cpu_baseline": cpu,
+        "kernel_ms": kernel_ms,
+        "build_s": build_s,
+        "work": work,
+        "queries_per_s_by_sigma_octave": octaves,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

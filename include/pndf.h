@@ -1,0 +1,203 @@
+/*
+ * pndf.h - C ABI of the MI355X (gfx950) library for batched evaluation of the
+ * manifold-based patch normal distribution function (P-NDF) of
+ * "Position-Normal Manifold for Efficient Glint Rendering on High-Resolution
+ * Normal Maps" (arXiv 2505.08985).
+ *
+ * The problem, in the paper's notation (section "Preliminaries", Eq. gndf):
+ *   D(m, x) = integral of k_r(u - x) delta(n(u) - m) du
+ *           = sum over preimages u_i of m of k_r(u_i - x) / |det J(u_i)|,
+ * where n(u) is the normal map made continuous by two triangles per texel cell
+ * (Eq. interpolation), det J is twice the normal-space triangle area
+ * (Eq. jacobian), and the sum is found by point-in-normal-triangle tests with
+ * barycentric recovery of u (Eq. ndf_eval), accelerated by a min-max hierarchy and
+ * a least-squares cluster hierarchy (section "Acceleration by mesh clustering").
+ *
+ * Conventions used by every entry point
+ *   - Texture coordinates are unnormalised texel units; texel (i, j) sits at (i, j)
+ *     (Table notation).  The map is periodic (a torus): cell (N-1, j) connects to
+ *     texel column 0, and footprints wider than the map sum every periodic image.
+ *   - Normals and query normals are the xy components of unit vectors on the
+ *     projected hemisphere (section "Preliminaries").
+ *   - The footprint kernel is the normalised axis-aligned Gaussian of standard
+ *     deviations (sx, sy); its support half-width is r = sigma_to_r * sigma (3 by
+ *     default: the "(6 sigma)^2 footprint" of the ablation section), truncated at
+ *     texel-cell granularity: every triangle of every periodic cell image whose
+ *     closed unit square meets [x - r, x + r] (r, x - r, x + r rounded to float32)
+ *     contributes, with the untruncated Gaussian.
+ *   - Triangles with Jacobian below eps (evaluated in FP64 from the float32 normals,
+ *     strict <) are replaced by an equilateral triangle of area eps/2 centred at the
+ *     cell-centre normal n(floor(u) + 1/2) = (n1 + n2)/2 (section "Preventing
+ *     Jacobian singularity", Eq. debias); its vertices sit at 90, 210, 330 degrees,
+ *     assigned to the triangle's (a, b, c).
+ *   - Device pointers are HIP device (HBM) addresses; `stream` is a hipStream_t
+ *     (NULL = the default stream).  Every call returns a pndf_status and never
+ *     aborts; pndf_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef PNDF_H
+#define PNDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pndf_mesh pndf_mesh; /* opaque, immutable after build */
+typedef struct pndf_hier pndf_hier; /* opaque, immutable after build; holds a reference to its mesh */
+
+typedef enum pndf_status {
+    PNDF_OK = 0,
+    PNDF_EINVAL = 1,      /* invalid argument (null pointer, bad size, out-of-range option or map value) */
+    PNDF_ENOMEM = 2,      /* device or host allocation failed */
+    PNDF_EDEVICE = 3,     /* a HIP runtime call failed (including an earlier asynchronous fault) */
+    PNDF_EOVERFLOW = 4,   /* a caller-provided buffer is too small; the required size is reported */
+    PNDF_EUNSUPPORTED = 5,/* valid request that this library does not implement (e.g. N > 8192) */
+    PNDF_EAGAIN = 6       /* serving: admission refused for now (memory or slots); retry later */
+} pndf_status;
+
+/* One query: footprint centre (x, y) in texel units, Gaussian standard deviations
+ * (sx, sy) in texels, query normal (hx, hy) on the projected hemisphere.  24 bytes,
+ * arrays of queries are tightly packed.  A query with a non-finite field, sx <= 0,
+ * sy <= 0, |x| or |y| above 2^24, or r above 2^24 evaluates to NaN (not a batch
+ * error).  A query normal outside every normal triangle evaluates to 0. */
+typedef struct pndf_query {
+    float x, y, sx, sy, hx, hy;
+} pndf_query;
+
+enum { PNDF_KERNEL_GAUSSIAN = 0 };
+
+/* Evaluation algorithm.  All give the same result (the set of triangles is fixed
+ * by the definition, not by the algorithm); they differ in speed. */
+enum {
+    PNDF_ALGO_AUTO = 0,       /* plain hierarchical traversal */
+    PNDF_ALGO_BRUTE = 1,      /* every triangle of every included cell, no hierarchy (tau must be 0) */
+    PNDF_ALGO_PLAIN = 2,      /* one wavefront per query, min-max (+ cluster cut) traversal */
+    PNDF_ALGO_PERSISTENT = 3  /* persistent work-stealing traversal (see pndf_eval_persistent) */
+};
+
+typedef struct pndf_eval_opts {
+    int32_t kernel;     /* PNDF_KERNEL_GAUSSIAN (the only kernel; anything else -> PNDF_EUNSUPPORTED) */
+    float tau;          /* cluster cut threshold: a node of level l >= 1 at or below the entry level is
+                         * used as two cluster triangles when e^l <= fl(fl(r_x r_y) tau); 0 = exact */
+    float sigma_to_r;   /* support half-width in standard deviations; the paper's Gaussian uses 3 */
+    int32_t algo;       /* PNDF_ALGO_* */
+    int32_t flags;      /* reserved, must be 0 */
+} pndf_eval_opts;
+
+typedef struct pndf_hier_opts {
+    int32_t cluster;    /* 1: fit the cluster hierarchy (needed for tau > 0); 0: min-max only */
+} pndf_hier_opts;
+
+/*
+ * Build the triangle mesh of a normal map (Fig. normal_map, Eq. interpolation,
+ * Eq. jacobian, section "Preventing Jacobian singularity").
+ *   normals  device pointer, N*N*2 float32, row-major (x, y) pairs, index (j*N + i)*2 with
+ *            i along u; every |n| must be < 1 and finite (else PNDF_EINVAL)
+ *   n        map side N: a power of two, 2 <= N <= 8192 (N > 8192: PNDF_EUNSUPPORTED)
+ *   eps      Jacobian clamp threshold (the paper uses 1e-6); must be > 0 and finite
+ *   out      receives the mesh handle (library-owned HBM: the padded normal planes, per-cell
+ *            clamp bits and FP64-derived Jacobians)
+ * The input is copied: the caller may free it once this call returns.  The call
+ * synchronises `stream` (it validates the map on the device and reads the result).
+ */
+pndf_status pndf_build_mesh(const float* normals, int32_t n, float eps, void* stream,
+                            pndf_mesh** out);
+
+/*
+ * Build the acceleration hierarchies of a mesh (section "Acceleration by mesh
+ * clustering"; supplement "Derivations of Cluster Normal Optimization"):
+ *   - the min-max hierarchy: for every 2^l x 2^l node (l = 1..log2 N) the normal-space
+ *     bounding box of every triangle beneath it (clamped triangles by their replacement);
+ *   - with opts->cluster: four cluster normals per node minimising the inverse-Jacobian
+ *     weighted squared distance between the cluster's two-triangle interpolant and the
+ *     map (Eq. normal_optimization), the minimised objective e^l (in texel-area units),
+ *     the cluster triangles' Jacobians (2 area / 4^l, clamped at eps like the map's), and
+ *     a second bounding-box hierarchy that also covers the cluster triangles.
+ * opts may be NULL (cluster = 1).  The mesh must outlive nothing: the hierarchy keeps
+ * a reference, so the caller may destroy the mesh handle at any time.  Synchronises
+ * `stream`.
+ */
+pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* opts, void* stream,
+                                 pndf_hier** out);
+
+/*
+ * Evaluate D(m, x) (Eq. ndf_eval) for nq queries.
+ *   d_q    device pointer to nq pndf_query records (caller-owned)
+ *   nq     number of queries, >= 0 (0 is a no-op)
+ *   opts   may be NULL (Gaussian, tau = 0, sigma_to_r = 3, auto algorithm)
+ *   d_out  device pointer to nq float32 results (caller-owned)
+ * Asynchronous and stream-ordered; the caller keeps d_q and d_out alive until the
+ * stream's work completes.  Deterministic: each query's result depends only on that
+ * query and the hierarchy, bit for bit, whatever else is in the batch.  tau > 0
+ * needs a hierarchy built with clusters (else PNDF_EINVAL).
+ */
+pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                            const pndf_eval_opts* opts, float* d_out, void* stream);
+
+/*
+ * As pndf_eval_batch, plus per-query work counters (debug/roofline accounting):
+ *   d_counts  device pointer to nq * 4 uint32: nodes tested, leaf cells tested,
+ *             cluster nodes used, hit triangles (for the brute-force algorithm the
+ *             node count is 0).
+ * The values of d_out are identical to pndf_eval_batch's.
+ */
+pndf_status pndf_eval_counts(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                             const pndf_eval_opts* opts, float* d_out, uint32_t* d_counts,
+                             void* stream);
+
+/*
+ * As pndf_eval_batch, plus the list of hit triangles of every query, for parity
+ * checks: CSR offsets d_offsets[nq + 1] (uint64, d_offsets[0] = 0), triangle ids
+ * d_ids[] and per-hit terms d_terms[] (float32: kernel weight summed over included
+ * periodic images, divided by the clamped Jacobian).  A triangle id packs
+ * (level << 58) | (J << 29) | (I << 1) | half: level 0 is a texel cell (I, J) and
+ * half 0 its lower triangle (u0, u1, u2), 1 its upper (u3, u2, u1); level >= 1 is a
+ * cluster node (I, J) of that level and its lower/upper cluster triangle.
+ * capacity is the length of d_ids and d_terms.  If the total number of hits exceeds
+ * it, returns PNDF_EOVERFLOW with *required set (d_out and d_offsets are still
+ * written).  Synchronises `stream` (two passes: count, then fill).
+ */
+pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                           const pndf_eval_opts* opts, float* d_out, uint64_t* d_offsets,
+                           uint64_t* d_ids, float* d_terms, uint64_t capacity,
+                           uint64_t* required, void* stream);
+
+/* Release handles (no work may be in flight on them).  NULL is ignored. */
+void pndf_destroy_mesh(pndf_mesh* mesh);
+void pndf_destroy_hierarchy(pndf_hier* h);
+
+const char* pndf_status_string(pndf_status s);
+const char* pndf_last_error(void);
+
+/* ---- introspection, for parity checks of the build steps ----------------- */
+
+/* Map side, clamp threshold and device bytes held by the mesh. */
+pndf_status pndf_mesh_info(const pndf_mesh* mesh, int32_t* n, float* eps, int64_t* bytes);
+
+/* Copy the mesh's per-cell clamp bits (N*N uint8: bit0 lower, bit1 upper clamped)
+ * and Jacobians used by the evaluation (N*N*2 float32, lower then upper; eps for
+ * clamped triangles) into caller device buffers.  Either pointer may be NULL. */
+pndf_status pndf_mesh_export(const pndf_mesh* mesh, uint8_t* d_deg, float* d_det, void* stream);
+
+/* Levels (log2 N), whether clusters were fitted, and device bytes of a hierarchy. */
+pndf_status pndf_hier_info(const pndf_hier* h, int32_t* levels, int32_t* cluster, int64_t* bytes);
+
+/* Copy level `level` (1..log2 N) of the hierarchy, (N >> level)^2 nodes in row-major
+ * node order (J * (N >> level) + I), into caller device buffers (any may be NULL):
+ *   d_bbox      4 float32 per node: min x, min y, max x, max y over the map's triangles
+ *   d_bbox_all  the same box extended by every cluster triangle at or below the node
+ *   d_clu_n     8 float32 per node: cluster normals N0..N3 (corners (0,0),(1,0),(0,1),(1,1))
+ *   d_clu_e     1 float32 per node: e^l
+ *   d_clu_det   2 float32 per node: Jacobians of the lower/upper cluster triangle
+ *               (eps when clamped)
+ * The cluster arrays need a hierarchy built with clusters (else PNDF_EINVAL). */
+pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_bbox,
+                                   float* d_bbox_all, float* d_clu_n, float* d_clu_e,
+                                   float* d_clu_det, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNDF_H */

@@ -50,11 +50,17 @@ def load():
                             _dp, _i64p, _i64p, _i32p,
                             _i64p, _u64p, _dp, _i64p, _u64p, _dp, _u8p]
     lib.or_sample_normals.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, ctypes.c_int64, _dp]
+    lib.or_num_threads.argtypes = []
     for f in (lib.or_mesh, lib.or_cluster_nodes, lib.or_fine_contrib, lib.or_eval,
-              lib.or_sample_normals):
+              lib.or_sample_normals, lib.or_num_threads):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def num_threads():
+    """OpenMP threads the oracle runs with."""
+    return int(load().or_num_threads())
 
 
 def _p(a, t):

@@ -665,3 +665,16 @@ int or_sample_normals(int n, const float* nrm, float eps, const double* u, int64
     }
     return 0;
 }
+
+/* number of OpenMP threads the evaluation uses (for reporting CPU baselines) */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,13 @@
+"""MI355X (gfx950) library for batched evaluation of the manifold-based P-NDF.
+
+The compute path is the HIP library libpndf.so (C ABI in include/pndf.h); this
+package is its thin Python binding.  Importing it requires the library to be
+built (`python -m paper_2505_08985_amd.build`).
+"""
+from .binding import (Mesh, Hierarchy, PndfError, build_mesh, build_hierarchy, eval_batch,
+                      eval_counts, eval_hits, mesh_info, mesh_export, hier_info, hier_export_level,
+                      EXPORTED, LIB_PATH)
+
+__all__ = ["Mesh", "Hierarchy", "PndfError", "build_mesh", "build_hierarchy", "eval_batch",
+           "eval_counts", "eval_hits", "mesh_info", "mesh_export", "hier_info",
+           "hier_export_level", "EXPORTED", "LIB_PATH"]

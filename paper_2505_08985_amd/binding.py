@@ -1,0 +1,249 @@
+"""Python binding of the C ABI in include/pndf.h (argument marshalling only).
+
+Device memory and streams come from PyTorch-ROCm; every step of the evaluation
+runs in the library's HIP kernels.  There is no CPU fallback: if the library is
+not built this module raises on import.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpndf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpndf.so is not built: run `python -m paper_2505_08985_amd.build` "
+                      "(or __graft_entry__.build()) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+PNDF_OK, PNDF_EINVAL, PNDF_ENOMEM, PNDF_EDEVICE, PNDF_EOVERFLOW, PNDF_EUNSUPPORTED, PNDF_EAGAIN = range(7)
+ALGOS = {"auto": 0, "brute": 1, "plain": 2, "persistent": 3}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_f32 = ctypes.c_float
+
+
+class EvalOpts(ctypes.Structure):
+    _fields_ = [("kernel", _i32), ("tau", _f32), ("sigma_to_r", _f32), ("algo", _i32), ("flags", _i32)]
+
+
+class HierOpts(ctypes.Structure):
+    _fields_ = [("cluster", _i32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_build_mesh = _sig("pndf_build_mesh", _i32, [_vp, _i32, _f32, _vp, ctypes.POINTER(_vp)])
+_build_hier = _sig("pndf_build_hierarchy", _i32, [_vp, ctypes.POINTER(HierOpts), _vp, ctypes.POINTER(_vp)])
+_eval_batch = _sig("pndf_eval_batch", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp])
+_eval_counts = _sig("pndf_eval_counts", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp])
+_eval_hits = _sig("pndf_eval_hits", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp, _vp,
+                                           _u64, ctypes.POINTER(_u64), _vp])
+_destroy_mesh = _sig("pndf_destroy_mesh", None, [_vp])
+_destroy_hier = _sig("pndf_destroy_hierarchy", None, [_vp])
+_status_string = _sig("pndf_status_string", ctypes.c_char_p, [_i32])
+_last_error = _sig("pndf_last_error", ctypes.c_char_p, [])
+_mesh_info = _sig("pndf_mesh_info", _i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f32), ctypes.POINTER(_i64)])
+_mesh_export = _sig("pndf_mesh_export", _i32, [_vp, _vp, _vp, _vp])
+_hier_info = _sig("pndf_hier_info", _i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)])
+_hier_export = _sig("pndf_hier_export_level", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp])
+
+EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_eval_counts",
+            "pndf_eval_hits", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
+            "pndf_last_error", "pndf_mesh_info", "pndf_mesh_export", "pndf_hier_info",
+            "pndf_hier_export_level"]
+
+
+class PndfError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (where, _status_string(status).decode(), msg))
+
+
+def _check(st, where):
+    if st != PNDF_OK:
+        raise PndfError(st, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return _vp(t.data_ptr())
+
+
+class Mesh:
+    def __init__(self, handle, n, eps):
+        self._h = handle
+        self.n = n
+        self.eps = eps
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _destroy_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hierarchy:
+    def __init__(self, handle, mesh, cluster):
+        self._h = handle
+        self.mesh = mesh
+        self.n = mesh.n
+        self.cluster = cluster
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _destroy_hier(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_mesh(normals, eps=1e-6, stream=None):
+    """normals: (N, N, 2) float32 device tensor."""
+    if normals.dim() != 3 or normals.shape[0] != normals.shape[1] or normals.shape[2] != 2:
+        raise ValueError("normals must have shape (N, N, 2)")
+    out = _vp()
+    _check(_build_mesh(_dev_ptr(normals, torch.float32, "normals"), int(normals.shape[0]), float(eps),
+                       _stream(stream), ctypes.byref(out)), "pndf_build_mesh")
+    return Mesh(out, int(normals.shape[0]), float(eps))
+
+
+def build_hierarchy(mesh, cluster=True, stream=None):
+    out = _vp()
+    opts = HierOpts(1 if cluster else 0)
+    _check(_build_hier(mesh.handle, ctypes.byref(opts), _stream(stream), ctypes.byref(out)),
+           "pndf_build_hierarchy")
+    return Hierarchy(out, mesh, bool(cluster))
+
+
+def _opts(tau, sigma_to_r, algo, kernel=0):
+    return EvalOpts(int(kernel), float(tau), float(sigma_to_r), ALGOS[algo] if isinstance(algo, str) else int(algo), 0)
+
+
+def _queries(q):
+    if q.dim() != 2 or q.shape[1] != 6:
+        raise ValueError("queries must have shape (Q, 6)")
+    return _dev_ptr(q, torch.float32, "queries"), int(q.shape[0])
+
+
+def eval_batch(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, stream=None, kernel=0):
+    qp, nq = _queries(queries)
+    if out is None:
+        out = torch.empty(nq, dtype=torch.float32, device=queries.device)
+    o = _opts(tau, sigma_to_r, algo, kernel)
+    _check(_eval_batch(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
+                       _stream(stream)), "pndf_eval_batch")
+    return out
+
+
+def eval_counts(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", stream=None):
+    """Returns (D, counts (Q, 4) int32: nodes, cells, clusters, hits)."""
+    qp, nq = _queries(queries)
+    out = torch.empty(nq, dtype=torch.float32, device=queries.device)
+    counts = torch.zeros((nq, 4), dtype=torch.int32, device=queries.device)
+    o = _opts(tau, sigma_to_r, algo)
+    _check(_eval_counts(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
+                        _dev_ptr(counts, torch.int32, "counts"), _stream(stream)), "pndf_eval_counts")
+    return out, counts
+
+
+def eval_hits(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", capacity=None, stream=None):
+    """Returns (D, offsets (Q+1,) int64, ids (H,) int64, terms (H,) float32)."""
+    qp, nq = _queries(queries)
+    dev = queries.device
+    out = torch.empty(nq, dtype=torch.float32, device=dev)
+    offs = torch.zeros(nq + 1, dtype=torch.int64, device=dev)
+    o = _opts(tau, sigma_to_r, algo)
+    req = _u64(0)
+    cap = 0 if capacity is None else int(capacity)
+    ids = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    terms = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    st = _eval_hits(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
+                    _dev_ptr(offs, torch.int64, "offsets"), _vp(ids.data_ptr()), _vp(terms.data_ptr()),
+                    cap, ctypes.byref(req), _stream(stream))
+    if st == PNDF_EOVERFLOW and capacity is None:
+        cap = int(req.value)
+        ids = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+        terms = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        st = _eval_hits(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
+                        _dev_ptr(offs, torch.int64, "offsets"), _vp(ids.data_ptr()), _vp(terms.data_ptr()),
+                        cap, ctypes.byref(req), _stream(stream))
+    _check(st, "pndf_eval_hits")
+    total = int(req.value)
+    return out, offs, ids[:total], terms[:total]
+
+
+def mesh_info(mesh):
+    n, eps, b = _i32(), _f32(), _i64()
+    _check(_mesh_info(mesh.handle, ctypes.byref(n), ctypes.byref(eps), ctypes.byref(b)), "pndf_mesh_info")
+    return dict(n=n.value, eps=eps.value, bytes=b.value)
+
+
+def mesh_export(mesh, stream=None):
+    n = mesh.n
+    deg = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+    det = torch.empty((n, n, 2), dtype=torch.float32, device="cuda")
+    _check(_mesh_export(mesh.handle, _vp(deg.data_ptr()), _vp(det.data_ptr()), _stream(stream)),
+           "pndf_mesh_export")
+    return deg, det
+
+
+def hier_info(hier):
+    lv, cl, b = _i32(), _i32(), _i64()
+    _check(_hier_info(hier.handle, ctypes.byref(lv), ctypes.byref(cl), ctypes.byref(b)), "pndf_hier_info")
+    return dict(levels=lv.value, cluster=bool(cl.value), bytes=b.value)
+
+
+def hier_export_level(hier, level, stream=None):
+    m = hier.n >> level
+    bbox = torch.empty((m, m, 4), dtype=torch.float32, device="cuda")
+    if hier.cluster:
+        bbox_all = torch.empty((m, m, 4), dtype=torch.float32, device="cuda")
+        clu_n = torch.empty((m, m, 4, 2), dtype=torch.float32, device="cuda")
+        clu_e = torch.empty((m, m), dtype=torch.float32, device="cuda")
+        clu_det = torch.empty((m, m, 2), dtype=torch.float32, device="cuda")
+        ptrs = [_vp(t.data_ptr()) for t in (bbox_all, clu_n, clu_e, clu_det)]
+    else:
+        bbox_all = clu_n = clu_e = clu_det = None
+        ptrs = [None] * 4
+    _check(_hier_export(hier.handle, int(level), _vp(bbox.data_ptr()), *ptrs, _stream(stream)),
+           "pndf_hier_export_level")
+    return dict(bbox=bbox, bbox_all=bbox_all, clu_n=clu_n, clu_e=clu_e, clu_det=clu_det)

@@ -1,0 +1,369 @@
+// Host side of the C ABI declared in include/pndf.h: argument validation, handle
+// ownership, device allocation and kernel dispatch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pndf_internal.h"
+
+namespace pndf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+pndf_status hip_fail(hipError_t e, const char* what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? PNDF_ENOMEM : PNDF_EDEVICE;
+}
+
+static pndf_status invalid(const std::string& msg)
+{
+    set_error(msg);
+    return PNDF_EINVAL;
+}
+
+// Surface an earlier asynchronous fault before starting new work.
+static pndf_status check_sticky()
+{
+    hipError_t e = hipPeekAtLastError();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return hip_fail(e, "earlier device error");
+    }
+    return PNDF_OK;
+}
+
+static int ilog2_exact(int n)
+{
+    int l = 0;
+    while (l < 31 && (1 << l) < n) ++l;
+    return (1 << l) == n ? l : -1;
+}
+
+static void fill_view(pndf_hier* h)
+{
+    HierDev& d = h->dev;
+    const pndf_mesh* m = h->mesh;
+    d.nrm = m->nrm;
+    d.deg = m->deg;
+    d.det = m->det;
+    d.bbox = h->bbox;
+    d.bbox_all = h->bbox_all;
+    d.clu_n = h->clu_n;
+    d.clu_e = h->clu_e;
+    d.clu_det = h->clu_det;
+    d.clu_deg = h->clu_deg;
+    d.n = m->n;
+    d.L = m->L;
+    d.logn = m->L;
+    d.eps = m->eps;
+    d.rho = (float)std::sqrt(2.0 * (double)m->eps / (3.0 * std::sqrt(3.0)));
+    int64_t off = 0;
+    for (int l = 0; l < kMaxLevels + 2; ++l) d.off[l] = 0;
+    for (int l = 1; l <= m->L; ++l) {
+        d.off[l] = off;
+        off += (int64_t)(m->n >> l) * (m->n >> l);
+    }
+    d.off[m->L + 1] = off;
+}
+
+static void mesh_release(pndf_mesh* m)
+{
+    if (!m) return;
+    if (m->refs.fetch_sub(1) == 1) {
+        (void)hipFree(m->nrm);
+        (void)hipFree(m->deg);
+        (void)hipFree(m->det);
+        delete m;
+    }
+}
+
+static pndf_status resolve_opts(const pndf_hier* h, const pndf_eval_opts* o, pndf_eval_opts* out)
+{
+    pndf_eval_opts d;
+    d.kernel = PNDF_KERNEL_GAUSSIAN;
+    d.tau = 0.f;
+    d.sigma_to_r = 3.f;
+    d.algo = PNDF_ALGO_AUTO;
+    d.flags = 0;
+    if (o) d = *o;
+    if (d.kernel != PNDF_KERNEL_GAUSSIAN) {
+        set_error("only the Gaussian footprint kernel is implemented");
+        return PNDF_EUNSUPPORTED;
+    }
+    if (!(std::isfinite(d.tau) && d.tau >= 0.f)) return invalid("tau must be finite and >= 0");
+    if (!(std::isfinite(d.sigma_to_r) && d.sigma_to_r > 0.f))
+        return invalid("sigma_to_r must be finite and > 0");
+    if (d.flags != 0) return invalid("flags must be 0");
+    if (d.algo < PNDF_ALGO_AUTO || d.algo > PNDF_ALGO_PERSISTENT) return invalid("unknown algo");
+    if (d.algo == PNDF_ALGO_PERSISTENT) {
+        set_error("use pndf_eval_persistent for the persistent traversal");
+        return PNDF_EUNSUPPORTED;
+    }
+    if (d.tau > 0.f && !h->cluster) return invalid("tau > 0 needs a hierarchy built with clusters");
+    if (d.tau > 0.f && d.algo == PNDF_ALGO_BRUTE) return invalid("brute force evaluates tau = 0 only");
+    *out = d;
+    return PNDF_OK;
+}
+
+}  // namespace pndf
+
+using namespace pndf;
+
+extern "C" {
+
+const char* pndf_status_string(pndf_status s)
+{
+    switch (s) {
+    case PNDF_OK: return "ok";
+    case PNDF_EINVAL: return "invalid argument";
+    case PNDF_ENOMEM: return "out of memory";
+    case PNDF_EDEVICE: return "device error";
+    case PNDF_EOVERFLOW: return "buffer too small";
+    case PNDF_EUNSUPPORTED: return "unsupported";
+    case PNDF_EAGAIN: return "try again";
+    }
+    return "unknown status";
+}
+
+const char* pndf_last_error(void) { return g_last_error.c_str(); }
+
+pndf_status pndf_build_mesh(const float* normals, int32_t n, float eps, void* stream,
+                            pndf_mesh** out)
+{
+    if (!out) return invalid("out is NULL");
+    *out = nullptr;
+    if (!normals) return invalid("normals is NULL");
+    const int L = ilog2_exact(n);
+    if (n < 2 || L < 0) return invalid("map side must be a power of two >= 2");
+    if (n > 8192) {
+        set_error("map side above 8192");
+        return PNDF_EUNSUPPORTED;
+    }
+    if (!(std::isfinite(eps) && eps > 0.f)) return invalid("eps must be finite and > 0");
+    pndf_status st = check_sticky();
+    if (st != PNDF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    pndf_mesh* m = new (std::nothrow) pndf_mesh;
+    if (!m) return PNDF_ENOMEM;
+    m->n = n;
+    m->L = L;
+    m->eps = eps;
+    (void)hipGetDevice(&m->device);
+    const size_t np = (size_t)(n + 1) * (n + 1), nc = (size_t)n * n;
+    unsigned* d_flag = nullptr;
+    hipError_t e = hipMalloc(&m->nrm, sizeof(float2) * np);
+    if (e == hipSuccess) e = hipMalloc(&m->deg, nc);
+    if (e == hipSuccess) e = hipMalloc(&m->det, sizeof(float2) * nc);
+    if (e == hipSuccess) e = hipMalloc(&d_flag, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemsetAsync(d_flag, 0, sizeof(unsigned), s);
+    if (e == hipSuccess) e = launch_build_mesh(normals, n, eps, m->nrm, m->deg, m->det, d_flag, s);
+    unsigned flag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, d_flag, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_flag);
+    if (e != hipSuccess) {
+        mesh_release(m);
+        return hip_fail(e, "pndf_build_mesh");
+    }
+    if (flag) {
+        mesh_release(m);
+        return invalid("normal map has a non-finite value or |n| >= 1");
+    }
+    m->bytes = (int64_t)(sizeof(float2) * np + nc + sizeof(float2) * nc);
+    *out = m;
+    return PNDF_OK;
+}
+
+void pndf_destroy_mesh(pndf_mesh* mesh) { mesh_release(mesh); }
+
+pndf_status pndf_mesh_info(const pndf_mesh* mesh, int32_t* n, float* eps, int64_t* bytes)
+{
+    if (!mesh) return invalid("mesh is NULL");
+    if (n) *n = mesh->n;
+    if (eps) *eps = mesh->eps;
+    if (bytes) *bytes = mesh->bytes;
+    return PNDF_OK;
+}
+
+pndf_status pndf_mesh_export(const pndf_mesh* mesh, uint8_t* d_deg, float* d_det, void* stream)
+{
+    if (!mesh) return invalid("mesh is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nc = (size_t)mesh->n * mesh->n;
+    hipError_t e = hipSuccess;
+    if (d_deg) e = hipMemcpyAsync(d_deg, mesh->deg, nc, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && d_det)
+        e = hipMemcpyAsync(d_det, mesh->det, sizeof(float2) * nc, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_mesh_export");
+}
+
+pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* opts, void* stream,
+                                 pndf_hier** out)
+{
+    if (!out) return invalid("out is NULL");
+    *out = nullptr;
+    if (!mesh) return invalid("mesh is NULL");
+    const int cluster = opts ? opts->cluster : 1;
+    if (cluster != 0 && cluster != 1) return invalid("cluster must be 0 or 1");
+    pndf_status st = check_sticky();
+    if (st != PNDF_OK) return st;
+    pndf_hier* h = new (std::nothrow) pndf_hier;
+    if (!h) return PNDF_ENOMEM;
+    pndf_mesh* m = const_cast<pndf_mesh*>(mesh);
+    m->refs.fetch_add(1);
+    h->mesh = m;
+    h->cluster = cluster;
+    h->L = m->L;
+    int64_t nodes = 0;
+    for (int l = 1; l <= m->L; ++l) nodes += (int64_t)(m->n >> l) * (m->n >> l);
+    h->nodes = nodes;
+    hipError_t e = hipMalloc(&h->bbox, sizeof(float4) * nodes);
+    if (cluster) {
+        if (e == hipSuccess) e = hipMalloc(&h->bbox_all, sizeof(float4) * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->clu_n, sizeof(float4) * 2 * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->clu_e, sizeof(float) * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->clu_det, sizeof(float2) * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->clu_deg, nodes);
+    }
+    fill_view(h);
+    if (e == hipSuccess) e = build_hierarchy_levels(h, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        pndf_destroy_hierarchy(h);
+        return hip_fail(e, "pndf_build_hierarchy");
+    }
+    h->bytes = (int64_t)nodes * (16 + (cluster ? 16 + 32 + 4 + 8 + 1 : 0));
+    *out = h;
+    return PNDF_OK;
+}
+
+void pndf_destroy_hierarchy(pndf_hier* h)
+{
+    if (!h) return;
+    (void)hipFree(h->bbox);
+    (void)hipFree(h->bbox_all);
+    (void)hipFree(h->clu_n);
+    (void)hipFree(h->clu_e);
+    (void)hipFree(h->clu_det);
+    (void)hipFree(h->clu_deg);
+    mesh_release(h->mesh);
+    delete h;
+}
+
+pndf_status pndf_hier_info(const pndf_hier* h, int32_t* levels, int32_t* cluster, int64_t* bytes)
+{
+    if (!h) return invalid("hierarchy is NULL");
+    if (levels) *levels = h->L;
+    if (cluster) *cluster = h->cluster;
+    if (bytes) *bytes = h->bytes;
+    return PNDF_OK;
+}
+
+pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_bbox,
+                                   float* d_bbox_all, float* d_clu_n, float* d_clu_e,
+                                   float* d_clu_det, void* stream)
+{
+    if (!h) return invalid("hierarchy is NULL");
+    if (level < 1 || level > h->L) return invalid("level out of range");
+    if (!h->cluster && (d_bbox_all || d_clu_n || d_clu_e || d_clu_det))
+        return invalid("hierarchy has no clusters");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t off = h->dev.off[level];
+    const size_t m = (size_t)(h->mesh->n >> level) * (h->mesh->n >> level);
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (dst && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    };
+    cp(d_bbox, h->bbox + off, sizeof(float4) * m);
+    if (h->cluster) {
+        cp(d_bbox_all, h->bbox_all + off, sizeof(float4) * m);
+        cp(d_clu_n, h->clu_n + 2 * off, sizeof(float4) * 2 * m);
+        cp(d_clu_e, h->clu_e + off, sizeof(float) * m);
+        cp(d_clu_det, h->clu_det + off, sizeof(float2) * m);
+    }
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_hier_export_level");
+}
+
+static pndf_status eval_common(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                               const pndf_eval_opts* opts, float* d_out, pndf_eval_opts* o)
+{
+    if (!h) return invalid("hierarchy is NULL");
+    if (nq < 0) return invalid("nq < 0");
+    if (nq > 0 && (!d_q || !d_out)) return invalid("query or output pointer is NULL");
+    if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
+    pndf_status st = resolve_opts(h, opts, o);
+    if (st != PNDF_OK) return st;
+    return check_sticky();
+}
+
+pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                            const pndf_eval_opts* opts, float* d_out, void* stream)
+{
+    pndf_eval_opts o;
+    pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
+    if (st != PNDF_OK) return st;
+    EvalArgs a{d_q, nq, d_out, nullptr, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    hipError_t e = launch_eval(h->dev, a, o.algo, (hipStream_t)stream);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_batch");
+}
+
+pndf_status pndf_eval_counts(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                             const pndf_eval_opts* opts, float* d_out, uint32_t* d_counts,
+                             void* stream)
+{
+    pndf_eval_opts o;
+    pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
+    if (st != PNDF_OK) return st;
+    if (nq > 0 && !d_counts) return invalid("counts pointer is NULL");
+    EvalArgs a{d_q, nq, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    hipError_t e = launch_eval(h->dev, a, o.algo, (hipStream_t)stream);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_counts");
+}
+
+pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                           const pndf_eval_opts* opts, float* d_out, uint64_t* d_offsets,
+                           uint64_t* d_ids, float* d_terms, uint64_t capacity,
+                           uint64_t* required, void* stream)
+{
+    pndf_eval_opts o;
+    pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
+    if (st != PNDF_OK) return st;
+    if (!required) return invalid("required is NULL");
+    if (nq > 0 && !d_offsets) return invalid("offsets pointer is NULL");
+    if (capacity > 0 && (!d_ids || !d_terms)) return invalid("id or term pointer is NULL");
+    *required = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (nq == 0) return PNDF_OK;
+    uint32_t* d_counts = nullptr;
+    hipError_t e = hipMalloc(&d_counts, sizeof(uint32_t) * 4 * (size_t)nq);
+    if (e != hipSuccess) return hip_fail(e, "pndf_eval_hits");
+    EvalArgs a{d_q, nq, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    e = launch_eval(h->dev, a, o.algo, s);
+    std::vector<uint32_t> counts((size_t)nq * 4);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts.data(), d_counts, sizeof(uint32_t) * 4 * nq, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    std::vector<uint64_t> offs((size_t)nq + 1, 0);
+    for (int64_t k = 0; k < nq; ++k) offs[k + 1] = offs[k] + counts[4 * k + 3];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_offsets, offs.data(), sizeof(uint64_t) * (nq + 1), hipMemcpyHostToDevice, s);
+    *required = offs[nq];
+    if (e == hipSuccess && offs[nq] <= capacity && offs[nq] > 0) {
+        EvalArgs b{d_q, nq, d_out, nullptr, d_offsets, d_ids, d_terms, o.tau, o.sigma_to_r};
+        e = launch_eval(h->dev, b, o.algo, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_counts);
+    if (e != hipSuccess) return hip_fail(e, "pndf_eval_hits");
+    if (offs[nq] > capacity) {
+        set_error("hit buffer too small");
+        return PNDF_EOVERFLOW;
+    }
+    return PNDF_OK;
+}
+
+}  // extern "C"

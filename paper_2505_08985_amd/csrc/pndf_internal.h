@@ -1,0 +1,260 @@
+// Internal definitions of the gfx950 P-NDF library: handle layouts, the device
+// view passed to kernels, and the device helpers shared by the evaluation
+// kernels (query setup, periodic-image arithmetic, triangle tests, hit terms).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+
+#include "../../include/pndf.h"
+
+namespace pndf {
+
+constexpr int kMaxLevels = 13;   // N <= 8192
+constexpr int kWave = 64;
+constexpr int kListCap = 256;    // per-level traversal list (64 parents x 4 children)
+constexpr int kCellCap = 320;    // leaf-cell queue: < 64 waiting + 256 pushed by one batch
+
+// Device-side view of a mesh + hierarchy, passed to kernels by value.
+struct HierDev {
+    const float2* nrm;      // (n+1) x (n+1) padded texel normals (last row/column wrap)
+    const uint8_t* deg;     // n x n clamp bits (bit0 lower, bit1 upper)
+    const float2* det;      // n x n Jacobians used by the evaluation (lower, upper)
+    const float4* bbox;     // all levels packed: min x, min y, max x, max y (map triangles)
+    const float4* bbox_all; // same, extended by cluster triangles (nullptr without clusters)
+    const float4* clu_n;    // 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x, N2.y, N3.x, N3.y)
+    const float* clu_e;     // e^l per node
+    const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
+    const uint8_t* clu_deg; // cluster clamp bits
+    int n, L, logn;
+    float eps;
+    float rho;              // circumradius of the clamp replacement triangle (area eps / 2)
+    int64_t off[kMaxLevels + 2]; // first node of level l in the packed arrays (off[1] = 0)
+};
+
+}  // namespace pndf
+
+struct pndf_mesh {
+    std::atomic<int> refs{1};
+    int device = 0;
+    int n = 0, L = 0;
+    float eps = 0.f;
+    float2* nrm = nullptr;
+    uint8_t* deg = nullptr;
+    float2* det = nullptr;
+    int64_t bytes = 0;
+};
+
+struct pndf_hier {
+    pndf_mesh* mesh = nullptr;
+    int cluster = 0;
+    int L = 0;
+    int64_t nodes = 0;
+    float4* bbox = nullptr;
+    float4* bbox_all = nullptr;
+    float4* clu_n = nullptr;
+    float* clu_e = nullptr;
+    float2* clu_det = nullptr;
+    uint8_t* clu_deg = nullptr;
+    int64_t bytes = 0;
+    pndf::HierDev dev;
+};
+
+namespace pndf {
+
+// ---------------------------------------------------------------- host side
+void set_error(const std::string& msg);
+pndf_status hip_fail(hipError_t e, const char* what);
+
+// launchers implemented in the .hip files
+hipError_t launch_build_mesh(const float* in, int n, float eps, float2* nrm, uint8_t* deg,
+                             float2* det, unsigned* d_flag, hipStream_t s);
+hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s);
+
+struct EvalArgs {
+    const pndf_query* q;
+    int64_t nq;
+    float* out;
+    uint32_t* counts;          // nullptr unless counting
+    const uint64_t* offsets;   // hit-record pass only
+    uint64_t* ids;
+    float* terms;
+    float tau;
+    float s2r;
+};
+hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s);
+
+// ---------------------------------------------------------------- device side
+#if defined(__HIPCC__)
+
+__device__ __forceinline__ float cross2(float ax, float ay, float bx, float by)
+{
+    return fmaf(ax, by, -(ay * bx));
+}
+
+__device__ __forceinline__ int floor_div_pow2(int a, int logn) { return a >> logn; }
+__device__ __forceinline__ int ceil_div_pow2(int a, int logn) { return -((-a) >> logn); }
+
+// Per-query constants, identical for every lane of the wave that owns the query.
+struct QuerySetup {
+    float x, y, hx, hy;
+    int cxlo, cxhi, cylo, cyhi;  // included unrolled cell range per axis
+    int l0;                      // entry level
+    float t;                     // cut threshold fl(fl(rx ry) tau)
+    float kx, ky;                // log2(e) / (2 sigma^2)
+    float norm;                  // 1 / (2 pi sx sy)
+    bool valid;
+};
+
+// Support box, entry level and kernel constants of one query (see pndf.h).
+__device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float tau, int L)
+{
+    QuerySetup q;
+    q.x = qr.x; q.y = qr.y; q.hx = qr.hx; q.hy = qr.hy;
+    const float lim = 16777216.0f;
+    bool ok = isfinite(qr.x) && isfinite(qr.y) && isfinite(qr.sx) && isfinite(qr.sy) &&
+              isfinite(qr.hx) && isfinite(qr.hy) && qr.sx > 0.f && qr.sy > 0.f;
+    float rx = __fmul_rn(s2r, qr.sx), ry = __fmul_rn(s2r, qr.sy);
+    ok = ok && fabsf(qr.x) <= lim && fabsf(qr.y) <= lim && rx <= lim && ry <= lim;
+    q.valid = ok;
+    if (!ok) {
+        q.cxlo = q.cylo = 0; q.cxhi = q.cyhi = -1; q.l0 = 0; q.t = -1.f;
+        q.kx = q.ky = q.norm = 0.f;
+        return q;
+    }
+    float lox = __fsub_rn(qr.x, rx), hix = __fadd_rn(qr.x, rx);
+    float loy = __fsub_rn(qr.y, ry), hiy = __fadd_rn(qr.y, ry);
+    q.cxlo = (int)ceilf(lox) - 1; q.cxhi = (int)floorf(hix);
+    q.cylo = (int)ceilf(loy) - 1; q.cyhi = (int)floorf(hiy);
+    float rmax = fmaxf(rx, ry);
+    int l0 = 0;
+    while (l0 < L && (float)(1 << l0) < rmax) l0++;
+    q.l0 = l0;
+    q.t = tau > 0.f ? __fmul_rn(__fmul_rn(rx, ry), tau) : -1.f;
+    const double log2e = 1.4426950408889634074;
+    q.kx = (float)(log2e / (2.0 * (double)qr.sx * (double)qr.sx));
+    q.ky = (float)(log2e / (2.0 * (double)qr.sy * (double)qr.sy));
+    q.norm = (float)(1.0 / (2.0 * 3.14159265358979323846 * (double)qr.sx * (double)qr.sy));
+    return q;
+}
+
+// Does a node of side 2^lev starting at torus cell `start` have a periodic image
+// with a cell inside the unrolled cell range [clo, chi]?
+__device__ __forceinline__ bool axis_overlap(int start, int side, int clo, int chi, int logn)
+{
+    return ceil_div_pow2(clo - start - side + 1, logn) <= floor_div_pow2(chi - start, logn);
+}
+
+// Sum over the included periodic images of one axis of exp(-d^2 / (2 sigma^2)),
+// d = start + p N + uoff - x; node of side `side` (1 for a texel cell).
+__device__ inline float gauss_axis(float x, float k, int start, int side, double uoff, int clo,
+                                   int chi, int logn)
+{
+    int p0 = ceil_div_pow2(clo - start - side + 1, logn);
+    int p1 = floor_div_pow2(chi - start, logn);
+    float g = 0.f;
+    double base = (double)start + uoff - (double)x;
+    for (int p = p0; p <= p1; ++p) {
+        double d = base + (double)p * (double)(1 << logn);
+        g += exp2f(-(float)(d * d) * k);
+    }
+    return g;
+}
+
+// Replacement-triangle vertices (circumradius rho around c, at 90/210/330 degrees).
+__device__ __forceinline__ void eqtri_f32(float cx, float cy, float rho, float v[6])
+{
+    const float c30 = 0.86602540378443864676f;
+    v[0] = cx;                     v[1] = cy + rho;
+    v[2] = cx - rho * c30;         v[3] = cy - 0.5f * rho;
+    v[4] = cx + rho * c30;         v[5] = cy - 0.5f * rho;
+}
+
+__device__ __forceinline__ void eqtri_f64(double cx, double cy, double rho, double v[6])
+{
+    const double c30 = 0.86602540378443864676;
+    v[0] = cx;                     v[1] = cy + rho;
+    v[2] = cx - rho * c30;         v[3] = cy - 0.5 * rho;
+    v[4] = cx + rho * c30;         v[5] = cy - 0.5 * rho;
+}
+
+// Inclusive point-in-triangle test in float32 with the cyclic edge functions of the
+// vertex offsets q_k = v_k - h: lambda_0 ~ q_b x q_c, lambda_1 ~ q_c x q_a,
+// lambda_2 ~ q_a x q_b (all of one sign inside, whatever the orientation).
+__device__ __forceinline__ bool tri_hit_f32(const float v[6], float hx, float hy)
+{
+    float ax = v[0] - hx, ay = v[1] - hy, bx = v[2] - hx, by = v[3] - hy;
+    float cx = v[4] - hx, cy = v[5] - hy;
+    float e0 = cross2(bx, by, cx, cy), e1 = cross2(cx, cy, ax, ay), e2 = cross2(ax, ay, bx, by);
+    return (e0 >= 0.f && e1 >= 0.f && e2 >= 0.f) || (e0 <= 0.f && e1 <= 0.f && e2 <= 0.f);
+}
+
+// FP64 barycentrics of h in triangle v (a, b, c); returns false if h is outside.
+__device__ inline bool tri_bary_f64(const double v[6], double hx, double hy, double* l1, double* l2)
+{
+    double ax = v[0] - hx, ay = v[1] - hy, bx = v[2] - hx, by = v[3] - hy;
+    double cx = v[4] - hx, cy = v[5] - hy;
+    double e0 = bx * cy - by * cx, e1 = cx * ay - cy * ax, e2 = ax * by - ay * bx;
+    bool in = (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) || (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0);
+    double S = e0 + e1 + e2;
+    *l1 = e1 / S;
+    *l2 = e2 / S;
+    return in;
+}
+
+// Contribution of a hit: the triangle's uv vertices are (a, b, c) =
+// lower: (U0, U0 + s e_x, U0 + s e_y), upper: (U3, U3 - s e_x, U3 - s e_y) of the node
+// (I, J) of side s = 2^lev (lev = 0: texel cell), so u* = corner +- s (l1, l2).
+__device__ inline float hit_term(const QuerySetup& q, int I, int J, int lev, int half, double l1,
+                                 double l2, float det_used, int logn)
+{
+    const int s = 1 << lev;
+    double ux = half ? (double)s * (1.0 - l1) : (double)s * l1;
+    double uy = half ? (double)s * (1.0 - l2) : (double)s * l2;
+    float gx = gauss_axis(q.x, q.kx, I * s, s, ux, q.cxlo, q.cxhi, logn);
+    float gy = gauss_axis(q.y, q.ky, J * s, s, uy, q.cylo, q.cyhi, logn);
+    return q.norm * gx * gy / det_used;
+}
+
+__device__ __forceinline__ uint64_t tri_id(int lev, int I, int J, int half)
+{
+    return ((uint64_t)lev << 58) | ((uint64_t)J << 29) | ((uint64_t)I << 1) | (uint64_t)half;
+}
+
+// Wave-level helpers (wave64).
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exclusive prefix over the wave of a per-lane count in [0, 7], and the total.
+__device__ __forceinline__ int wave_prefix_small(int c, int* total)
+{
+    uint64_t b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4);
+    uint64_t lt = (1ull << lane_id()) - 1ull;
+    *total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+    return __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+#endif  // __HIPCC__
+
+}  // namespace pndf

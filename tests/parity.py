@@ -1,0 +1,79 @@
+"""Parity checking of GPU results against the FP64 oracle.
+
+Protocol: the oracle reports, per query, its hit triangles with their terms and
+every triangle whose normal-space boundary lies within 1e-6 of the query normal
+(ambiguous: hit or miss may flip under float32 rounding), with the term it would
+contribute.  The GPU's hit-id set must equal the oracle's outside the ambiguous
+set.  The reference value is then recomputed with the GPU's include/exclude
+choice for each ambiguous triangle, and |D_gpu - D_ref| <= rtol * D_ref.
+Queries whose cluster cut decision sits within rounding of the threshold
+(oracle flag bit 0) are excluded from the strict comparison and counted.
+"""
+import numpy as np
+
+RTOL = 1e-4
+
+
+def _split(off, vals):
+    return [vals[off[k]:off[k + 1]] for k in range(len(off) - 1)]
+
+
+def compare(ref, d_gpu, gpu_off=None, gpu_ids=None, rtol=RTOL, check_ids=True):
+    """ref: oracle.evaluate(..., records=True) dict.  d_gpu: (Q,) float32.
+    gpu_off / gpu_ids: CSR hit lists from the GPU (optional).
+    Returns a dict of statistics; raises AssertionError on a mismatch."""
+    d_gpu = np.asarray(d_gpu, dtype=np.float64)
+    nq = len(d_gpu)
+    D = ref["D"]
+    flags = ref["flags"]
+    nan_ref = np.isnan(D)
+    assert np.array_equal(nan_ref, np.isnan(d_gpu)), "NaN pattern differs"
+    skip = (flags & 1) != 0
+    hoff, hid, hterm = ref["hit_off"], ref["hit_id"], ref["hit_term"]
+    aoff, aid, aterm = ref["amb_off"], ref["amb_id"], ref["amb_term"]
+    worst = 0.0
+    n_amb_q = 0
+    bad = []
+    for k in range(nq):
+        if nan_ref[k] or skip[k]:
+            continue
+        h_ids = hid[hoff[k]:hoff[k + 1]]
+        h_terms = hterm[hoff[k]:hoff[k + 1]]
+        a_ids = aid[aoff[k]:aoff[k + 1]]
+        a_terms = aterm[aoff[k]:aoff[k + 1]]
+        amb = set(a_ids.tolist())
+        if amb:
+            n_amb_q += 1
+        if gpu_ids is not None:
+            g = gpu_ids[gpu_off[k]:gpu_off[k + 1]].tolist()
+            gset = set(g)
+            if check_ids:
+                assert len(gset) == len(g), "query %d: duplicate GPU hit ids" % k
+                diff = gset.symmetric_difference(set(h_ids.tolist()))
+                if not diff <= amb:
+                    bad.append((k, sorted(diff - amb)[:4]))
+                    continue
+            # reference with the GPU's choice on ambiguous triangles
+            dref = float(sum(t for i, t in zip(h_ids.tolist(), h_terms.tolist()) if i not in amb))
+            dref += float(sum(t for i, t in zip(a_ids.tolist(), a_terms.tolist()) if i in gset))
+        else:
+            if amb:
+                # without the GPU's ids, accept any choice on the ambiguous set
+                base = float(sum(t for i, t in zip(h_ids.tolist(), h_terms.tolist()) if i not in amb))
+                lo, hi = base, base + float(np.sum(a_terms))
+                if lo * (1 - rtol) - 1e-30 <= d_gpu[k] <= hi * (1 + rtol) + 1e-30:
+                    continue
+                bad.append((k, "value %r outside [%r, %r]" % (d_gpu[k], lo, hi)))
+                continue
+            dref = D[k]
+        if dref == 0.0:
+            if d_gpu[k] != 0.0:
+                bad.append((k, "gpu %r ref 0" % d_gpu[k]))
+            continue
+        err = abs(d_gpu[k] - dref) / dref
+        worst = max(worst, err)
+        if err > rtol:
+            bad.append((k, "rel err %.3g (gpu %r ref %r)" % (err, d_gpu[k], dref)))
+    assert not bad, "%d mismatching queries, first: %s" % (len(bad), bad[:5])
+    return dict(worst_rel=worst, ambiguous_queries=n_amb_q, cut_ambiguous=int(skip.sum()),
+                nonzero=int((np.nan_to_num(D) > 0).sum()))

@@ -1,0 +1,379 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Every case prints what it runs before touching the device.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from parity import compare
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
+
+EPS32 = float(np.float32(1e-6))
+
+
+def announce(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2505_08985_amd as P
+    return P
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_build(P, nrm, cluster=True):
+    import torch
+    mesh = P.build_mesh(to_dev(nrm))
+    hier = P.build_hierarchy(mesh, cluster=cluster)
+    torch.cuda.synchronize()
+    return mesh, hier
+
+
+def gpu_hits(P, hier, q, tau=0.0, algo="auto"):
+    import torch
+    d, off, ids, terms = P.eval_hits(hier, to_dev(q), tau=tau, algo=algo)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), off.cpu().numpy(), ids.cpu().numpy().view(np.uint64), terms.cpu().numpy()
+
+
+def random_disk_map(n, seed, radius=0.5):
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.uniform(size=(n, n)))
+    t = rng.uniform(0, 2 * np.pi, size=(n, n))
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=-1).astype(np.float32)
+
+
+def mixed_queries(n, count, seed, smin, smax, radius, aniso=True, spread=1.0):
+    rng = np.random.default_rng(seed)
+    q = np.zeros((count, 6), dtype=np.float32)
+    q[:, 0:2] = rng.uniform(-spread * n, (1 + spread) * n, (count, 2)) if spread > 0 else rng.uniform(0, n, (count, 2))
+    q[:, 2] = np.exp(rng.uniform(np.log(smin), np.log(smax), count))
+    q[:, 3] = q[:, 2] * (np.exp(rng.uniform(-0.7, 0.7, count)) if aniso else 1.0)
+    r = radius * np.sqrt(rng.uniform(size=count))
+    t = rng.uniform(0, 2 * np.pi, count)
+    q[:, 4] = r * np.cos(t)
+    q[:, 5] = r * np.sin(t)
+    return q
+
+
+MAPS = {
+    "bumps64": lambda: __import__("workloads").make_map("bumps", 64, 101, count=32),
+    "powerlaw128": lambda: __import__("workloads").make_map("powerlaw", 128, 7),
+    "disk32": lambda: random_disk_map(32, 3, 0.45),
+    "scratched128": lambda: __import__("workloads").make_map(
+        "scratched", 128, 9, scratches=60, flakes=150),
+}
+
+
+# --------------------------------------------------------------- mesh build
+@pytest.mark.parametrize("name", sorted(MAPS))
+def test_mesh_build_bit_exact(P, oracle_mod, name):
+    announce("mesh build %s" % name)
+    nrm = MAPS[name]()
+    mesh, hier = gpu_build(P, nrm, cluster=False)
+    deg, det = P.mesh_export(mesh)
+    odet, odeg = oracle_mod.mesh(nrm)
+    np.testing.assert_array_equal(deg.cpu().numpy(), odeg)
+    want = np.where(odet < EPS32, np.float32(EPS32), odet.astype(np.float32)).astype(np.float32)
+    np.testing.assert_array_equal(det.cpu().numpy(), want)
+
+
+def test_mesh_rejects_bad_maps(P):
+    import torch
+    announce("mesh validation")
+    bad = np.zeros((8, 8, 2), dtype=np.float32)
+    bad[3, 4] = (0.8, 0.7)                     # |n| >= 1
+    with pytest.raises(P.PndfError):
+        P.build_mesh(to_dev(bad))
+    bad[3, 4] = (np.nan, 0)
+    with pytest.raises(P.PndfError):
+        P.build_mesh(to_dev(bad))
+    with pytest.raises(P.PndfError):
+        P.build_mesh(torch.zeros((6, 6, 2), device="cuda"))   # not a power of two
+    with pytest.raises(P.PndfError):
+        P.build_mesh(torch.zeros((8, 8, 2), device="cuda"), eps=0.0)
+
+
+# ----------------------------------------------------------- hierarchy build
+def triangle_boxes(nrm, deg, rho):
+    """Per-cell box over both triangles (clamped ones by their replacement disk)."""
+    n = nrm.shape[0]
+    f = nrm.astype(np.float64)
+    n0 = f
+    n1 = np.roll(f, -1, axis=1)
+    n2 = np.roll(f, -1, axis=0)
+    n3 = np.roll(n1, -1, axis=0)
+    c = 0.5 * (n1 + n2)
+    lo = np.full((n, n, 2), np.inf)
+    hi = np.full((n, n, 2), -np.inf)
+    for bit, verts in ((1, (n0, n1, n2)), (2, (n3, n2, n1))):
+        dg = (deg & bit) != 0
+        vmin = np.minimum(np.minimum(verts[0], verts[1]), verts[2])
+        vmax = np.maximum(np.maximum(verts[0], verts[1]), verts[2])
+        vmin = np.where(dg[..., None], c - rho, vmin)
+        vmax = np.where(dg[..., None], c + rho, vmax)
+        lo = np.minimum(lo, vmin)
+        hi = np.maximum(hi, vmax)
+    return lo, hi
+
+
+@pytest.mark.parametrize("name", sorted(MAPS))
+def test_hierarchy_boxes_and_clusters(P, oracle_mod, name):
+    announce("hierarchy build %s" % name)
+    nrm = MAPS[name]()
+    n = nrm.shape[0]
+    L = int(math.log2(n))
+    mesh, hier = gpu_build(P, nrm, cluster=True)
+    _, odeg = oracle_mod.mesh(nrm)
+    rho = math.sqrt(2 * EPS32 / (3 * math.sqrt(3)))
+    clo, chi = triangle_boxes(nrm, odeg, rho)
+    for level in range(1, L + 1):
+        ex = P.hier_export_level(hier, level)
+        m = n >> level
+        s = 1 << level
+        box = ex["bbox"].cpu().numpy().astype(np.float64)
+        lo = clo.reshape(m, s, m, s, 2).min(axis=(1, 3))
+        hi = chi.reshape(m, s, m, s, 2).max(axis=(1, 3))
+        # conservative and tight: contains every triangle, within 2e-6 of the true extent
+        assert (box[..., 0] <= lo[..., 0]).all() and (box[..., 1] <= lo[..., 1]).all()
+        assert (box[..., 2] >= hi[..., 0]).all() and (box[..., 3] >= hi[..., 1]).all()
+        assert (box[..., 0] >= lo[..., 0] - 2e-6).all() and (box[..., 2] <= hi[..., 0] + 2e-6).all()
+        ns, e = oracle_mod.cluster_level(nrm, level)
+        gn = ex["clu_n"].cpu().numpy().reshape(m * m, 4, 2).astype(np.float64)
+        ge = ex["clu_e"].cpu().numpy().reshape(m * m).astype(np.float64)
+        scale = np.abs(ns).max() + 1e-3
+        np.testing.assert_allclose(gn, ns, rtol=0, atol=2e-6 * scale)
+        np.testing.assert_allclose(ge, e, rtol=2e-5, atol=1e-9 * (np.abs(e).max() + 1e-30))
+        # cluster boxes cover the cluster triangles
+        ball = ex["bbox_all"].cpu().numpy()
+        assert (ball[..., 0] <= box[..., 0]).all() and (ball[..., 2] >= box[..., 2]).all()
+        cn = ex["clu_n"].cpu().numpy()
+        cdet = ex["clu_det"].cpu().numpy()
+        for half, idx in ((0, (0, 1, 2)), (1, (3, 2, 1))):
+            v = cn[:, :, list(idx), :]
+            d = np.abs((v[:, :, 2, 0].astype(np.float64) - v[:, :, 0, 0]) * (v[:, :, 1, 1].astype(np.float64) - v[:, :, 0, 1])
+                       - (v[:, :, 2, 1].astype(np.float64) - v[:, :, 0, 1]) * (v[:, :, 1, 0].astype(np.float64) - v[:, :, 0, 0])) / (s * s)
+            clamped = d < EPS32
+            want = np.where(clamped, np.float32(EPS32), d.astype(np.float32))
+            np.testing.assert_allclose(cdet[..., half], want, rtol=1e-6)
+            nc = ~clamped
+            assert (ball[..., 0][nc] <= v[..., 0].min(axis=2)[nc]).all()
+            assert (ball[..., 2][nc] >= v[..., 0].max(axis=2)[nc]).all()
+
+
+# ------------------------------------------------------------- evaluation
+def run_parity(P, oracle_mod, nrm, q, tau=0.0, algo="auto", clusters=None, hier=None):
+    if hier is None:
+        _, hier = gpu_build(P, nrm, cluster=tau > 0)
+    d, off, ids, terms = gpu_hits(P, hier, q, tau=tau, algo=algo)
+    ref = oracle_mod.evaluate(nrm, q, tau=tau, clusters=clusters, records=True)
+    st = compare(ref, d, off, ids)
+    # the plain output equals the hit-record pass bit for bit
+    import torch
+    d2 = P.eval_batch(hier, to_dev(q), tau=tau, algo=algo).cpu().numpy()
+    np.testing.assert_array_equal(d2.view(np.uint32), d.view(np.uint32))
+    return st
+
+
+def test_brute_bumps64_all_queries(P, oracle_mod):
+    """The small configuration: 64^2 bumps, 4096 queries, sigma = 2, |h| < 0.3."""
+    import workloads
+    announce("eval brute bumps64 4096 queries")
+    nrm = workloads.make_map("bumps", 64, 101, count=32)
+    q = workloads.uniform_queries(64, 4096, 102, 2.0, 0.3)
+    st = run_parity(P, oracle_mod, nrm, q, algo="brute")
+    assert st["nonzero"] > 100
+
+
+@pytest.mark.parametrize("algo", ["plain", "brute"])
+def test_plain_bumps64_all_queries(P, oracle_mod, algo):
+    import workloads
+    announce("eval %s bumps64 4096 queries, query normals inside the map's range" % algo)
+    nrm = workloads.make_map("bumps", 64, 101, count=32)
+    q = workloads.uniform_queries(64, 4096, 102, 2.0, 0.1)
+    st = run_parity(P, oracle_mod, nrm, q, algo=algo)
+    assert st["nonzero"] > 1000
+
+
+@pytest.mark.parametrize("name", sorted(MAPS))
+def test_plain_mixed_footprints(P, oracle_mod, name):
+    """Footprints from 0.05 to ~2N texels (periodic images), anisotropic, centres
+    outside the base period; a ragged batch size."""
+    announce("eval plain mixed %s" % name)
+    nrm = MAPS[name]()
+    n = nrm.shape[0]
+    q = mixed_queries(n, 1499, 11, 0.05, 0.7 * n, 0.35)
+    st = run_parity(P, oracle_mod, nrm, q)
+    assert st["nonzero"] > 200
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-3, 1e-2])
+@pytest.mark.parametrize("name", ["bumps64", "powerlaw128", "scratched128"])
+def test_cluster_cut(P, oracle_mod, name, tau):
+    announce("eval cut tau=%g %s" % (tau, name))
+    nrm = MAPS[name]()
+    n = nrm.shape[0]
+    clusters = oracle_mod.cluster_all(nrm)
+    q = mixed_queries(n, 1003, 21, 0.3, 0.5 * n, 0.35)
+    st = run_parity(P, oracle_mod, nrm, q, tau=tau, clusters=clusters)
+    assert st["cut_ambiguous"] <= 5
+
+
+def test_edge_cases(P, oracle_mod):
+    import torch
+    announce("eval edge cases")
+    nrm = random_disk_map(16, 5, 0.45)
+    _, hier = gpu_build(P, nrm, cluster=True)
+    # empty batch
+    out = P.eval_batch(hier, torch.zeros((0, 6), device="cuda"))
+    assert out.numel() == 0
+    q = np.array([
+        [3.5, 4.5, 0.01, 0.01, 0.1, 0.1],       # tiny footprint: entry level 0
+        [3.5, 4.5, 1e-3, 5.0, 0.1, 0.1],        # extreme anisotropy
+        [-100.25, 700.5, 2.0, 2.0, 0.0, 0.0],   # far outside the base period
+        [7.0, 7.0, 200.0, 200.0, 0.05, -0.1],   # many periods wide
+        [7.0, 7.0, 2.0, 2.0, 1.5, 0.0],         # |h| > 1: zero
+        [7.0, 7.0, 2.0, 2.0, 0.999, 0.0],
+        [np.nan, 1, 1, 1, 0, 0],                 # invalid: NaN
+        [1, 1, 0.0, 1, 0, 0],                   # sigma = 0
+        [1, 1, 1, -2, 0, 0],                    # sigma < 0
+        [1, 1, 1, 1, np.inf, 0],
+        [3e7, 1, 1, 1, 0, 0],                   # beyond 2^24
+        [1, 1, 1e7, 1, 0, 0],                   # r beyond 2^24
+        [8.0, 8.0, 1.0 / 3.0, 1.0 / 3.0, 0.2, 0.1],  # box edges on cell boundaries
+        [0.0, 0.0, 2.0 / 3.0, 2.0 / 3.0, -0.2, 0.1],
+    ], dtype=np.float32)
+    d, off, ids, terms = gpu_hits(P, hier, q)
+    ref = oracle_mod.evaluate(nrm, q, records=True)
+    compare(ref, d, off, ids)
+    assert np.isnan(d[6:12]).all() and d[4] == 0.0
+    clusters = oracle_mod.cluster_all(nrm)
+    d, off, ids, terms = gpu_hits(P, hier, q, tau=1e-3)
+    compare(oracle_mod.evaluate(nrm, q, tau=1e-3, clusters=clusters, records=True), d, off, ids)
+
+
+def test_minimal_map(P, oracle_mod):
+    announce("eval on a 2x2 map")
+    nrm = random_disk_map(2, 8, 0.4)
+    q = mixed_queries(2, 301, 3, 0.05, 6.0, 0.4)
+    run_parity(P, oracle_mod, nrm, q)
+
+
+def test_options_and_errors(P):
+    import torch
+    announce("eval option validation")
+    nrm = random_disk_map(8, 2)
+    _, hier = gpu_build(P, nrm, cluster=False)
+    q = torch.zeros((4, 6), device="cuda")
+    q[:, 2:4] = 1.0
+    with pytest.raises(P.PndfError):
+        P.eval_batch(hier, q, tau=1e-3)           # no clusters
+    with pytest.raises(P.PndfError):
+        P.eval_batch(hier, q, tau=-1.0)
+    with pytest.raises(P.PndfError):
+        P.eval_batch(hier, q, sigma_to_r=0.0)
+    with pytest.raises(P.PndfError):
+        P.eval_batch(hier, q, kernel=1)
+    _, hier2 = gpu_build(P, nrm, cluster=True)
+    with pytest.raises(P.PndfError):
+        P.eval_batch(hier2, q, tau=1e-3, algo="brute")
+
+
+def test_sigma_to_r(P, oracle_mod):
+    announce("eval with a different support width")
+    nrm = random_disk_map(32, 6, 0.4)
+    q = mixed_queries(32, 500, 4, 0.3, 8.0, 0.35)
+    _, hier = gpu_build(P, nrm, cluster=False)
+    import torch
+    d, off, ids, terms = P.eval_hits(hier, to_dev(q), sigma_to_r=2.0)
+    ref = oracle_mod.evaluate(nrm, q, sigma_to_r=2.0, records=True)
+    compare(ref, d.cpu().numpy(), off.cpu().numpy(), ids.cpu().numpy().view(np.uint64))
+
+
+def test_counts_are_consistent(P, oracle_mod):
+    import workloads
+    announce("eval counters")
+    nrm = workloads.make_map("powerlaw", 128, 7)
+    q = mixed_queries(128, 700, 5, 0.3, 30.0, 0.3, spread=0)
+    _, hier = gpu_build(P, nrm, cluster=True)
+    import torch
+    tq = to_dev(q)
+    d, c = P.eval_counts(hier, tq)
+    d0 = P.eval_batch(hier, tq)
+    assert torch.equal(d.view(torch.int32), d0.view(torch.int32))
+    dd, off, ids, terms = P.eval_hits(hier, tq)
+    c = c.cpu().numpy()
+    np.testing.assert_array_equal(c[:, 3], np.diff(off.cpu().numpy()))
+    assert (c[:, 2] == 0).all()
+    db, cb = P.eval_counts(hier, tq, algo="brute")
+    cb = cb.cpu().numpy()
+    for k in range(len(q)):
+        sx = np.float32(3) * q[k, 2]
+        sy = np.float32(3) * q[k, 3]
+        nx = math.floor(np.float32(q[k, 0] + sx)) - (math.ceil(np.float32(q[k, 0] - sx)) - 1) + 1
+        ny = math.floor(np.float32(q[k, 1] + sy)) - (math.ceil(np.float32(q[k, 1] - sy)) - 1) + 1
+        assert cb[k, 1] == min(nx, 128) * min(ny, 128)
+    # the hierarchy tests at most as many cells as brute force and finds the same hits
+    assert (c[:, 1] <= cb[:, 1]).all()
+    np.testing.assert_array_equal(c[:, 3], cb[:, 3])
+    dt, ct = P.eval_counts(hier, tq, tau=1e-2)
+    assert ct.cpu().numpy()[:, 2].sum() > 0
+
+
+def test_deterministic_alone_and_in_the_mix(P):
+    import torch
+    import workloads
+    announce("determinism: repeat and batch composition")
+    nrm = workloads.make_map("powerlaw", 256, 12)
+    _, hier = gpu_build(P, nrm, cluster=True)
+    q = mixed_queries(256, 4000, 6, 0.5, 40.0, 0.3, spread=0)
+    tq = to_dev(q)
+    for tau in (0.0, 1e-3):
+        a = P.eval_batch(hier, tq, tau=tau)
+        b = P.eval_batch(hier, tq, tau=tau)
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+        sub = np.arange(5, 4000, 37)
+        alone = P.eval_batch(hier, to_dev(q[sub]), tau=tau)
+        assert torch.equal(alone.view(torch.int32), a[torch.from_numpy(sub).cuda()].view(torch.int32))
+        perm = np.random.default_rng(1).permutation(4000)
+        c = P.eval_batch(hier, to_dev(q[perm]), tau=tau)
+        inv = np.argsort(perm)
+        assert torch.equal(c[torch.from_numpy(inv).cuda()].view(torch.int32), a.view(torch.int32))
+
+
+def test_full_size_powerlaw2048_sampled(P, oracle_mod):
+    """The measured workload at full size (2048^2 power-law map, 2^20 queries, sigma
+    log-uniform in [1, 64], |h| < 0.4), in the launch configuration the benchmark
+    times; a stratified sample is checked against the oracle query by query."""
+    import torch
+    import workloads
+    announce("full size powerlaw2048, 1M queries, sampled parity")
+    cfg = workloads.CONFIGS["powerlaw2048"]
+    nrm = workloads.make_map(**cfg["map"])
+    qc = cfg["queries"]
+    q = workloads.uniform_queries(2048, qc["count"], qc["seed"], qc["sigma"], qc["radius"])
+    _, hier = gpu_build(P, nrm, cluster=True)
+    tq = to_dev(q)
+    d = P.eval_batch(hier, tq).cpu().numpy()
+    assert np.isfinite(d).all() and (d >= 0).all()
+    # stratified sample: 160 per sigma octave, plus the nonzero ones are well represented
+    rng = np.random.default_rng(0)
+    oct_ = np.floor(np.log2(q[:, 2])).astype(int)
+    sample = np.concatenate([rng.choice(np.where(oct_ == o)[0], 160, replace=False) for o in range(6)])
+    ref = oracle_mod.evaluate(nrm, q[sample], records=True)
+    dh, off, ids, terms = gpu_hits(P, hier, q[sample])
+    np.testing.assert_array_equal(dh.view(np.uint32), d[sample].view(np.uint32))
+    st = compare(ref, dh, off, ids)
+    assert st["nonzero"] > 100
