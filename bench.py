@@ -79,6 +79,95 @@ def cpu_baseline(nrm, q, tau, budget_s=15.0):
                       "every included cell)" % (k2, dt2)}
 
 
+SERVE_MAPS = (dict(kind="bumps", n=1024, seed=411, count=8192),
+              dict(kind="scratched", n=4096, seed=301),
+              dict(kind="powerlaw", n=8192, seed=501, rms_slope=0.15))
+
+
+def serve_bench(args):
+    """Serving workload: Poisson arrivals of render tiles (64 x 64 px x 4 spp) over three
+    resident maps, footprints from synthetic ray differentials; continuous batching
+    (persistent plans on concurrent streams) against FIFO per-tile plain evaluation,
+    at fractions of the plain per-tile throughput."""
+    import torch
+    import paper_2505_08985_amd as P
+    import workloads
+    tau = args.serve_tau
+    hiers, ns = [], []
+    t0 = time.perf_counter()
+    for mc in SERVE_MAPS:
+        nrm = workloads.make_map(**mc)
+        mesh = P.build_mesh(torch.from_numpy(nrm).cuda())
+        hiers.append(P.build_hierarchy(mesh, cluster=True))
+        ns.append(mc["n"])
+        del nrm
+        torch.cuda.synchronize()
+        print("[serve] map %s %d^2 resident (%.1f s)" % (mc["kind"], mc["n"], time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    rng = np.random.default_rng(401)
+    ntiles = args.serve_tiles
+    mids = rng.integers(0, len(SERVE_MAPS), ntiles)
+    smax = args.serve_sigma_max
+    tiles = [workloads.tile_request(ns[m], int(rng.integers(1 << 30)), sigma_range=(0.5, smax)) for m in mids]
+    # plain per-tile cost (each tile alone, synchronised)
+    dq = [torch.from_numpy(t).cuda() for t in tiles]
+    for m, q in zip(mids[:4], dq[:4]):
+        P.eval_batch(hiers[m], q, tau=tau)
+    torch.cuda.synchronize()
+    cost = []
+    for m, q in zip(mids, dq):
+        a = time.perf_counter()
+        P.eval_batch(hiers[m], q, tau=tau)
+        torch.cuda.synchronize()
+        cost.append(time.perf_counter() - a)
+    cost = np.array(cost)
+    plain_tiles_per_s = ntiles / cost.sum()
+    print("[serve] plain per-tile: %.2f tiles/s (median tile %.2f ms, max %.1f ms)"
+          % (plain_tiles_per_s, 1e3 * np.median(cost), 1e3 * cost.max()), file=sys.stderr, flush=True)
+    qpt = tiles[0].shape[0]
+    results = []
+    srv = P.Server(hiers, slots=args.serve_slots, max_batch_queries=qpt * args.serve_batch_tiles,
+                   max_pending=4 * ntiles, tau=tau)
+    srv.replay(mids[:4], np.zeros(4), tiles[:4])  # warm-up
+    for frac in [float(f) for f in args.serve_rates.split(",")]:
+        rate = frac * plain_tiles_per_s
+        arr = np.cumsum(rng.exponential(1.0 / rate, ntiles))
+        arr -= arr[0]
+        # FIFO per-tile plain evaluation at the same arrivals (simulated from measured costs)
+        free, lat_fifo = 0.0, []
+        for a, c in zip(arr, cost):
+            start = max(a, free)
+            free = start + c
+            lat_fifo.append(1e3 * (free - a))
+        srv.reset_stats()
+        a = time.perf_counter()
+        outs, lat = srv.replay(mids, arr, tiles)
+        wall = time.perf_counter() - a
+        st = srv.stats()
+        results.append({"rate_frac": frac, "tiles_per_s_offered": rate,
+                        "served_queries_per_s": ntiles * qpt / wall,
+                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "mean_batch_tiles": st["mean_batch_requests"],
+                        "fifo_plain_p50_ms": float(np.percentile(lat_fifo, 50)),
+                        "fifo_plain_p99_ms": float(np.percentile(lat_fifo, 99)),
+                        "fifo_plain_queries_per_s": ntiles * qpt / max(free, arr[-1])})
+        print("[serve] %s" % json.dumps(results[-1]), file=sys.stderr, flush=True)
+    # saturation throughput: everything arrives at once
+    srv.reset_stats()
+    a = time.perf_counter()
+    srv.replay(mids, np.zeros(ntiles), tiles)
+    sat = ntiles * qpt / (time.perf_counter() - a)
+    srv.close()
+    line = {"metric": METRIC, "value": sat, "unit": "queries/s", "n_gpus": 1, "steps": ntiles,
+            "warmup": 4, "ms_per_step": 1e3 * qpt / sat, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "serving: Poisson 64x64x4 tiles over bumps1024 / scratched4096 / "
+                                   "powerlaw8192", "tau": tau, "sigma_range": [0.5, smax],
+                       "slots": args.serve_slots, "batch_tiles": args.serve_batch_tiles},
+            "plain_per_tile_queries_per_s": plain_tiles_per_s * qpt, "by_rate": results}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +178,13 @@ def main():
     ap.add_argument("--queries", type=int, default=0, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-octaves", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark (continuous batching)")
+    ap.add_argument("--serve-tau", type=float, default=1e-3)
+    ap.add_argument("--serve-tiles", type=int, default=200)
+    ap.add_argument("--serve-sigma-max", type=float, default=4096.0)
+    ap.add_argument("--serve-rates", default="0.5,0.8,0.95")
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-batch-tiles", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (3 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -107,6 +203,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}), flush=True)
+        return
+    if args.serve:
+        serve_bench(args)
         return
     import paper_2505_08985_amd as P
     import workloads

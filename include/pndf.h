@@ -73,7 +73,7 @@ enum {
     PNDF_ALGO_AUTO = 0,       /* plain hierarchical traversal */
     PNDF_ALGO_BRUTE = 1,      /* every triangle of every included cell, no hierarchy (tau must be 0) */
     PNDF_ALGO_PLAIN = 2,      /* one wavefront per query, min-max (+ cluster cut) traversal */
-    PNDF_ALGO_PERSISTENT = 3  /* persistent work-stealing traversal (see pndf_eval_persistent) */
+    PNDF_ALGO_PERSISTENT = 3  /* persistent work-stealing traversal: needs a plan (pndf_plan_create) */
 };
 
 typedef struct pndf_eval_opts {
@@ -169,6 +169,139 @@ void pndf_destroy_hierarchy(pndf_hier* h);
 
 const char* pndf_status_string(pndf_status s);
 const char* pndf_last_error(void);
+
+/* ---- persistent work-stealing evaluation ----------------------------------
+ *
+ * A plan owns the workspace of the persistent traversal for batches of up to
+ * max_nq queries: a fixed grid of workers (compute units x blocks_per_cu blocks of
+ * four wavefronts) takes queries from a global counter; a query whose entry level
+ * is above split_level descends to that level and donates the surviving subtrees
+ * to a global task queue, from which idle workers steal.  Each query's terms are
+ * summed exactly (128-bit fixed point), so the result is bit-identical to
+ * pndf_eval_batch whatever the split, the schedule or the batch composition.
+ * The launch sequence (reset, workers, finalize) is instantiated once as a HIP
+ * graph and replayed per batch.
+ */
+typedef struct pndf_plan pndf_plan;
+
+typedef struct pndf_tuning {
+    int32_t blocks_per_cu; /* worker blocks per compute unit (>= 1) */
+    int32_t split_level;   /* donated subtree level, 1..log2 N */
+    int32_t queue_factor;  /* task-queue slots per query of max_nq (>= 1); a donation that does not
+                            * fit is descended in place, so capacity only affects balance */
+    int32_t use_graph;     /* 1: replay the instantiated graph; 0: three plain launches */
+} pndf_tuning;
+
+typedef struct pndf_plan_stats {
+    uint64_t spawned;      /* subtrees donated to the queue in the last run */
+    uint64_t refused;      /* donations that did not fit and were descended in place */
+    uint64_t idle_spins;   /* worker polls that found no work (load-balance diagnostic) */
+    uint32_t error;        /* nonzero: a worker gave up waiting (bit0 idle, bit1 slot); results invalid */
+} pndf_plan_stats;
+
+/* Default tuning for a hierarchy (used when pndf_plan_create gets tuning == NULL). */
+pndf_status pndf_default_tuning(const pndf_hier* h, pndf_tuning* out);
+
+/*
+ * Create a plan for batches of at most max_nq (>= 1) queries with the given options
+ * (opts->algo is ignored) and tuning (NULL: pndf_default_tuning).  The hierarchy must
+ * outlive the plan.  Allocates device memory; synchronises `stream`.
+ */
+pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval_opts* opts,
+                             const pndf_tuning* tuning, void* stream, pndf_plan** out);
+
+/*
+ * Evaluate nq (0 <= nq <= max_nq) queries with the plan: same contract as
+ * pndf_eval_batch (asynchronous, stream-ordered, deterministic).  Runs of one plan
+ * must not overlap: order them on one stream (the plan's workspace is reused).
+ */
+pndf_status pndf_plan_eval(pndf_plan* plan, const pndf_query* d_q, int64_t nq, float* d_out,
+                           void* stream);
+
+/* Statistics of the plan's last run (synchronises `stream`). */
+pndf_status pndf_plan_get_stats(pndf_plan* plan, pndf_plan_stats* out, void* stream);
+
+void pndf_plan_destroy(pndf_plan* plan);
+
+/*
+ * Autotuner: time the persistent traversal on the given queries (a representative
+ * sample of the workload) for every candidate tuning (blocks per compute unit 1..4,
+ * split level 3..8 within the map's levels, graph replay) and return the fastest in
+ * *best, with its time per batch in *best_ms (may be NULL).  Synchronises `stream`.
+ */
+pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                          const pndf_eval_opts* opts, pndf_tuning* best, double* best_ms,
+                          void* stream);
+
+/* ---- serving: continuous batching over resident maps ----------------------
+ *
+ * A server keeps one or more hierarchies resident and evaluates requests (for
+ * example one render tile: a block of queries against one map) as they arrive.
+ * A request is admitted when its pinned staging fits the memory budget and the
+ * pending queue has room; otherwise pndf_server_submit returns PNDF_EAGAIN.  A
+ * scheduler thread packs admitted requests of the same map into batches (up to
+ * max_batch_queries) and runs each batch with a persistent plan on one of
+ * `slots` streams, so batches formed while others execute overlap on the device
+ * (continuous batching).  Results are bit-identical to pndf_eval_batch for the
+ * same queries, whatever the batch a request lands in.  Latency is measured from
+ * submission to the moment its results are in host memory.
+ */
+typedef struct pndf_server pndf_server;
+
+typedef struct pndf_server_opts {
+    int32_t slots;              /* concurrent batches in flight (streams), >= 1 */
+    int64_t max_batch_queries;  /* queries per batch (and the largest request), >= 1 */
+    int64_t memory_budget;      /* bytes of pinned staging for admitted requests (28 B per query) */
+    int32_t max_pending;        /* admitted requests not yet finished, >= 1 */
+    float tau;                  /* cluster cut threshold for every request (0 = exact) */
+    float sigma_to_r;           /* support half-width in standard deviations (3) */
+    pndf_tuning tuning;         /* persistent-plan tuning (blocks_per_cu = 0: default) */
+} pndf_server_opts;
+
+typedef struct pndf_server_stats {
+    uint64_t completed, refused;       /* requests finished / refused by admission */
+    uint64_t queries, batches;         /* queries evaluated, batches launched */
+    double p50_ms, p99_ms, max_ms;     /* request latency percentiles (completed requests) */
+    double mean_batch_requests;        /* average requests per batch */
+    double busy_s;                     /* wall time from first admission to last completion */
+} pndf_server_stats;
+
+/* Create a server over nmaps resident hierarchies (which must outlive it). */
+pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, const pndf_server_opts* opts,
+                               pndf_server** out);
+
+/*
+ * Submit a request: nq queries (host memory, copied at submission) against map
+ * `map`; results are written to h_out (host memory, nq floats, caller-owned, valid
+ * until the request completes).  *ticket identifies it.  PNDF_EAGAIN: not admitted
+ * (memory budget or pending limit), nothing was queued.
+ */
+pndf_status pndf_server_submit(pndf_server* srv, int32_t map, const pndf_query* h_q, int64_t nq,
+                               float* h_out, uint64_t* ticket);
+
+/* Wait for a request (timeout_s < 0: forever).  *latency_ms (may be NULL) receives
+ * its latency.  PNDF_EAGAIN on timeout. */
+pndf_status pndf_server_wait(pndf_server* srv, uint64_t ticket, double timeout_s, double* latency_ms);
+
+/* Wait until every admitted request has completed. */
+pndf_status pndf_server_drain(pndf_server* srv);
+
+pndf_status pndf_server_get_stats(pndf_server* srv, pndf_server_stats* out);
+
+/* Clear the statistics (not the resident maps or plans). */
+pndf_status pndf_server_reset_stats(pndf_server* srv);
+
+/*
+ * Replay an arrival trace: request k (map map_ids[k], nq[k] queries at h_q[k],
+ * results to h_out[k]) is submitted arrival_s[k] seconds after the call starts
+ * (non-decreasing), retrying while it is refused; returns after every request has
+ * completed.  latency_ms[k] (may be NULL) receives each latency.
+ */
+pndf_status pndf_server_replay(pndf_server* srv, int64_t nreq, const int32_t* map_ids,
+                               const double* arrival_s, const pndf_query* const* h_q,
+                               const int64_t* nq, float* const* h_out, double* latency_ms);
+
+void pndf_server_destroy(pndf_server* srv);
 
 /* ---- introspection, for parity checks of the build steps ----------------- */
 

@@ -6,8 +6,8 @@ built (`python -m paper_2505_08985_amd.build`).
 """
 from .binding import (Mesh, Hierarchy, PndfError, build_mesh, build_hierarchy, eval_batch,
                       eval_counts, eval_hits, mesh_info, mesh_export, hier_info, hier_export_level,
-                      EXPORTED, LIB_PATH)
+                      EXPORTED, LIB_PATH, Plan, default_tuning, autotune, Server)
 
 __all__ = ["Mesh", "Hierarchy", "PndfError", "build_mesh", "build_hierarchy", "eval_batch",
            "eval_counts", "eval_hits", "mesh_info", "mesh_export", "hier_info",
-           "hier_export_level", "EXPORTED", "LIB_PATH"]
+           "hier_export_level", "EXPORTED", "LIB_PATH", "Plan", "default_tuning", "autotune", "Server"]

@@ -35,6 +35,17 @@ class HierOpts(ctypes.Structure):
     _fields_ = [("cluster", _i32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", _i32), ("split_level", _i32), ("queue_factor", _i32), ("use_graph", _i32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("spawned", _u64), ("refused", _u64), ("idle_spins", _u64), ("error", ctypes.c_uint32)]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -57,10 +68,20 @@ _mesh_export = _sig("pndf_mesh_export", _i32, [_vp, _vp, _vp, _vp])
 _hier_info = _sig("pndf_hier_info", _i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)])
 _hier_export = _sig("pndf_hier_export_level", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp])
 
+_default_tuning = _sig("pndf_default_tuning", _i32, [_vp, ctypes.POINTER(Tuning)])
+_plan_create = _sig("pndf_plan_create", _i32, [_vp, _i64, ctypes.POINTER(EvalOpts), ctypes.POINTER(Tuning), _vp,
+                                               ctypes.POINTER(_vp)])
+_plan_eval = _sig("pndf_plan_eval", _i32, [_vp, _vp, _i64, _vp, _vp])
+_plan_get_stats = _sig("pndf_plan_get_stats", _i32, [_vp, ctypes.POINTER(PlanStats), _vp])
+_plan_destroy = _sig("pndf_plan_destroy", None, [_vp])
+_autotune = _sig("pndf_autotune", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_double), _vp])
+
 EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_eval_counts",
             "pndf_eval_hits", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
             "pndf_last_error", "pndf_mesh_info", "pndf_mesh_export", "pndf_hier_info",
-            "pndf_hier_export_level"]
+            "pndf_hier_export_level", "pndf_default_tuning", "pndf_plan_create", "pndf_plan_eval",
+            "pndf_plan_get_stats", "pndf_plan_destroy", "pndf_autotune"]
 
 
 class PndfError(RuntimeError):
@@ -247,3 +268,167 @@ def hier_export_level(hier, level, stream=None):
     _check(_hier_export(hier.handle, int(level), _vp(bbox.data_ptr()), *ptrs, _stream(stream)),
            "pndf_hier_export_level")
     return dict(bbox=bbox, bbox_all=bbox_all, clu_n=clu_n, clu_e=clu_e, clu_det=clu_det)
+
+
+class Plan:
+    """Persistent work-stealing evaluation plan (workspace + instantiated HIP graph)."""
+
+    def __init__(self, hier, max_nq, tau=0.0, sigma_to_r=3.0, tuning=None, stream=None):
+        self.hier = hier  # the hierarchy must outlive the plan
+        self.max_nq = int(max_nq)
+        o = _opts(tau, sigma_to_r, "persistent")
+        t = None
+        if tuning is not None:
+            t = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
+        h = _vp()
+        _check(_plan_create(hier.handle, self.max_nq, ctypes.byref(o), ctypes.byref(t) if t is not None else None,
+                            _stream(stream), ctypes.byref(h)), "pndf_plan_create")
+        self._h = h
+
+    def eval(self, queries, out=None, stream=None):
+        qp, nq = _queries(queries)
+        if out is None:
+            out = torch.empty(nq, dtype=torch.float32, device=queries.device)
+        _check(_plan_eval(self._h, qp, nq, _dev_ptr(out, torch.float32, "out"), _stream(stream)),
+               "pndf_plan_eval")
+        return out
+
+    def stats(self, stream=None):
+        st = PlanStats()
+        _check(_plan_get_stats(self._h, ctypes.byref(st), _stream(stream)), "pndf_plan_get_stats")
+        return dict(spawned=int(st.spawned), refused=int(st.refused), idle_spins=int(st.idle_spins),
+                    error=int(st.error))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_tuning(hier):
+    t = Tuning()
+    _check(_default_tuning(hier.handle, ctypes.byref(t)), "pndf_default_tuning")
+    return t.as_dict()
+
+
+def autotune(hier, queries, tau=0.0, sigma_to_r=3.0, stream=None):
+    """Returns (best tuning dict, ms per batch of `queries`)."""
+    qp, nq = _queries(queries)
+    o = _opts(tau, sigma_to_r, "persistent")
+    t = Tuning()
+    ms = ctypes.c_double(0)
+    _check(_autotune(hier.handle, qp, nq, ctypes.byref(o), ctypes.byref(t), ctypes.byref(ms), _stream(stream)),
+           "pndf_autotune")
+    return t.as_dict(), float(ms.value)
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", _i32), ("max_batch_queries", _i64), ("memory_budget", _i64), ("max_pending", _i32),
+                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", _u64), ("refused", _u64), ("queries", _u64), ("batches", _u64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_batch_requests", ctypes.c_double), ("busy_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+_server_create = _sig("pndf_server_create", _i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(ServerOpts),
+                                                   ctypes.POINTER(_vp)])
+_server_submit = _sig("pndf_server_submit", _i32, [_vp, _i32, _vp, _i64, _vp, ctypes.POINTER(_u64)])
+_server_wait = _sig("pndf_server_wait", _i32, [_vp, _u64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)])
+_server_drain = _sig("pndf_server_drain", _i32, [_vp])
+_server_get_stats = _sig("pndf_server_get_stats", _i32, [_vp, ctypes.POINTER(ServerStats)])
+_server_reset_stats = _sig("pndf_server_reset_stats", _i32, [_vp])
+_server_replay = _sig("pndf_server_replay", _i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp])
+_server_destroy = _sig("pndf_server_destroy", None, [_vp])
+EXPORTED += ["pndf_server_create", "pndf_server_submit", "pndf_server_wait", "pndf_server_drain",
+             "pndf_server_get_stats", "pndf_server_reset_stats", "pndf_server_replay", "pndf_server_destroy"]
+
+
+class Server:
+    """Continuous-batching server over resident hierarchies (host-side requests)."""
+
+    def __init__(self, hiers, slots=2, max_batch_queries=1 << 16, memory_budget=None, max_pending=256,
+                 tau=0.0, sigma_to_r=3.0, tuning=None):
+        import numpy as np
+        self._np = np
+        self.hiers = list(hiers)  # keep the hierarchies alive
+        if memory_budget is None:
+            memory_budget = 28 * max_batch_queries * max(4, 2 * slots) + 4096
+        t = Tuning(0, 1, 16, 1) if tuning is None else (tuning if isinstance(tuning, Tuning) else Tuning(**tuning))
+        o = ServerOpts(int(slots), int(max_batch_queries), int(memory_budget), int(max_pending), float(tau),
+                       float(sigma_to_r), t)
+        arr = (_vp * len(self.hiers))(*[h.handle for h in self.hiers])
+        h = _vp()
+        _check(_server_create(arr, len(self.hiers), ctypes.byref(o), ctypes.byref(h)), "pndf_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, map_id, queries, out=None):
+        """queries: (Q, 6) float32 numpy array.  Returns (ticket, out array) or raises PndfError
+        (status PNDF_EAGAIN when not admitted)."""
+        np = self._np
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        if out is None:
+            out = np.empty(q.shape[0], dtype=np.float32)
+        t = _u64(0)
+        _check(_server_submit(self._h, int(map_id), q.ctypes.data_as(_vp), q.shape[0], out.ctypes.data_as(_vp),
+                              ctypes.byref(t)), "pndf_server_submit")
+        self._keep[int(t.value)] = (q, out)
+        return int(t.value), out
+
+    def wait(self, ticket, timeout=-1.0):
+        ms = ctypes.c_double(0)
+        _check(_server_wait(self._h, int(ticket), float(timeout), ctypes.byref(ms)), "pndf_server_wait")
+        self._keep.pop(int(ticket), None)
+        return float(ms.value)
+
+    def drain(self):
+        _check(_server_drain(self._h), "pndf_server_drain")
+
+    def stats(self):
+        st = ServerStats()
+        _check(_server_get_stats(self._h, ctypes.byref(st)), "pndf_server_get_stats")
+        return st.as_dict()
+
+    def reset_stats(self):
+        _check(_server_reset_stats(self._h), "pndf_server_reset_stats")
+
+    def replay(self, map_ids, arrivals, queries):
+        """Replay an arrival trace; returns (list of result arrays, latencies in ms)."""
+        np = self._np
+        n = len(queries)
+        qs = [np.ascontiguousarray(q, dtype=np.float32) for q in queries]
+        outs = [np.empty(q.shape[0], dtype=np.float32) for q in qs]
+        mids = np.ascontiguousarray(map_ids, dtype=np.int32)
+        arr = np.ascontiguousarray(arrivals, dtype=np.float64)
+        qp = (_vp * n)(*[q.ctypes.data for q in qs])
+        op = (_vp * n)(*[o.ctypes.data for o in outs])
+        nq = np.ascontiguousarray([q.shape[0] for q in qs], dtype=np.int64)
+        lat = np.zeros(n, dtype=np.float64)
+        _check(_server_replay(self._h, n, mids.ctypes.data_as(_vp), arr.ctypes.data_as(_vp), ctypes.cast(qp, _vp),
+                              nq.ctypes.data_as(_vp), ctypes.cast(op, _vp), lat.ctypes.data_as(_vp)),
+               "pndf_server_replay")
+        return outs, lat
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libpndf.so")
 
-SOURCES = ["api.cpp", "mesh.hip", "hier.hip", "eval.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "serve.cpp", "mesh.hip", "hier.hip", "eval.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -28,9 +28,7 @@ DEVICE = ["--offload-arch=gfx950", "-fno-fast-math", "-fno-gpu-flush-denormals-t
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
-    if src.endswith(".hip"):
-        cmd[1:1] = ["-x", "hip"] + DEVICE
+    cmd = [HIPCC, "-x", "hip"] + DEVICE + COMMON + ["-c", path, "-o", obj]
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in p.stdout.splitlines()
                     if "packed-fp32-ops' is not a recognized feature" not in l)

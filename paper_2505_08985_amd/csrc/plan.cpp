@@ -1,0 +1,219 @@
+// Host side of the persistent work-stealing evaluation: plans (workspace and
+// instantiated launch graph) and the autotuner that picks their shape.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pndf_internal.h"
+
+struct pndf_plan {
+    const pndf_hier* h = nullptr;
+    pndf_tuning tuning{};
+    pndf_eval_opts opts{};
+    pndf::PersistPlan P;
+};
+
+namespace pndf {
+
+static pndf_status plan_invalid(const char* msg)
+{
+    set_error(msg);
+    return PNDF_EINVAL;
+}
+
+static int compute_units()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+static void plan_free(pndf_plan* p)
+{
+    if (!p) return;
+    PersistPlan& P = p->P;
+    if (P.exec) (void)hipGraphExecDestroy(P.exec);
+    if (P.graph) (void)hipGraphDestroy(P.graph);
+    (void)hipFree(P.ctl);
+    (void)hipFree(P.acc);
+    (void)hipFree(P.fexp);
+    (void)hipFree(P.tasks);
+    (void)hipFree(P.flags);
+    delete p;
+}
+
+}  // namespace pndf
+
+using namespace pndf;
+
+extern "C" {
+
+pndf_status pndf_default_tuning(const pndf_hier* h, pndf_tuning* out)
+{
+    if (!h || !out) return plan_invalid("NULL argument");
+    out->blocks_per_cu = 2;
+    out->split_level = std::min(h->L, 5);
+    out->queue_factor = 16;
+    out->use_graph = 1;
+    return PNDF_OK;
+}
+
+pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval_opts* opts,
+                             const pndf_tuning* tuning, void* stream, pndf_plan** out)
+{
+    if (!out) return plan_invalid("out is NULL");
+    *out = nullptr;
+    if (!h) return plan_invalid("hierarchy is NULL");
+    if (max_nq < 1 || max_nq >= ((int64_t)1 << 32)) return plan_invalid("max_nq must be in [1, 2^32)");
+    pndf_eval_opts o{PNDF_KERNEL_GAUSSIAN, 0.f, 3.f, PNDF_ALGO_PERSISTENT, 0};
+    if (opts) o = *opts;
+    if (o.kernel != PNDF_KERNEL_GAUSSIAN) {
+        set_error("only the Gaussian footprint kernel is implemented");
+        return PNDF_EUNSUPPORTED;
+    }
+    if (!(std::isfinite(o.tau) && o.tau >= 0.f)) return plan_invalid("tau must be finite and >= 0");
+    if (!(std::isfinite(o.sigma_to_r) && o.sigma_to_r > 0.f)) return plan_invalid("sigma_to_r must be > 0");
+    if (o.flags != 0) return plan_invalid("flags must be 0");
+    if (o.tau > 0.f && !h->cluster) return plan_invalid("tau > 0 needs a hierarchy built with clusters");
+    pndf_tuning t;
+    pndf_default_tuning(h, &t);
+    if (tuning) t = *tuning;
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 64) return plan_invalid("blocks_per_cu out of range");
+    if (t.split_level < 1 || t.split_level > h->L) return plan_invalid("split_level out of range");
+    if (t.queue_factor < 1 || t.queue_factor > 1024) return plan_invalid("queue_factor out of range");
+    if (t.use_graph != 0 && t.use_graph != 1) return plan_invalid("use_graph must be 0 or 1");
+    pndf_plan* p = new (std::nothrow) pndf_plan;
+    if (!p) return PNDF_ENOMEM;
+    p->h = h;
+    p->tuning = t;
+    p->opts = o;
+    PersistPlan& P = p->P;
+    P.max_nq = max_nq;
+    P.capacity = (unsigned long long)max_nq * (unsigned long long)t.queue_factor;
+    P.blocks = compute_units() * t.blocks_per_cu;
+    P.split_level = t.split_level;
+    P.tau = o.tau;
+    P.s2r = o.sigma_to_r;
+    hipError_t e = hipMalloc(&P.ctl, sizeof(QueueCtl));
+    if (e == hipSuccess) e = hipMalloc(&P.acc, sizeof(Fix128) * (size_t)max_nq);
+    if (e == hipSuccess) e = hipMalloc(&P.fexp, sizeof(int) * (size_t)max_nq);
+    if (e == hipSuccess) e = hipMalloc(&P.tasks, sizeof(unsigned long long) * P.capacity);
+    if (e == hipSuccess) e = hipMalloc(&P.flags, sizeof(unsigned) * P.capacity);
+    // flags start at 0; the first run publishes with epoch 1
+    if (e == hipSuccess) e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * P.capacity, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemsetAsync(P.ctl, 0, sizeof(QueueCtl), (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess && t.use_graph) e = persist_graph_build(h->dev, P);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "pndf_plan_create");
+    }
+    if (!t.use_graph) {
+        P.H = h->dev;
+        P.pa.Q.ctl = P.ctl;
+        P.pa.Q.tasks = P.tasks;
+        P.pa.Q.flags = P.flags;
+        P.pa.Q.capacity = P.capacity;
+        P.pa.acc = P.acc;
+        P.pa.fexp = P.fexp;
+        P.pa.tau = P.tau;
+        P.pa.s2r = P.s2r;
+        P.pa.split_level = P.split_level;
+    }
+    *out = p;
+    return PNDF_OK;
+}
+
+pndf_status pndf_plan_eval(pndf_plan* plan, const pndf_query* d_q, int64_t nq, float* d_out,
+                           void* stream)
+{
+    if (!plan) return plan_invalid("plan is NULL");
+    if (nq < 0 || nq > plan->P.max_nq) return plan_invalid("nq out of range for this plan");
+    if (nq == 0) return PNDF_OK;
+    if (!d_q || !d_out) return plan_invalid("query or output pointer is NULL");
+    hipError_t e = hipPeekAtLastError();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return hip_fail(e, "earlier device error");
+    }
+    e = persist_run(plan->P, d_q, nq, d_out, plan->tuning.use_graph != 0, (hipStream_t)stream);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_plan_eval");
+}
+
+pndf_status pndf_plan_get_stats(pndf_plan* plan, pndf_plan_stats* out, void* stream)
+{
+    if (!plan || !out) return plan_invalid("NULL argument");
+    QueueCtl c;
+    hipError_t e = hipMemcpyAsync(&c, plan->P.ctl, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "pndf_plan_get_stats");
+    out->spawned = c.spawned;
+    out->refused = c.refused;
+    out->idle_spins = c.spins;
+    out->error = c.error;
+    return PNDF_OK;
+}
+
+void pndf_plan_destroy(pndf_plan* plan) { plan_free(plan); }
+
+pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                          const pndf_eval_opts* opts, pndf_tuning* best, double* best_ms,
+                          void* stream)
+{
+    if (!h || !best) return plan_invalid("NULL argument");
+    if (nq < 1 || !d_q) return plan_invalid("autotuning needs a non-empty query sample");
+    hipStream_t s = (hipStream_t)stream;
+    float* d_out = nullptr;
+    hipError_t e = hipMalloc(&d_out, sizeof(float) * (size_t)nq);
+    if (e != hipSuccess) return hip_fail(e, "pndf_autotune");
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best_t = 1e300;
+    pndf_tuning bt;
+    pndf_default_tuning(h, &bt);
+    pndf_status st = PNDF_OK;
+    const int lo = std::min(3, h->L), hi = std::min(8, h->L);
+    for (int bpc = 1; bpc <= 4 && st == PNDF_OK; ++bpc) {
+        for (int sl = lo; sl <= hi && st == PNDF_OK; ++sl) {
+            pndf_tuning t{bpc, sl, 16, 1};
+            pndf_plan* p = nullptr;
+            st = pndf_plan_create(h, nq, opts, &t, stream, &p);
+            if (st != PNDF_OK) break;
+            st = pndf_plan_eval(p, d_q, nq, d_out, stream);  // warm-up
+            float ms_best = 1e30f;
+            for (int r = 0; r < 3 && st == PNDF_OK; ++r) {
+                (void)hipEventRecord(e0, s);
+                st = pndf_plan_eval(p, d_q, nq, d_out, stream);
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) st = PNDF_EDEVICE;
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms_best = std::min(ms_best, ms);
+            }
+            pndf_plan_stats ps{};
+            if (st == PNDF_OK) st = pndf_plan_get_stats(p, &ps, stream);
+            pndf_plan_destroy(p);
+            if (st == PNDF_OK && ps.error) {
+                set_error("persistent workers reported an error during autotuning");
+                st = PNDF_EDEVICE;
+            }
+            if (st == PNDF_OK && ms_best < best_t) {
+                best_t = ms_best;
+                bt = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_out);
+    if (st != PNDF_OK) return st;
+    *best = bt;
+    if (best_ms) *best_ms = best_t;
+    return PNDF_OK;
+}
+
+}  // extern "C"

@@ -18,6 +18,9 @@ constexpr int kWave = 64;
 constexpr int kListCap = 256;    // per-level traversal list (64 parents x 4 children)
 constexpr int kCellCap = 320;    // leaf-cell queue: < 64 waiting + 256 pushed by one batch
 
+// 32-bit LDS words per wavefront of the descent: L node lists + the leaf queue.
+__host__ __device__ inline size_t wave_lds_words(int L) { return (size_t)L * kListCap + kCellCap; }
+
 // Device-side view of a mesh + hierarchy, passed to kernels by value.
 struct HierDev {
     const float2* nrm;      // (n+1) x (n+1) padded texel normals (last row/column wrap)
@@ -34,6 +37,75 @@ struct HierDev {
     float rho;              // circumradius of the clamp replacement triangle (area eps / 2)
     int64_t off[kMaxLevels + 2]; // first node of level l in the packed arrays (off[1] = 0)
 };
+
+// ---- exact accumulation: unsigned 128-bit fixed point, lo + 2^64 hi units of 2^fexp ----
+// Adding the float32 terms of a query in any order gives the same integer, so every
+// evaluation algorithm (brute force, descent, split across waves) returns the same D.
+struct Fix128 {
+    uint64_t lo, hi;
+};
+
+// Global task queue of the persistent traversal.  Slots are reserved by a CAS on
+// `tail` (never beyond capacity), written, then published by storing the launch's
+// epoch into the slot flag; takers claim slots below `tail` by a CAS on `head`
+// and wait for the flag.  `outstanding` counts queries and tasks taken but not
+// finished; a worker exits once every query is taken and nothing is outstanding.
+struct QueueCtl {
+    unsigned long long qhead;       // next query index
+    unsigned long long head, tail;  // task slots taken / reserved
+    unsigned long long outstanding;
+    unsigned long long spawned, refused, spins;  // statistics
+    unsigned int epoch, error;      // error bit0: idle wait gave up, bit1: slot wait gave up, bit2: bad task
+    const pndf_query* q;
+    float* out;
+    long long nq;
+};
+
+struct TaskQueue {
+    QueueCtl* ctl;
+    unsigned long long* tasks;  // (query << 32) | (level << 26) | (J << 13) | I
+    unsigned int* flags;        // epoch of the launch that published the slot
+    unsigned long long capacity;
+};
+
+struct PersistArgs {
+    TaskQueue Q;
+    Fix128* acc;     // per-query exact sums
+    int* fexp;       // per-query binary point (written by the query's root task)
+    float tau, s2r;
+    int split_level; // donate subtrees rooted at this level (>= 1)
+};
+
+// Device resources and the instantiated launch graph of a persistent plan.
+struct PersistPlan {
+    QueueCtl* ctl = nullptr;
+    Fix128* acc = nullptr;
+    int* fexp = nullptr;
+    unsigned long long* tasks = nullptr;
+    unsigned int* flags = nullptr;
+    unsigned long long capacity = 0;
+    long long max_nq = 0;
+    int blocks = 0, split_level = 1;
+    float tau = 0.f, s2r = 3.f;
+    unsigned epoch = 0;
+    HierDev H{};
+    PersistArgs pa{};
+    // graph and the argument storage its kernel nodes point to
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t reset_node = nullptr;
+    hipKernelNodeParams reset{};
+    const pndf_query* rq = nullptr;
+    long long rnq = 0;
+    float* rout = nullptr;
+    void* rargs[7];
+    void* wargs[2];
+    void* fargs[3];
+};
+
+hipError_t persist_graph_build(const HierDev& H, PersistPlan& P);
+hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float* out, bool use_graph,
+                       hipStream_t s);
 
 }  // namespace pndf
 
@@ -106,11 +178,13 @@ struct QuerySetup {
     float t;                     // cut threshold fl(fl(rx ry) tau)
     float kx, ky;                // log2(e) / (2 sigma^2)
     float norm;                  // 1 / (2 pi sx sy)
+    int fexp;                    // binary point of the exact accumulator (units of 2^fexp)
     bool valid;
 };
 
 // Support box, entry level and kernel constants of one query (see pndf.h).
-__device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float tau, int L)
+__device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float tau, int L,
+                                         float eps)
 {
     QuerySetup q;
     q.x = qr.x; q.y = qr.y; q.hx = qr.hx; q.hy = qr.hy;
@@ -123,6 +197,7 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     if (!ok) {
         q.cxlo = q.cylo = 0; q.cxhi = q.cyhi = -1; q.l0 = 0; q.t = -1.f;
         q.kx = q.ky = q.norm = 0.f;
+        q.fexp = 0;
         return q;
     }
     float lox = __fsub_rn(qr.x, rx), hix = __fadd_rn(qr.x, rx);
@@ -137,8 +212,58 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     const double log2e = 1.4426950408889634074;
     q.kx = (float)(log2e / (2.0 * (double)qr.sx * (double)qr.sx));
     q.ky = (float)(log2e / (2.0 * (double)qr.sy * (double)qr.sy));
-    q.norm = (float)(1.0 / (2.0 * 3.14159265358979323846 * (double)qr.sx * (double)qr.sy));
+    const double norm = 1.0 / (2.0 * 3.14159265358979323846 * (double)qr.sx * (double)qr.sy);
+    q.norm = (float)norm;
+    // Every term is at most norm / eps per included cell image and triangle (node
+    // images of a cluster reach at most one cell beyond the box per side), so
+    // D < bound = 2 (nx + 2) (ny + 2) norm / eps.  The exact accumulator counts in
+    // units of 2^fexp with bound < 2^(fexp + 126): 128 bits hold any D, and every
+    // float32 term is represented exactly down to 2^fexp.
+    const double bound = 2.0 * ((double)(q.cxhi - q.cxlo) + 3.0) * ((double)(q.cyhi - q.cylo) + 3.0) *
+                         norm / (double)eps;
+    int e2;
+    frexp(bound, &e2);
+    q.fexp = e2 + 1 - 126;
     return q;
+}
+
+__device__ __forceinline__ void fix_add_term(Fix128& a, float t, int fexp)
+{
+    const uint32_t b = __float_as_uint(t);
+    int ex = (int)((b >> 23) & 0xffu);
+    uint64_t m = b & 0x7fffffu;
+    if (ex) m |= 0x800000u; else ex = 1;
+    const int sh = ex - 150 - fexp;  // t = m 2^(ex - 150) = (m 2^sh) 2^fexp, sh <= 101
+    uint64_t vlo, vhi;
+    if (sh >= 64) {
+        vlo = 0;
+        vhi = m << (sh - 64);
+    } else if (sh > 0) {
+        vlo = m << sh;
+        vhi = m >> (64 - sh);
+    } else if (sh > -64) {
+        vlo = m >> (-sh);
+        vhi = 0;
+    } else {
+        vlo = 0;
+        vhi = 0;
+    }
+    const uint64_t lo = a.lo + vlo;
+    a.hi += vhi + (lo < vlo ? 1u : 0u);
+    a.lo = lo;
+}
+
+__device__ __forceinline__ void fix_add(Fix128& a, const Fix128& b)
+{
+    const uint64_t lo = a.lo + b.lo;
+    a.hi += b.hi + (lo < b.lo ? 1u : 0u);
+    a.lo = lo;
+}
+
+__device__ __forceinline__ float fix_to_float(const Fix128& a, int fexp)
+{
+    const double d = (double)a.hi * 18446744073709551616.0 + (double)a.lo;
+    return (float)ldexp(d, fexp);
 }
 
 // Does a node of side 2^lev starting at torus cell `start` have a periodic image
@@ -246,6 +371,17 @@ __device__ __forceinline__ int wave_prefix_small(int c, int* total)
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ Fix128 wave_sum_fix(Fix128 v)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        Fix128 w;
+        w.lo = __shfl_xor(v.lo, o, 64);
+        w.hi = __shfl_xor(v.hi, o, 64);
+        fix_add(v, w);
+    }
     return v;
 }
 
