@@ -178,6 +178,7 @@ def main():
     ap.add_argument("--queries", type=int, default=0, help="override the batch size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-octaves", action="store_true")
+    ap.add_argument("--input-order", action="store_true", help="keep the query order (no spatial ordering)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (continuous batching)")
     ap.add_argument("--serve-tau", type=float, default=1e-3)
     ap.add_argument("--serve-tiles", type=int, default=200)
@@ -233,15 +234,29 @@ def main():
     out = torch.empty(count, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    tuning = None
+    if args.algo == "persistent":
+        sample = tq[:min(count, 1 << 16)]
+        tuning, tms = P.autotune(hier, sample, tau=tau)
+        print("[bench] autotuned %s (%.3f ms on %d queries)" % (tuning, tms, sample.shape[0]),
+              file=sys.stderr, flush=True)
+        plan = P.Plan(hier, count, tau=tau, tuning=tuning)
+
+        def step():
+            plan.eval(tq, out=out)
+    else:
+        def step():
+            P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out, input_order=args.input_order)
+
     for _ in range(args.warmup):
-        P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out)
+        step()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out)
+        step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -252,8 +267,13 @@ def main():
     d = out.cpu().numpy()
     assert np.isfinite(d).all() and (d >= 0).all()
 
+    if args.algo == "persistent":
+        st = plan.stats()
+        assert st["error"] == 0, st
+        ref = P.eval_batch(hier, tq, tau=tau)
+        assert torch.equal(ref.view(torch.int32), out.view(torch.int32)), "persistent != plain"
     # instrumented launch: work units for the algorithmic byte count
-    _, counts = P.eval_counts(hier, tq, tau=tau, algo=args.algo)
+    _, counts = P.eval_counts(hier, tq, tau=tau, algo="brute" if args.algo == "brute" else "plain")
     counts = counts.cpu().numpy()
     abytes = algorithmic_bytes(counts, tau)
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
@@ -273,14 +293,15 @@ def main():
             if len(sel):
                 sq = tq[torch.from_numpy(sel).cuda()]
                 so = torch.empty(len(sel), dtype=torch.float32, device="cuda")
-                P.eval_batch(hier, sq, tau=tau, algo=args.algo, out=so)
+                oalgo = "plain" if args.algo == "persistent" else args.algo
+                P.eval_batch(hier, sq, tau=tau, algo=oalgo, out=so)
                 torch.cuda.synchronize()
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 reps = 3
                 for _ in range(reps):
-                    P.eval_batch(hier, sq, tau=tau, algo=args.algo, out=so)
+                    P.eval_batch(hier, sq, tau=tau, algo=oalgo, out=so)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 octaves["sigma %g-%g" % (a, b)] = len(sel) * reps / (e0.elapsed_time(e1) * 1e-3)
@@ -306,7 +327,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "map": "%s %dx%d" % (mc["kind"], n, n), "queries": count,
                    "sigma": list(qc["sigma"]) if isinstance(qc["sigma"], tuple) else qc["sigma"],
-                   "h_radius": qc["radius"], "tau": tau, "algo": args.algo, "sigma_to_r": 3.0},
+                   "h_radius": qc["radius"], "tau": tau, "algo": args.algo, "sigma_to_r": 3.0,
+                   "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,

@@ -82,8 +82,13 @@ typedef struct pndf_eval_opts {
                          * used as two cluster triangles when e^l <= fl(fl(r_x r_y) tau); 0 = exact */
     float sigma_to_r;   /* support half-width in standard deviations; the paper's Gaussian uses 3 */
     int32_t algo;       /* PNDF_ALGO_* */
-    int32_t flags;      /* reserved, must be 0 */
+    int32_t flags;      /* PNDF_EVAL_INPUT_ORDER or 0 */
 } pndf_eval_opts;
+
+/* Batches of 4096 or more queries are processed in a spatial order (Morton buckets
+ * of the footprint centres) for cache locality; results do not depend on the order.
+ * This flag keeps the caller's order instead. */
+enum { PNDF_EVAL_INPUT_ORDER = 1 };
 
 typedef struct pndf_hier_opts {
     int32_t cluster;    /* 1: fit the cluster hierarchy (needed for tau > 0); 0: min-max only */
@@ -177,7 +182,7 @@ const char* pndf_last_error(void);
  * four wavefronts) takes queries from a global counter; a query whose entry level
  * is above split_level descends to that level and donates the surviving subtrees
  * to a global task queue, from which idle workers steal.  Each query's terms are
- * summed exactly (128-bit fixed point), so the result is bit-identical to
+ * summed exactly (192-bit fixed point), so the result is bit-identical to
  * pndf_eval_batch whatever the split, the schedule or the batch composition.
  * The launch sequence (reset, workers, finalize) is instantiated once as a HIP
  * graph and replayed per batch.

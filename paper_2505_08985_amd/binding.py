@@ -175,8 +175,12 @@ def build_hierarchy(mesh, cluster=True, stream=None):
     return Hierarchy(out, mesh, bool(cluster))
 
 
-def _opts(tau, sigma_to_r, algo, kernel=0):
-    return EvalOpts(int(kernel), float(tau), float(sigma_to_r), ALGOS[algo] if isinstance(algo, str) else int(algo), 0)
+EVAL_INPUT_ORDER = 1
+
+
+def _opts(tau, sigma_to_r, algo, kernel=0, flags=0):
+    return EvalOpts(int(kernel), float(tau), float(sigma_to_r), ALGOS[algo] if isinstance(algo, str) else int(algo),
+                    int(flags))
 
 
 def _queries(q):
@@ -185,11 +189,12 @@ def _queries(q):
     return _dev_ptr(q, torch.float32, "queries"), int(q.shape[0])
 
 
-def eval_batch(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, stream=None, kernel=0):
+def eval_batch(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, stream=None, kernel=0,
+               input_order=False):
     qp, nq = _queries(queries)
     if out is None:
         out = torch.empty(nq, dtype=torch.float32, device=queries.device)
-    o = _opts(tau, sigma_to_r, algo, kernel)
+    o = _opts(tau, sigma_to_r, algo, kernel, EVAL_INPUT_ORDER if input_order else 0)
     _check(_eval_batch(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
                        _stream(stream)), "pndf_eval_batch")
     return out

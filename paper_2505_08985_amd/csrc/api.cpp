@@ -12,6 +12,10 @@ namespace pndf {
 
 static thread_local std::string g_last_error;
 
+// Batches at least this large are evaluated in spatial order (results do not depend
+// on the order; only cache locality does).
+constexpr int64_t kOrderMin = 4096;
+
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 pndf_status hip_fail(hipError_t e, const char* what)
@@ -57,6 +61,7 @@ static void fill_view(pndf_hier* h)
     d.clu_e = h->clu_e;
     d.clu_det = h->clu_det;
     d.clu_deg = h->clu_deg;
+    d.quad = h->quad;
     d.n = m->n;
     d.L = m->L;
     d.logn = m->L;
@@ -98,7 +103,7 @@ static pndf_status resolve_opts(const pndf_hier* h, const pndf_eval_opts* o, pnd
     if (!(std::isfinite(d.tau) && d.tau >= 0.f)) return invalid("tau must be finite and >= 0");
     if (!(std::isfinite(d.sigma_to_r) && d.sigma_to_r > 0.f))
         return invalid("sigma_to_r must be finite and > 0");
-    if (d.flags != 0) return invalid("flags must be 0");
+    if (d.flags & ~PNDF_EVAL_INPUT_ORDER) return invalid("unknown flags");
     if (d.algo < PNDF_ALGO_AUTO || d.algo > PNDF_ALGO_PERSISTENT) return invalid("unknown algo");
     if (d.algo == PNDF_ALGO_PERSISTENT) {
         set_error("use pndf_eval_persistent for the persistent traversal");
@@ -223,6 +228,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
     for (int l = 1; l <= m->L; ++l) nodes += (int64_t)(m->n >> l) * (m->n >> l);
     h->nodes = nodes;
     hipError_t e = hipMalloc(&h->bbox, sizeof(float4) * nodes);
+    if (e == hipSuccess) e = hipMalloc(&h->quad, sizeof(QuadRec) * (size_t)(m->n >> 1) * (size_t)(m->n >> 1));
     if (cluster) {
         if (e == hipSuccess) e = hipMalloc(&h->bbox_all, sizeof(float4) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_n, sizeof(float4) * 2 * nodes);
@@ -236,7 +242,8 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + (cluster ? 16 + 32 + 4 + 8 + 1 : 0));
+    h->bytes = (int64_t)nodes * (16 + (cluster ? 16 + 32 + 4 + 8 + 1 : 0)) +
+               (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
 }
@@ -245,6 +252,7 @@ void pndf_destroy_hierarchy(pndf_hier* h)
 {
     if (!h) return;
     (void)hipFree(h->bbox);
+    (void)hipFree(h->quad);
     (void)hipFree(h->bbox_all);
     (void)hipFree(h->clu_n);
     (void)hipFree(h->clu_e);
@@ -275,15 +283,17 @@ pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_b
     const int64_t off = h->dev.off[level];
     const size_t m = (size_t)(h->mesh->n >> level) * (h->mesh->n >> level);
     hipError_t e = hipSuccess;
-    auto cp = [&](void* dst, const void* src, size_t bytes) {
-        if (dst && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    const int side = h->mesh->n >> level;
+    (void)m;
+    auto cp = [&](void* dst, const void* src, int words) {
+        if (dst && e == hipSuccess) e = export_rowmajor(src, dst, side, words, s);
     };
-    cp(d_bbox, h->bbox + off, sizeof(float4) * m);
+    cp(d_bbox, h->bbox + off, 4);
     if (h->cluster) {
-        cp(d_bbox_all, h->bbox_all + off, sizeof(float4) * m);
-        cp(d_clu_n, h->clu_n + 2 * off, sizeof(float4) * 2 * m);
-        cp(d_clu_e, h->clu_e + off, sizeof(float) * m);
-        cp(d_clu_det, h->clu_det + off, sizeof(float2) * m);
+        cp(d_bbox_all, h->bbox_all + off, 4);
+        cp(d_clu_n, h->clu_n + 2 * off, 8);
+        cp(d_clu_e, h->clu_e + off, 1);
+        cp(d_clu_det, h->clu_det + off, 2);
     }
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_hier_export_level");
 }
@@ -306,8 +316,14 @@ pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t n
     pndf_eval_opts o;
     pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
     if (st != PNDF_OK) return st;
-    EvalArgs a{d_q, nq, d_out, nullptr, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
-    hipError_t e = launch_eval(h->dev, a, o.algo, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* order = nullptr;
+    hipError_t e = hipSuccess;
+    if (nq >= kOrderMin && o.algo != PNDF_ALGO_BRUTE && !(o.flags & PNDF_EVAL_INPUT_ORDER))
+        e = make_order(h->dev, d_q, nq, &order, s);
+    EvalArgs a{d_q, order, nq, 0, 0, d_out, nullptr, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    if (e == hipSuccess) e = launch_eval(h->dev, a, o.algo, s);
+    free_order(order, s);
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_batch");
 }
 
@@ -319,7 +335,7 @@ pndf_status pndf_eval_counts(const pndf_hier* h, const pndf_query* d_q, int64_t 
     pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
     if (st != PNDF_OK) return st;
     if (nq > 0 && !d_counts) return invalid("counts pointer is NULL");
-    EvalArgs a{d_q, nq, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    EvalArgs a{d_q, nullptr, nq, 0, 0, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
     hipError_t e = launch_eval(h->dev, a, o.algo, (hipStream_t)stream);
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_counts");
 }
@@ -341,7 +357,7 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
     uint32_t* d_counts = nullptr;
     hipError_t e = hipMalloc(&d_counts, sizeof(uint32_t) * 4 * (size_t)nq);
     if (e != hipSuccess) return hip_fail(e, "pndf_eval_hits");
-    EvalArgs a{d_q, nq, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    EvalArgs a{d_q, nullptr, nq, 0, 0, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
     e = launch_eval(h->dev, a, o.algo, s);
     std::vector<uint32_t> counts((size_t)nq * 4);
     if (e == hipSuccess)
@@ -353,7 +369,7 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
         e = hipMemcpyAsync(d_offsets, offs.data(), sizeof(uint64_t) * (nq + 1), hipMemcpyHostToDevice, s);
     *required = offs[nq];
     if (e == hipSuccess && offs[nq] <= capacity && offs[nq] > 0) {
-        EvalArgs b{d_q, nq, d_out, nullptr, d_offsets, d_ids, d_terms, o.tau, o.sigma_to_r};
+        EvalArgs b{d_q, nullptr, nq, 0, 0, d_out, nullptr, d_offsets, d_ids, d_terms, o.tau, o.sigma_to_r};
         e = launch_eval(h->dev, b, o.algo, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

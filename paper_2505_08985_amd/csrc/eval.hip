@@ -15,7 +15,7 @@
 // Triangle tests run in float32; a float32 hit is confirmed and its barycentrics
 // recomputed in FP64 from the float32 vertices, so the recovered uv and the term
 // are accurate even for sliver triangles.  Jacobians come from the mesh build
-// (FP64, clamped), never from the hot loop.  Terms are summed exactly (128-bit
+// (FP64, clamped), never from the hot loop.  Terms are summed exactly (192-bit
 // fixed point at a per-query binary point), so D does not depend on the order in
 // which hits are found: all algorithms, batch compositions and work splits give
 // the same bits.
@@ -30,7 +30,7 @@ namespace {
 enum { kModeValue = 0, kModeCount = 1, kModeRecord = 2 };
 
 struct Acc {
-    Fix128 d{0, 0};
+    Fix192 d{0, 0, 0};
     uint32_t nodes = 0, cells = 0, clusters = 0, hits = 0;
 };
 
@@ -41,23 +41,71 @@ struct Rec {  // hit-record cursor (record mode)
 };
 
 // FP64 confirmation of a float32 hit, barycentrics and term; < 0 if rejected.
-__device__ __forceinline__ float confirm_and_term(const QuerySetup& q, const double v[6], int I,
-                                                  int J, int lev, int half, float det_used,
-                                                  int logn)
+__device__ __forceinline__ double confirm_and_term(const QuerySetup& q, const double v[6], int I,
+                                                   int J, int lev, int half, float det_used,
+                                                   int logn)
 {
     double l1, l2;
-    if (!tri_bary_f64(v, (double)q.hx, (double)q.hy, &l1, &l2)) return -1.f;
+    if (!tri_bary_f64(v, (double)q.hx, (double)q.hy, &l1, &l2)) return -1.0;
     return hit_term(q, I, J, lev, half, l1, l2, det_used, logn);
 }
 
-// Test the two triangles of texel cell (i, j).  Writes up to two (id, term) pairs.
-__device__ __forceinline__ int test_cell(const HierDev& H, const QuerySetup& q, int i, int j,
-                                         uint64_t ids[2], float terms[2])
+// Per-lane hit sink: value/count modes add the term to the exact accumulator at
+// once; record mode also buffers (id, term) until the wave writes its records in
+// lane order.
+template <int MODE>
+struct HitSink {
+    static constexpr int kMax = MODE == kModeRecord ? 8 : 1;
+    uint64_t ids[kMax];
+    float terms[kMax];
+    int n = 0;
+    __device__ __forceinline__ void put(const QuerySetup& q, Acc& acc, uint64_t id, double t)
+    {
+        fix_add_term(acc.d, t, q.fexp);
+        acc.hits += 1;
+        if (MODE == kModeRecord && n < kMax) {
+            ids[n] = id;
+            terms[n] = (float)t;
+        }
+        ++n;
+    }
+};
+
+// Exclusive prefix over the wave of a per-lane count in [0, 15], and the total.
+__device__ __forceinline__ int wave_prefix16(int c, int* total)
 {
-    const int w = H.n + 1;
-    const float2* p = H.nrm + (int64_t)j * w + i;
-    const float2 n0 = p[0], n1 = p[1], n2 = p[w], n3 = p[w + 1];
-    const uint8_t dg = H.deg[(int64_t)j * H.n + i];
+    const uint64_t b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4), b3 = __ballot(c & 8);
+    const uint64_t lt = (1ull << lane_id()) - 1ull;
+    *total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2) + 8 * __popcll(b3);
+    return __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt) + 8 * __popcll(b3 & lt);
+}
+
+// Write the wave's buffered records in lane order, never leaving the query's own
+// CSR slot [pos, end).  Every lane must call it.
+template <int MODE>
+__device__ __forceinline__ void flush_records(HitSink<MODE>& hs, Rec& rec)
+{
+    if (MODE == kModeRecord) {
+        int total;
+        const int pos = wave_prefix16(hs.n, &total);
+        for (int k = 0; k < hs.n && k < HitSink<MODE>::kMax; ++k) {
+            const uint64_t at = rec.pos + pos + k;
+            if (at < rec.end) {
+                rec.ids[at] = hs.ids[k];
+                rec.terms[at] = hs.terms[k];
+            }
+        }
+        rec.pos += total;
+    }
+    hs.n = 0;
+}
+
+// The two triangles of one cell from its four corner normals and clamp bits.
+template <int MODE>
+__device__ __forceinline__ void cell_triangles(const HierDev& H, const QuerySetup& q, int i, int j,
+                                               float2 n0, float2 n1, float2 n2, float2 n3, uint8_t dg,
+                                               Acc& acc, HitSink<MODE>& hs)
+{
     bool hl, hu;
     float vl[6], vu[6];
     if (dg == 0) {
@@ -71,7 +119,7 @@ __device__ __forceinline__ int test_cell(const HierDev& H, const QuerySetup& q, 
         const float c32 = cross2(q3x, q3y, q2x, q2y);
         hl = (c12 >= 0.f && c20 >= 0.f && c01 >= 0.f) || (c12 <= 0.f && c20 <= 0.f && c01 <= 0.f);
         hu = (c12 <= 0.f && c13 >= 0.f && c32 >= 0.f) || (c12 >= 0.f && c13 <= 0.f && c32 <= 0.f);
-        if (!(hl || hu)) return 0;
+        if (!(hl || hu)) return;
         vl[0] = n0.x; vl[1] = n0.y; vl[2] = n1.x; vl[3] = n1.y; vl[4] = n2.x; vl[5] = n2.y;
         vu[0] = n3.x; vu[1] = n3.y; vu[2] = n2.x; vu[3] = n2.y; vu[4] = n1.x; vu[5] = n1.y;
     } else {
@@ -82,9 +130,8 @@ __device__ __forceinline__ int test_cell(const HierDev& H, const QuerySetup& q, 
         else { vu[0] = n3.x; vu[1] = n3.y; vu[2] = n2.x; vu[3] = n2.y; vu[4] = n1.x; vu[5] = n1.y; }
         hl = tri_hit_f32(vl, q.hx, q.hy);
         hu = tri_hit_f32(vu, q.hx, q.hy);
-        if (!(hl || hu)) return 0;
+        if (!(hl || hu)) return;
     }
-    int nh = 0;
     const float2 dd = H.det[(int64_t)j * H.n + i];
     for (int half = 0; half < 2; ++half) {
         if (!(half ? hu : hl)) continue;
@@ -96,19 +143,52 @@ __device__ __forceinline__ int test_cell(const HierDev& H, const QuerySetup& q, 
             const float* f = half ? vu : vl;
             for (int k = 0; k < 6; ++k) v[k] = (double)f[k];
         }
-        const float t = confirm_and_term(q, v, i, j, 0, half, half ? dd.y : dd.x, H.logn);
-        if (t >= 0.f) {
-            ids[nh] = tri_id(0, i, j, half);
-            terms[nh] = t;
-            ++nh;
-        }
+        const double t = confirm_and_term(q, v, i, j, 0, half, half ? dd.y : dd.x, H.logn);
+        if (t >= 0.0) hs.put(q, acc, tri_id(0, i, j, half), t);
     }
-    return nh;
 }
 
-// Test the two cluster triangles of node (lev, I, J) with packed index idx.
-__device__ __forceinline__ int test_cluster(const HierDev& H, const QuerySetup& q, int lev, int I,
-                                            int J, int64_t idx, uint64_t ids[2], float terms[2])
+// A texel cell tested from the padded normal plane (brute force, tiny footprints).
+template <int MODE>
+__device__ __forceinline__ void plane_cell(const HierDev& H, const QuerySetup& q, int i, int j, Acc& acc,
+                                           HitSink<MODE>& hs)
+{
+    const int w = H.n + 1;
+    const float2* p = H.nrm + (int64_t)j * w + i;
+    cell_triangles<MODE>(H, q, i, j, p[0], p[1], p[w], p[w + 1], H.deg[(int64_t)j * H.n + i], acc, hs);
+    acc.cells += 1;
+}
+
+// The 2 x 2 cells of level-1 node (I, J) (leaf record m), those overlapping the box.
+template <int MODE>
+__device__ __forceinline__ void leaf_quad(const HierDev& H, const QuerySetup& q, int I, int J, uint32_t m,
+                                          Acc& acc, HitSink<MODE>& hs)
+{
+    const float4* r = reinterpret_cast<const float4*>(H.quad + m);
+    const float4 a = r[0], b = r[1], c = r[2], d = r[3], e = r[4];
+    const float2 t[9] = {make_float2(a.x, a.y), make_float2(a.z, a.w), make_float2(b.x, b.y),
+                         make_float2(b.z, b.w), make_float2(c.x, c.y), make_float2(c.z, c.w),
+                         make_float2(d.x, d.y), make_float2(d.z, d.w), make_float2(e.x, e.y)};
+    const uint32_t dg4 = __float_as_uint(e.z);
+    const int logn = H.logn;
+    const bool x0 = axis_overlap(2 * I, 1, q.cxlo, q.cxhi, logn);
+    const bool x1 = axis_overlap(2 * I + 1, 1, q.cxlo, q.cxhi, logn);
+    const bool y0 = axis_overlap(2 * J, 1, q.cylo, q.cyhi, logn);
+    const bool y1 = axis_overlap(2 * J + 1, 1, q.cylo, q.cyhi, logn);
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+        const int di = c4 & 1, dj = c4 >> 1;
+        if (!((di ? x1 : x0) && (dj ? y1 : y0))) continue;
+        acc.cells += 1;
+        cell_triangles<MODE>(H, q, 2 * I + di, 2 * J + dj, t[3 * dj + di], t[3 * dj + di + 1],
+                             t[3 * dj + di + 3], t[3 * dj + di + 4], (uint8_t)(dg4 >> (8 * c4)), acc, hs);
+    }
+}
+
+// The two cluster triangles of node (lev, I, J) with packed index idx.
+template <int MODE>
+__device__ __forceinline__ void cluster_pair(const HierDev& H, const QuerySetup& q, int lev, int I, int J,
+                                             int64_t idx, Acc& acc, HitSink<MODE>& hs)
 {
     const float4 a = H.clu_n[2 * idx], b = H.clu_n[2 * idx + 1];
     const uint8_t dg = H.clu_deg[idx];
@@ -120,45 +200,17 @@ __device__ __forceinline__ int test_cluster(const HierDev& H, const QuerySetup& 
     else { vl[0] = a.x; vl[1] = a.y; vl[2] = a.z; vl[3] = a.w; vl[4] = b.x; vl[5] = b.y; }
     if (dg & 2) eqtri_f32(cx, cy, rho, vu);
     else { vu[0] = b.z; vu[1] = b.w; vu[2] = b.x; vu[3] = b.y; vu[4] = a.z; vu[5] = a.w; }
-    int nh = 0;
+    acc.clusters += 1;
     for (int half = 0; half < 2; ++half) {
         const float* f = half ? vu : vl;
         if (!tri_hit_f32(f, q.hx, q.hy)) continue;
         double v[6];
         if (dg & (1 << half))
-            eqtri_f64(0.5 * ((double)a.z + (double)b.x), 0.5 * ((double)a.w + (double)b.y),
-                      (double)rho, v);
+            eqtri_f64(0.5 * ((double)a.z + (double)b.x), 0.5 * ((double)a.w + (double)b.y), (double)rho, v);
         else
             for (int k = 0; k < 6; ++k) v[k] = (double)f[k];
-        const float t = confirm_and_term(q, v, I, J, lev, half, half ? dd.y : dd.x, H.logn);
-        if (t >= 0.f) {
-            ids[nh] = tri_id(lev, I, J, half);
-            terms[nh] = t;
-            ++nh;
-        }
-    }
-    return nh;
-}
-
-// Accumulate this lane's hits; in record mode write them in deterministic order,
-// never leaving the query's own CSR slot [pos, end).
-template <int MODE>
-__device__ __forceinline__ void take_hits(const QuerySetup& q, int nh, const uint64_t ids[2],
-                                          const float terms[2], Acc& acc, Rec& rec)
-{
-    for (int k = 0; k < nh; ++k) fix_add_term(acc.d, terms[k], q.fexp);
-    acc.hits += nh;
-    if (MODE == kModeRecord) {
-        int total;
-        const int pos = wave_prefix_small(nh, &total);
-        for (int k = 0; k < nh; ++k) {
-            const uint64_t at = rec.pos + pos + k;
-            if (at < rec.end) {
-                rec.ids[at] = ids[k];
-                rec.terms[at] = terms[k];
-            }
-        }
-        rec.pos += total;
+        const double t = confirm_and_term(q, v, I, J, lev, half, half ? dd.y : dd.x, H.logn);
+        if (t >= 0.0) hs.put(q, acc, tri_id(lev, I, J, half), t);
     }
 }
 
@@ -174,53 +226,52 @@ __device__ __forceinline__ unsigned long long queue_reserve(const TaskQueue& Q, 
     }
 }
 
-// The shared descent.  Roots: every lane with root_ok holds a root item of level
-// root_level (level 0: texel cells).  With SPAWN, a node of level split_level that
-// passes its tests is donated to the task queue instead of being descended (when
-// the queue has room; otherwise it is descended here).
+__device__ __forceinline__ bool in_box(const QuerySetup& q, const float4& bb)
+{
+    return q.hx >= bb.x && q.hy >= bb.y && q.hx <= bb.z && q.hy <= bb.w;
+}
+
+// The shared descent.  List items are nodes (Morton codes) whose box contains h
+// and whose region meets the support box.  A lane takes one item: a node under the
+// cut answers with its cluster triangles; a level-1 node tests its 2 x 2 cells from
+// its leaf record; any other node loads its (up to) four overlapping children's
+// boxes together and pushes those that contain h.  Roots: every lane with root_ok
+// holds a root of level root_level (level 0: texel cell packed i | j << 16; else a
+// Morton code), box-tested here unless roots_tested.  With SPAWN, a node of level
+// split_level is donated to the task queue instead of expanded (when the queue has
+// room; otherwise it is expanded here).
 template <int MODE, bool CUT, bool SPAWN>
-__device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, uint32_t* cellq,
-                        int root_level, bool root_ok, uint32_t root_item, int split_level,
+__device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, int root_level,
+                        bool root_ok, uint32_t root_item, bool roots_tested, int split_level,
                         unsigned long long qidx, const TaskQueue& Q, Acc& acc, Rec& rec)
 {
+    static_assert(!SPAWN || MODE == kModeValue, "donation is only used by value-mode workers");
     const int lane = threadIdx.x & 63;
     const int logn = H.logn;
     const float4* __restrict__ boxes = CUT ? H.bbox_all : H.bbox;
+    HitSink<MODE> hs;
+    if (root_level == 0) {
+        if (root_ok) plane_cell<MODE>(H, q, (int)(root_item & 0xffffu), (int)(root_item >> 16), acc, hs);
+        flush_records<MODE>(hs, rec);
+        return;
+    }
     uint32_t nonempty = 0;   // bit l: list of level l non-empty (wave-uniform)
     int cntv = 0;            // lane l holds the size of list l
-    int ncell = 0;
     {
-        const bool ok = root_ok;
+        bool ok = root_ok;
+        if (ok && !roots_tested) {
+            acc.nodes += 1;
+            ok = in_box(q, boxes[H.off[root_level] + root_item]);
+        }
         const uint64_t bal = __ballot(ok);
         const int pos = __popcll(bal & ((1ull << lane) - 1ull));
         const int tot = __popcll(bal);
-        if (root_level == 0) {
-            if (ok) cellq[pos] = root_item;
-            ncell = tot;
-        } else {
-            if (ok) lists[(root_level - 1) * kListCap + pos] = root_item;
-            if (lane == root_level) cntv = tot;
-            if (tot) nonempty |= 1u << root_level;
-        }
+        if (ok) lists[(root_level - 1) * kListCap + pos] = root_item;
+        if (lane == root_level) cntv = tot;
+        if (tot) nonempty |= 1u << root_level;
         wave_sync();
     }
-    while (true) {
-        if (ncell >= 64 || (nonempty == 0 && ncell > 0)) {
-            const int k = min(ncell, 64), base = ncell - k;
-            int nh = 0;
-            uint64_t ids[2];
-            float terms[2];
-            if (lane < k) {
-                const uint32_t c = cellq[base + lane];
-                nh = test_cell(H, q, (int)(c & 0xffffu), (int)(c >> 16), ids, terms);
-                acc.cells += 1;
-            }
-            ncell = base;
-            take_hits<MODE>(q, nh, ids, terms, acc, rec);
-            wave_sync();
-            continue;
-        }
-        if (nonempty == 0) break;
+    while (nonempty) {
         const int l = __builtin_ctz(nonempty);
         const int cnt = __builtin_amdgcn_readlane(cntv, l);
         const int k = min(cnt, 64), base = cnt - k;
@@ -228,38 +279,37 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         if (base == 0) nonempty &= ~(1u << l);
         uint32_t ch[4];
         int nch = 0;
-        int nh = 0;
         bool give = false;
-        uint32_t item = 0;
-        uint64_t ids[2];
-        float terms[2];
+        uint32_t m = 0;
         if (lane < k) {
-            item = lists[(l - 1) * kListCap + base + lane];
-            const int I = (int)(item & 0xffffu), J = (int)(item >> 16);
-            const int64_t idx = H.off[l] + (int64_t)J * (H.n >> l) + I;
-            const float4 bb = boxes[idx];
-            acc.nodes += 1;
-            if (q.hx >= bb.x && q.hy >= bb.y && q.hx <= bb.z && q.hy <= bb.w) {
-                if (CUT && l <= q.l0 && H.clu_e[idx] <= q.t) {
-                    nh = test_cluster(H, q, l, I, J, idx, ids, terms);
-                    acc.clusters += 1;
-                } else if (SPAWN && l == split_level) {
-                    give = true;
-                } else {
-                    const int side = 1 << (l - 1);
-                    const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
-                    const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
-                    const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
-                    const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
-                    const uint32_t ci = 2u * I, cj = 2u * J;
-                    if (x0 && y0) ch[nch++] = ci | (cj << 16);
-                    if (x1 && y0) ch[nch++] = (ci + 1) | (cj << 16);
-                    if (x0 && y1) ch[nch++] = ci | ((cj + 1) << 16);
-                    if (x1 && y1) ch[nch++] = (ci + 1) | ((cj + 1) << 16);
-                }
+            m = lists[(l - 1) * kListCap + base + lane];
+            const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
+            const int64_t idx = H.off[l] + m;
+            if (CUT && l <= q.l0 && H.clu_e[idx] <= q.t) {
+                cluster_pair<MODE>(H, q, l, I, J, idx, acc, hs);
+            } else if (SPAWN && l == split_level) {
+                give = true;
+            } else if (l == 1) {
+                leaf_quad<MODE>(H, q, I, J, m, acc, hs);
+            } else {
+                const int side = 1 << (l - 1);
+                const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
+                const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
+                const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
+                const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
+                const float4* cb = boxes + H.off[l - 1] + 4 * (int64_t)m;
+                float4 b0 = make_float4(1.f, 1.f, -1.f, -1.f), b1 = b0, b2 = b0, b3 = b0;
+                if (x0 && y0) b0 = cb[0];
+                if (x1 && y0) b1 = cb[1];
+                if (x0 && y1) b2 = cb[2];
+                if (x1 && y1) b3 = cb[3];
+                acc.nodes += (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
+                if (in_box(q, b0)) ch[nch++] = 4 * m;
+                if (in_box(q, b1)) ch[nch++] = 4 * m + 1;
+                if (in_box(q, b2)) ch[nch++] = 4 * m + 2;
+                if (in_box(q, b3)) ch[nch++] = 4 * m + 3;
             }
         }
-        if (CUT) take_hits<MODE>(q, nh, ids, terms, acc, rec);
         if (SPAWN) {
             const uint64_t gb = __ballot(give);
             if (gb) {
@@ -267,8 +317,8 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 unsigned long long slot = 0;
                 if (lane == 0) {
                     // count the tasks before they become visible, then reserve
-                    __hip_atomic_fetch_add(&Q.ctl->outstanding, (unsigned long long)total,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&Q.ctl->outstanding, (unsigned long long)total, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                     slot = queue_reserve(Q, total);
                     if (slot == ~0ull) {
                         __hip_atomic_fetch_add(&Q.ctl->outstanding, (unsigned long long)(-(long long)total),
@@ -282,34 +332,35 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 if (slot != ~0ull) {
                     if (give) {
                         const unsigned long long at = slot + __popcll(gb & ((1ull << lane) - 1ull));
-                        Q.tasks[at] = (qidx << 32) | ((unsigned long long)l << 26) |
-                                      ((unsigned long long)(item >> 16) << 13) | (item & 0xffffu);
+                        Q.tasks[at] = (qidx << 32) | ((unsigned long long)l << 26) | (unsigned long long)m;
                         __threadfence();
-                        __hip_atomic_store(&Q.flags[at], Q.ctl->epoch, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&Q.flags[at], Q.ctl->epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 } else if (give) {
-                    // queue full: descend this subtree here
-                    const int I = (int)(item & 0xffffu), J = (int)(item >> 16);
-                    const int side = 1 << (l - 1);
-                    const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
-                    const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
-                    const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
-                    const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
-                    const uint32_t ci = 2u * I, cj = 2u * J;
-                    if (x0 && y0) ch[nch++] = ci | (cj << 16);
-                    if (x1 && y0) ch[nch++] = (ci + 1) | (cj << 16);
-                    if (x0 && y1) ch[nch++] = ci | ((cj + 1) << 16);
-                    if (x1 && y1) ch[nch++] = (ci + 1) | ((cj + 1) << 16);
+                    // queue full: handle this node here like any other list item
+                    const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
+                    if (l == 1) {
+                        leaf_quad<MODE>(H, q, I, J, m, acc, hs);
+                    } else {
+                        const int side = 1 << (l - 1);
+                        const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
+                        const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
+                        const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
+                        const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
+                        const float4* cb = boxes + H.off[l - 1] + 4 * (int64_t)m;
+                        acc.nodes += (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
+                        if (x0 && y0 && in_box(q, cb[0])) ch[nch++] = 4 * m;
+                        if (x1 && y0 && in_box(q, cb[1])) ch[nch++] = 4 * m + 1;
+                        if (x0 && y1 && in_box(q, cb[2])) ch[nch++] = 4 * m + 2;
+                        if (x1 && y1 && in_box(q, cb[3])) ch[nch++] = 4 * m + 3;
+                    }
                 }
             }
         }
-        int total;
-        const int pos = wave_prefix_small(nch, &total);
-        if (l == 1) {
-            for (int c = 0; c < nch; ++c) cellq[ncell + pos + c] = ch[c];
-            ncell += total;
-        } else {
+        flush_records<MODE>(hs, rec);
+        if (l >= 2) {
+            int total;
+            const int pos = wave_prefix_small(nch, &total);
             uint32_t* dst = lists + (l - 2) * kListCap;
             for (int c = 0; c < nch; ++c) dst[pos + c] = ch[c];
             if (lane == l - 1) cntv = total;
@@ -320,7 +371,8 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 }
 
 // Root items of a query: the entry-level nodes overlapping the box (<= 4 per
-// axis), one per lane of lanes 0..15 where *ok is set.
+// axis), one per lane of lanes 0..15 where *ok is set; Morton codes (level >= 1)
+// or packed texel cells (entry level 0).
 __device__ __forceinline__ uint32_t root_item(const HierDev& H, const QuerySetup& q, bool* ok)
 {
     const int lane = threadIdx.x & 63;
@@ -329,14 +381,15 @@ __device__ __forceinline__ uint32_t root_item(const HierDev& H, const QuerySetup
     const int nkx = min((q.cxhi >> l0) - kx0 + 1, M), nky = min((q.cyhi >> l0) - ky0 + 1, M);
     const int ra = lane & 3, rb = lane >> 2;
     *ok = lane < 16 && ra < nkx && rb < nky;
-    return (uint32_t)((kx0 + ra) & mm) | ((uint32_t)((ky0 + rb) & mm) << 16);
+    const uint32_t I = (uint32_t)((kx0 + ra) & mm), J = (uint32_t)((ky0 + rb) & mm);
+    return l0 == 0 ? (I | (J << 16)) : morton(I, J);
 }
 
 template <int MODE>
 __device__ __forceinline__ void finish(const EvalArgs& a, int64_t qi, const QuerySetup& q,
                                        const Acc& acc)
 {
-    const Fix128 d = wave_sum_fix(acc.d);
+    const Fix192 d = wave_sum_fix(acc.d);
     if (MODE == kModeCount) {
         const uint32_t nodes = wave_sum_u32(acc.nodes), cells = wave_sum_u32(acc.cells);
         const uint32_t clus = wave_sum_u32(acc.clusters), hits = wave_sum_u32(acc.hits);
@@ -364,8 +417,9 @@ __device__ __forceinline__ void invalid(const EvalArgs& a, int64_t qi)
 template <int MODE>
 __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
 {
-    const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (qi >= a.nq) return;
+    const int64_t local = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (local >= a.slots) return;
+    const int64_t qi = a.slot0 + local;
     const int lane = threadIdx.x & 63;
     const QuerySetup q = setup_query(a.q[qi], a.s2r, 0.f, H.L, H.eps);
     if (!q.valid) { invalid<MODE>(a, qi); return; }
@@ -376,35 +430,33 @@ __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
     Acc acc;
     Rec rec{a.ids, a.terms, MODE == kModeRecord ? a.offsets[qi] : 0,
             MODE == kModeRecord ? a.offsets[qi + 1] : 0};
+    HitSink<MODE> hs;
     for (int base = 0; base < total; base += 64) {
         const int idx = base + lane;
-        int nh = 0;
-        uint64_t ids[2];
-        float terms[2];
         if (idx < total) {
             const int ca = idx % nx, cb = idx / nx;
             const int i = spanx >= n ? ca : ((q.cxlo + ca) & msk);
             const int j = spany >= n ? cb : ((q.cylo + cb) & msk);
-            nh = test_cell(H, q, i, j, ids, terms);
-            acc.cells += 1;
+            plane_cell<MODE>(H, q, i, j, acc, hs);
         }
-        take_hits<MODE>(q, nh, ids, terms, acc, rec);
+        flush_records<MODE>(hs, rec);
     }
     finish<MODE>(a, qi, q, acc);
 }
 
 // ------------------------------------------------------------ hierarchical
 
-// LDS per wave: L lists of kListCap node entries (levels 1..L) + the leaf queue.
+// One wavefront per workgroup (a long query holds only its own LDS).  LDS: L lists
+// of kListCap node entries (levels 1..L) + the leaf queue.
 template <int MODE, bool CUT>
-__global__ __launch_bounds__(256) void k_eval_plain(HierDev H, EvalArgs a)
+__global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
 {
     extern __shared__ uint32_t lds[];
-    const int wave = threadIdx.x >> 6;
-    const int64_t qi = (int64_t)blockIdx.x * 4 + wave;
-    if (qi >= a.nq) return;
-    uint32_t* lists = lds + (size_t)wave * wave_lds_words(H.L);
-    uint32_t* cellq = lists + H.L * kListCap;
+    const int64_t local = xcd_contiguous(blockIdx.x, gridDim.x);
+    if (local >= a.slots) return;
+    const int64_t slot = a.slot0 + local;
+    const int64_t qi = a.order ? (int64_t)a.order[slot] : slot;
+    uint32_t* lists = lds;
     const QuerySetup q = setup_query(a.q[qi], a.s2r, CUT ? a.tau : 0.f, H.L, H.eps);
     if (!q.valid) { invalid<MODE>(a, qi); return; }
     Acc acc;
@@ -413,26 +465,41 @@ __global__ __launch_bounds__(256) void k_eval_plain(HierDev H, EvalArgs a)
     bool ok;
     const uint32_t item = root_item(H, q, &ok);
     TaskQueue none{};
-    descend<MODE, CUT, false>(H, q, lists, cellq, q.l0, ok, item, 0, 0, none, acc, rec);
+    descend<MODE, CUT, false>(H, q, lists, q.l0, ok, item, false, 0, 0, none, acc, rec);
     finish<MODE>(a, qi, q, acc);
 }
 
 // ------------------------------------------------------------ persistent
-__device__ __forceinline__ void acc_atomic_add(Fix128* dst, const Fix128& v)
+// Exact atomic accumulation of a 192-bit value: each word is added atomically and
+// every carry out of a word is added to the next one, so once all atomics have
+// completed the sum is exact whatever their interleaving.
+__device__ __forceinline__ void acc_atomic_add(Fix192* dst, const Fix192& v)
 {
-    if (v.lo == 0 && v.hi == 0) return;
-    const unsigned long long old = atomicAdd((unsigned long long*)&dst->lo, (unsigned long long)v.lo);
-    const unsigned long long carry = (old + v.lo < old) ? 1ull : 0ull;
-    atomicAdd((unsigned long long*)&dst->hi, (unsigned long long)(v.hi + carry));
+    unsigned long long* w = (unsigned long long*)dst;
+    unsigned long long c1 = 0, c2 = 0;
+    if (v.w0) {
+        const unsigned long long old = atomicAdd(&w[0], (unsigned long long)v.w0);
+        c1 = (old + v.w0 < old) ? 1ull : 0ull;
+    }
+    if (v.w1) {
+        const unsigned long long old = atomicAdd(&w[1], (unsigned long long)v.w1);
+        c2 += (old + v.w1 < old) ? 1ull : 0ull;
+    }
+    if (c1) {
+        const unsigned long long old = atomicAdd(&w[1], 1ull);
+        c2 += (old + 1ull < old) ? 1ull : 0ull;
+    }
+    if (v.w2 + c2) atomicAdd(&w[2], (unsigned long long)(v.w2 + c2));
 }
 
-__global__ void k_persist_reset(QueueCtl* ctl, Fix128* acc, int* fexp, const pndf_query* q,
+__global__ void k_persist_reset(QueueCtl* ctl, Fix192* acc, int* fexp, const pndf_query* q,
                                 long long nq, float* out, unsigned epoch)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (long long i = t; i < nq; i += (long long)gridDim.x * blockDim.x) {
-        acc[i].lo = 0;
-        acc[i].hi = 0;
+        acc[i].w0 = 0;
+        acc[i].w1 = 0;
+        acc[i].w2 = 0;
         fexp[i] = 0;
     }
     if (t == 0) {
@@ -455,7 +522,6 @@ __global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
     extern __shared__ uint32_t lds[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t* lists = lds + (size_t)wave * wave_lds_words(H.L);
-    uint32_t* cellq = lists + H.L * kListCap;
     QueueCtl* ctl = pa.Q.ctl;
     const long long nq = ctl->nq;
     const pndf_query* qs = ctl->q;
@@ -539,8 +605,9 @@ __global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
                     word = pa.Q.tasks[task_slot];
                     const long long wq = (long long)(word >> 32);
                     const int wl = (int)((word >> 26) & 0x3fu);
-                    const int wi = (int)(word & 0x1fffu), wj = (int)((word >> 13) & 0x1fffu);
-                    if (wq >= nq || wl < 1 || wl > H.L || wi >= (H.n >> wl) || wj >= (H.n >> wl)) {
+                    const uint64_t wm = word & 0x3ffffffu;
+                    if (wq >= nq || wl < 1 || wl > H.L ||
+                        wm >= (uint64_t)(H.n >> wl) * (uint64_t)(H.n >> wl)) {
                         atomicOr(&ctl->error, 4u);
                         ok = 0;
                     }
@@ -551,11 +618,10 @@ __global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
             if (ok) {
                 const long long qi = (long long)(word >> 32);
                 const int lev = (int)((word >> 26) & 0x3fu);
-                const uint32_t item = (uint32_t)(word & 0x1fffu) | ((uint32_t)((word >> 13) & 0x1fffu) << 16);
+                const uint32_t item = (uint32_t)(word & 0x3ffffffu);
                 const QuerySetup q = setup_query(qs[qi], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps);
-                descend<kModeValue, CUT, false>(H, q, lists, cellq, lev, lane == 0, item, 0, 0, pa.Q, acc,
-                                                rec);
-                const Fix128 d = wave_sum_fix(acc.d);
+                descend<kModeValue, CUT, false>(H, q, lists, lev, lane == 0, item, true, 0, 0, pa.Q, acc, rec);
+                const Fix192 d = wave_sum_fix(acc.d);
                 if (lane == 0) acc_atomic_add(&pa.acc[qi], d);
             }
             if (lane == 0) {
@@ -569,13 +635,12 @@ __global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
                 bool ok;
                 const uint32_t item = root_item(H, q, &ok);
                 if (q.l0 > pa.split_level)
-                    descend<kModeValue, CUT, true>(H, q, lists, cellq, q.l0, ok, item, pa.split_level,
+                    descend<kModeValue, CUT, true>(H, q, lists, q.l0, ok, item, false, pa.split_level,
                                                    (unsigned long long)query, pa.Q, acc, rec);
                 else
-                    descend<kModeValue, CUT, false>(H, q, lists, cellq, q.l0, ok, item, 0, 0, pa.Q, acc,
-                                                    rec);
+                    descend<kModeValue, CUT, false>(H, q, lists, q.l0, ok, item, false, 0, 0, pa.Q, acc, rec);
             }
-            const Fix128 d = wave_sum_fix(acc.d);
+            const Fix192 d = wave_sum_fix(acc.d);
             if (lane == 0) {
                 pa.fexp[query] = q.valid ? q.fexp : 0x7fffffff;
                 acc_atomic_add(&pa.acc[query], d);
@@ -588,7 +653,7 @@ __global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
     if (lane == 0 && spins) atomicAdd(&ctl->spins, spins);
 }
 
-__global__ void k_persist_finalize(const QueueCtl* ctl, const Fix128* acc, const int* fexp)
+__global__ void k_persist_finalize(const QueueCtl* ctl, const Fix192* acc, const int* fexp)
 {
     const long long nq = ctl->nq;
     float* out = ctl->out;
@@ -599,23 +664,128 @@ __global__ void k_persist_finalize(const QueueCtl* ctl, const Fix128* acc, const
     }
 }
 
+// Launches cover at most kChunk queries (grid dimensions stay far below 2^32 work-items).
+constexpr int64_t kChunk = (int64_t)1 << 24;
+
 template <int MODE>
-hipError_t launch_mode(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s)
+hipError_t launch_mode(const HierDev& H, const EvalArgs& a0, int algo, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((a.nq + 3) / 4);
-    if (algo == PNDF_ALGO_BRUTE) {
-        hipLaunchKernelGGL(k_eval_brute<MODE>, dim3(blocks), dim3(256), 0, s, H, a);
-    } else {
-        const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(H.L);
-        if (a.tau > 0.f)
-            hipLaunchKernelGGL((k_eval_plain<MODE, true>), dim3(blocks), dim3(256), lds, s, H, a);
-        else
-            hipLaunchKernelGGL((k_eval_plain<MODE, false>), dim3(blocks), dim3(256), lds, s, H, a);
+    for (int64_t off = 0; off < a0.nq; off += kChunk) {
+        EvalArgs a = a0;
+        a.slot0 = off;
+        a.slots = std::min<int64_t>(kChunk, a0.nq - off);
+        if (algo == PNDF_ALGO_BRUTE) {
+            const unsigned blocks = (unsigned)((a.slots + 3) / 4);
+            hipLaunchKernelGGL(k_eval_brute<MODE>, dim3(blocks), dim3(256), 0, s, H, a);
+        } else {
+            const unsigned blocks = (unsigned)a.slots;
+            const size_t lds = sizeof(uint32_t) * wave_lds_words(H.L);
+            if (a.tau > 0.f)
+                hipLaunchKernelGGL((k_eval_plain<MODE, true>), dim3(blocks), dim3(64), lds, s, H, a);
+            else
+                hipLaunchKernelGGL((k_eval_plain<MODE, false>), dim3(blocks), dim3(64), lds, s, H, a);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------ query order
+constexpr int kOrderBits = 6;  // 64 x 64 buckets
+
+__global__ void k_order_zero(uint32_t* hist, int nb)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) hist[i] = 0;
+}
+
+__global__ void k_order_hist(const pndf_query* __restrict__ q, int64_t nq, int n, int bshift,
+                             uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = q[i].x, y = q[i].y;
+        uint32_t k = 0;
+        if (fabsf(x) <= 16777216.0f && fabsf(y) <= 16777216.0f) {  // false for NaN
+            const uint32_t cx = (uint32_t)((int)floorf(x) & (n - 1)) >> bshift;
+            const uint32_t cy = (uint32_t)((int)floorf(y) & (n - 1)) >> bshift;
+            k = morton(cx, cy);
+        }
+        key[i] = k;
+        atomicAdd(&hist[k], 1u);
+    }
+}
+
+// exclusive scan of nb <= 4096 counters by one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_order_scan(uint32_t* hist, int nb)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x, per = (nb + 1023) / 1024;
+    uint32_t sum = 0;
+    for (int k = 0; k < per; ++k) {
+        const int i = t * per + k;
+        if (i < nb) sum += hist[i];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int k = 0; k < per; ++k) {
+        const int i = t * per + k;
+        if (i < nb) {
+            const uint32_t c = hist[i];
+            hist[i] = run;
+            run += c;
+        }
+    }
+}
+
+__global__ void k_order_scatter(const uint32_t* __restrict__ key, int64_t nq, uint32_t* __restrict__ cursor,
+                                uint32_t* __restrict__ order)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t pos = atomicAdd(&cursor[key[i]], 1u);
+        order[pos] = (uint32_t)i;
+    }
 }
 
 }  // namespace
+
+hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s)
+{
+    *order = nullptr;
+    const int bits = H.logn < kOrderBits ? H.logn : kOrderBits;
+    const int nb = 1 << (2 * bits);
+    const int bshift = H.logn - bits;
+    uint32_t* buf = nullptr;  // order[nq] | key[nq] | hist[nb]
+    hipError_t e = hipMallocAsync((void**)&buf, sizeof(uint32_t) * (2 * (size_t)nq + nb), s);
+    if (e != hipSuccess) return e;
+    uint32_t* key = buf + nq;
+    uint32_t* hist = key + nq;
+    const unsigned g = (unsigned)std::min<int64_t>(2048, (nq + 255) / 256);
+    hipLaunchKernelGGL(k_order_zero, dim3(16), dim3(256), 0, s, hist, nb);
+    hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, s, q, nq, H.n, bshift, key, hist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, hist, nb);
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, s, key, nq, hist, buf);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(buf, s);
+        return e;
+    }
+    *order = buf;
+    return hipSuccess;
+}
+
+void free_order(uint32_t* order, hipStream_t s)
+{
+    if (order) (void)hipFreeAsync(order, s);
+}
 
 hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s)
 {

@@ -206,14 +206,25 @@ struct LevelOut {
     uint8_t* clu_deg;
 };
 
-// Level 1: every node integrates its 2 x 2 cells (8 fine triangles) directly.
-__global__ void k_level1(HierDev H, LevelOut o, double* __restrict__ mom, int cluster)
+// Level 1: every node integrates its 2 x 2 cells (8 fine triangles) directly and
+// writes its leaf record.  Thread index = Morton code of the node.
+__global__ void k_level1(HierDev H, LevelOut o, QuadRec* __restrict__ quad, double* __restrict__ mom,
+                         int cluster)
 {
     const int m = H.n >> 1;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)m * m) return;
-    const int I = (int)(t % m), J = (int)(t / m);
+    const int I = (int)morton_compact((uint32_t)t), J = (int)morton_compact((uint32_t)t >> 1);
     const int w = H.n + 1;
+    {
+        QuadRec r;
+        for (int y = 0; y < 3; ++y)
+            for (int x = 0; x < 3; ++x) r.t[3 * y + x] = H.nrm[(int64_t)(2 * J + y) * w + 2 * I + x];
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) r.deg[2 * dj + di] = H.deg[(int64_t)(2 * J + dj) * H.n + 2 * I + di];
+        r.pad = 0;
+        quad[t] = r;
+    }
     double lo[kMom] = {0}, up[kMom] = {0};
     float4 box = empty_box();
     for (int dj = 0; dj < 2; ++dj)
@@ -256,16 +267,16 @@ __global__ void k_level1(HierDev H, LevelOut o, double* __restrict__ mom, int cl
 }
 
 // Level l >= 2 from level l-1: boxes are unions of the children; moments are
-// shifted into the parent frame and split over its halves.
+// shifted into the parent frame and split over its halves.  Thread index = Morton
+// code; the children of node t are 4t + (di + 2 dj).
 __global__ void k_level_up(HierDev H, int level, LevelOut o, const float4* __restrict__ cbox,
                            const float4* __restrict__ cbox_all, const double* __restrict__ cmom,
                            double* __restrict__ mom, int cluster)
 {
-    const int m = H.n >> level, mc = m * 2;
+    const int m = H.n >> level;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)m * m) return;
-    const int I = (int)(t % m), J = (int)(t / m);
-    const int64_t c00 = (int64_t)(2 * J) * mc + 2 * I, c10 = c00 + 1, c01 = c00 + mc, c11 = c01 + 1;
+    const int64_t c00 = 4 * t, c10 = c00 + 1, c01 = c00 + 2, c11 = c00 + 3;
     float4 box = cbox[c00];
     box_union(box, cbox[c10]);
     box_union(box, cbox[c01]);
@@ -298,7 +309,26 @@ __global__ void k_level_up(HierDev H, int level, LevelOut o, const float4* __res
     o.bbox_all[t] = cb;
 }
 
+__global__ void k_export_rowmajor(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int m,
+                                  int words)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)m * m) return;
+    const uint32_t I = (uint32_t)(k % m), J = (uint32_t)(k / m);
+    const uint32_t* a = src + (int64_t)morton(I, J) * words;
+    uint32_t* b = dst + k * words;
+    for (int w = 0; w < words; ++w) b[w] = a[w];
+}
+
 }  // namespace
+
+hipError_t export_rowmajor(const void* src, void* dst, int m, int words, hipStream_t s)
+{
+    const int64_t cnt = (int64_t)m * m;
+    hipLaunchKernelGGL(k_export_rowmajor, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       (const uint32_t*)src, (uint32_t*)dst, m, words);
+    return hipGetLastError();
+}
 
 hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
 {
@@ -329,7 +359,7 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
     };
     const int bs = 128;
     hipLaunchKernelGGL(k_level1, dim3((unsigned)((m1 + bs - 1) / bs)), dim3(bs), 0, s, H, out_for(1),
-                       mom[0], h->cluster);
+                       h->quad, mom[0], h->cluster);
     err = hipGetLastError();
     for (int level = 2; level <= H.L && err == hipSuccess; ++level) {
         const int64_t m = (int64_t)(n >> level) * (n >> level);

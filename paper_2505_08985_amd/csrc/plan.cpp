@@ -76,7 +76,7 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     }
     if (!(std::isfinite(o.tau) && o.tau >= 0.f)) return plan_invalid("tau must be finite and >= 0");
     if (!(std::isfinite(o.sigma_to_r) && o.sigma_to_r > 0.f)) return plan_invalid("sigma_to_r must be > 0");
-    if (o.flags != 0) return plan_invalid("flags must be 0");
+    if (o.flags & ~PNDF_EVAL_INPUT_ORDER) return plan_invalid("unknown flags");
     if (o.tau > 0.f && !h->cluster) return plan_invalid("tau > 0 needs a hierarchy built with clusters");
     pndf_tuning t;
     pndf_default_tuning(h, &t);
@@ -98,7 +98,7 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     P.tau = o.tau;
     P.s2r = o.sigma_to_r;
     hipError_t e = hipMalloc(&P.ctl, sizeof(QueueCtl));
-    if (e == hipSuccess) e = hipMalloc(&P.acc, sizeof(Fix128) * (size_t)max_nq);
+    if (e == hipSuccess) e = hipMalloc(&P.acc, sizeof(Fix192) * (size_t)max_nq);
     if (e == hipSuccess) e = hipMalloc(&P.fexp, sizeof(int) * (size_t)max_nq);
     if (e == hipSuccess) e = hipMalloc(&P.tasks, sizeof(unsigned long long) * P.capacity);
     if (e == hipSuccess) e = hipMalloc(&P.flags, sizeof(unsigned) * P.capacity);

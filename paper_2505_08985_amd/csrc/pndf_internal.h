@@ -16,12 +16,23 @@ namespace pndf {
 constexpr int kMaxLevels = 13;   // N <= 8192
 constexpr int kWave = 64;
 constexpr int kListCap = 256;    // per-level traversal list (64 parents x 4 children)
-constexpr int kCellCap = 320;    // leaf-cell queue: < 64 waiting + 256 pushed by one batch
 
-// 32-bit LDS words per wavefront of the descent: L node lists + the leaf queue.
-__host__ __device__ inline size_t wave_lds_words(int L) { return (size_t)L * kListCap + kCellCap; }
+// 32-bit LDS words per wavefront of the descent: one node list per level 1..L.
+__host__ __device__ inline size_t wave_lds_words(int L) { return (size_t)L * kListCap; }
 
-// Device-side view of a mesh + hierarchy, passed to kernels by value.
+// Level-1 leaf record: the 3 x 3 texel normals of a 2 x 2 cell block (row-major,
+// texel (2I + x, 2J + y) at t[3 y + x], periodic) and the clamp bits of its four
+// cells (cell (di, dj) at deg[2 dj + di]), 80 bytes = five 16-byte loads.
+struct QuadRec {
+    float2 t[9];
+    uint8_t deg[4];
+    uint32_t pad;
+};
+static_assert(sizeof(QuadRec) == 80, "QuadRec is five 16-byte words");
+
+// Device-side view of a mesh + hierarchy, passed to kernels by value.  Every
+// per-node array is stored per level in Morton (Z) order: node (I, J) of level l at
+// off[l] + morton(I, J), so the four children of node m are 4m .. 4m + 3.
 struct HierDev {
     const float2* nrm;      // (n+1) x (n+1) padded texel normals (last row/column wrap)
     const uint8_t* deg;     // n x n clamp bits (bit0 lower, bit1 upper)
@@ -32,17 +43,19 @@ struct HierDev {
     const float* clu_e;     // e^l per node
     const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
     const uint8_t* clu_deg; // cluster clamp bits
+    const QuadRec* quad;    // level-1 leaf records (Morton order)
     int n, L, logn;
     float eps;
     float rho;              // circumradius of the clamp replacement triangle (area eps / 2)
     int64_t off[kMaxLevels + 2]; // first node of level l in the packed arrays (off[1] = 0)
 };
 
-// ---- exact accumulation: unsigned 128-bit fixed point, lo + 2^64 hi units of 2^fexp ----
-// Adding the float32 terms of a query in any order gives the same integer, so every
-// evaluation algorithm (brute force, descent, split across waves) returns the same D.
-struct Fix128 {
-    uint64_t lo, hi;
+// ---- exact accumulation: unsigned 192-bit fixed point w0 + 2^64 w1 + 2^128 w2, in
+// units of 2^fexp.  Adding the float32 terms of a query in any order gives the same
+// integer, so every evaluation algorithm (brute force, descent, split across waves)
+// returns the same D.
+struct Fix192 {
+    uint64_t w0, w1, w2;
 };
 
 // Global task queue of the persistent traversal.  Slots are reserved by a CAS on
@@ -70,7 +83,7 @@ struct TaskQueue {
 
 struct PersistArgs {
     TaskQueue Q;
-    Fix128* acc;     // per-query exact sums
+    Fix192* acc;     // per-query exact sums
     int* fexp;       // per-query binary point (written by the query's root task)
     float tau, s2r;
     int split_level; // donate subtrees rooted at this level (>= 1)
@@ -79,7 +92,7 @@ struct PersistArgs {
 // Device resources and the instantiated launch graph of a persistent plan.
 struct PersistPlan {
     QueueCtl* ctl = nullptr;
-    Fix128* acc = nullptr;
+    Fix192* acc = nullptr;
     int* fexp = nullptr;
     unsigned long long* tasks = nullptr;
     unsigned int* flags = nullptr;
@@ -131,6 +144,7 @@ struct pndf_hier {
     float* clu_e = nullptr;
     float2* clu_det = nullptr;
     uint8_t* clu_deg = nullptr;
+    pndf::QuadRec* quad = nullptr;
     int64_t bytes = 0;
     pndf::HierDev dev;
 };
@@ -145,10 +159,14 @@ pndf_status hip_fail(hipError_t e, const char* what);
 hipError_t launch_build_mesh(const float* in, int n, float eps, float2* nrm, uint8_t* deg,
                              float2* det, unsigned* d_flag, hipStream_t s);
 hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s);
+// Row-major copy of a Morton-ordered per-node array of `words` 32-bit words per node.
+hipError_t export_rowmajor(const void* src, void* dst, int m, int words, hipStream_t s);
 
 struct EvalArgs {
     const pndf_query* q;
+    const uint32_t* order;     // optional processing order (query index per slot)
     int64_t nq;
+    int64_t slot0, slots;      // the launch covers processing slots [slot0, slot0 + slots)
     float* out;
     uint32_t* counts;          // nullptr unless counting
     const uint64_t* offsets;   // hit-record pass only
@@ -158,6 +176,11 @@ struct EvalArgs {
     float s2r;
 };
 hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s);
+
+// Spatial processing order of a batch: queries bucketed by the Morton code of their
+// centre cell (64 x 64 buckets over the torus), stream-ordered workspace.
+hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s);
+void free_order(uint32_t* order, hipStream_t s);
 
 // ---------------------------------------------------------------- device side
 #if defined(__HIPCC__)
@@ -176,8 +199,8 @@ struct QuerySetup {
     int cxlo, cxhi, cylo, cyhi;  // included unrolled cell range per axis
     int l0;                      // entry level
     float t;                     // cut threshold fl(fl(rx ry) tau)
-    float kx, ky;                // log2(e) / (2 sigma^2)
-    float norm;                  // 1 / (2 pi sx sy)
+    double kx, ky;               // log2(e) / (2 sigma^2)
+    double norm;                 // 1 / (2 pi sx sy)
     int fexp;                    // binary point of the exact accumulator (units of 2^fexp)
     bool valid;
 };
@@ -196,7 +219,7 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     q.valid = ok;
     if (!ok) {
         q.cxlo = q.cylo = 0; q.cxhi = q.cyhi = -1; q.l0 = 0; q.t = -1.f;
-        q.kx = q.ky = q.norm = 0.f;
+        q.kx = q.ky = q.norm = 0.0;
         q.fexp = 0;
         return q;
     }
@@ -210,59 +233,75 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     q.l0 = l0;
     q.t = tau > 0.f ? __fmul_rn(__fmul_rn(rx, ry), tau) : -1.f;
     const double log2e = 1.4426950408889634074;
-    q.kx = (float)(log2e / (2.0 * (double)qr.sx * (double)qr.sx));
-    q.ky = (float)(log2e / (2.0 * (double)qr.sy * (double)qr.sy));
+    q.kx = log2e / (2.0 * (double)qr.sx * (double)qr.sx);
+    q.ky = log2e / (2.0 * (double)qr.sy * (double)qr.sy);
     const double norm = 1.0 / (2.0 * 3.14159265358979323846 * (double)qr.sx * (double)qr.sy);
-    q.norm = (float)norm;
+    q.norm = norm;
     // Every term is at most norm / eps per included cell image and triangle (node
     // images of a cluster reach at most one cell beyond the box per side), so
     // D < bound = 2 (nx + 2) (ny + 2) norm / eps.  The exact accumulator counts in
-    // units of 2^fexp with bound < 2^(fexp + 126): 128 bits hold any D, and every
-    // float32 term is represented exactly down to 2^fexp.
+    // units of 2^fexp with bound < 2^(fexp + 190): 192 bits hold any D, and every
+    // float32 term down to bound 2^-190 is represented exactly.
     const double bound = 2.0 * ((double)(q.cxhi - q.cxlo) + 3.0) * ((double)(q.cyhi - q.cylo) + 3.0) *
                          norm / (double)eps;
     int e2;
     frexp(bound, &e2);
-    q.fexp = e2 + 1 - 126;
+    q.fexp = e2 + 1 - 190;
     return q;
 }
 
-__device__ __forceinline__ void fix_add_term(Fix128& a, float t, int fexp)
+// FP64 term t >= 0 added exactly down to 2^fexp: t = m 2^(ex - 1075) = (m 2^sh) 2^fexp,
+// sh <= 136 since t < 2^(fexp + 189)
+__device__ __forceinline__ void fix_add_term(Fix192& a, double t, int fexp)
 {
-    const uint32_t b = __float_as_uint(t);
-    int ex = (int)((b >> 23) & 0xffu);
-    uint64_t m = b & 0x7fffffu;
-    if (ex) m |= 0x800000u; else ex = 1;
-    const int sh = ex - 150 - fexp;  // t = m 2^(ex - 150) = (m 2^sh) 2^fexp, sh <= 101
-    uint64_t vlo, vhi;
-    if (sh >= 64) {
-        vlo = 0;
-        vhi = m << (sh - 64);
-    } else if (sh > 0) {
-        vlo = m << sh;
-        vhi = m >> (64 - sh);
-    } else if (sh > -64) {
-        vlo = m >> (-sh);
-        vhi = 0;
+    const uint64_t b = (uint64_t)__double_as_longlong(t);
+    int ex = (int)((b >> 52) & 0x7ffu);
+    uint64_t m = b & 0xfffffffffffffull;
+    if (ex) m |= 0x10000000000000ull; else ex = 1;
+    const int sh = ex - 1075 - fexp;
+    uint64_t v0 = 0, v1 = 0, v2 = 0;
+    if (sh <= -64) {
+        // below the accumulator's resolution
+    } else if (sh < 0) {
+        v0 = m >> (-sh);
+    } else if (sh < 64) {
+        v0 = m << sh;
+        v1 = sh ? (m >> (64 - sh)) : 0;
+    } else if (sh < 128) {
+        const int s1 = sh - 64;
+        v1 = m << s1;
+        v2 = s1 ? (m >> (64 - s1)) : 0;
     } else {
-        vlo = 0;
-        vhi = 0;
+        v2 = m << (sh - 128);
     }
-    const uint64_t lo = a.lo + vlo;
-    a.hi += vhi + (lo < vlo ? 1u : 0u);
-    a.lo = lo;
+    const uint64_t r0 = a.w0 + v0;
+    const uint64_t c0 = r0 < v0 ? 1u : 0u;
+    const uint64_t t1 = a.w1 + v1;
+    const uint64_t c1 = t1 < v1 ? 1u : 0u;
+    const uint64_t r1 = t1 + c0;
+    const uint64_t c1b = r1 < c0 ? 1u : 0u;
+    a.w0 = r0;
+    a.w1 = r1;
+    a.w2 += v2 + c1 + c1b;
 }
 
-__device__ __forceinline__ void fix_add(Fix128& a, const Fix128& b)
+__device__ __forceinline__ void fix_add(Fix192& a, const Fix192& b)
 {
-    const uint64_t lo = a.lo + b.lo;
-    a.hi += b.hi + (lo < b.lo ? 1u : 0u);
-    a.lo = lo;
+    const uint64_t r0 = a.w0 + b.w0;
+    const uint64_t c0 = r0 < b.w0 ? 1u : 0u;
+    const uint64_t t1 = a.w1 + b.w1;
+    const uint64_t c1 = t1 < b.w1 ? 1u : 0u;
+    const uint64_t r1 = t1 + c0;
+    const uint64_t c1b = r1 < c0 ? 1u : 0u;
+    a.w0 = r0;
+    a.w1 = r1;
+    a.w2 += b.w2 + c1 + c1b;
 }
 
-__device__ __forceinline__ float fix_to_float(const Fix128& a, int fexp)
+__device__ __forceinline__ float fix_to_float(const Fix192& a, int fexp)
 {
-    const double d = (double)a.hi * 18446744073709551616.0 + (double)a.lo;
+    const double d = ((double)a.w2 * 18446744073709551616.0 + (double)a.w1) * 18446744073709551616.0 +
+                     (double)a.w0;
     return (float)ldexp(d, fexp);
 }
 
@@ -274,17 +313,22 @@ __device__ __forceinline__ bool axis_overlap(int start, int side, int clo, int c
 }
 
 // Sum over the included periodic images of one axis of exp(-d^2 / (2 sigma^2)),
-// d = start + p N + uoff - x; node of side `side` (1 for a texel cell).
-__device__ inline float gauss_axis(float x, float k, int start, int side, double uoff, int clo,
-                                   int chi, int logn)
+// d = start + p N + uoff - x; node of side `side` (1 for a texel cell).  The
+// exponent a = d^2 log2(e) / (2 sigma^2) is split into floor(a) (an exact power of
+// two, ldexp) and a fraction (float32 exp2), so nothing underflows before the
+// FP64 product.
+__device__ inline double gauss_axis(float x, double k, int start, int side, double uoff, int clo,
+                                    int chi, int logn)
 {
     int p0 = ceil_div_pow2(clo - start - side + 1, logn);
     int p1 = floor_div_pow2(chi - start, logn);
-    float g = 0.f;
+    double g = 0.0;
     double base = (double)start + uoff - (double)x;
     for (int p = p0; p <= p1; ++p) {
-        double d = base + (double)p * (double)(1 << logn);
-        g += exp2f(-(float)(d * d) * k);
+        const double d = base + (double)p * (double)(1 << logn);
+        const double a = d * d * k;
+        const double ai = floor(a);
+        g += ldexp((double)exp2f(-(float)(a - ai)), -(int)fmin(ai, 2000.0));
     }
     return g;
 }
@@ -333,20 +377,56 @@ __device__ inline bool tri_bary_f64(const double v[6], double hx, double hy, dou
 // Contribution of a hit: the triangle's uv vertices are (a, b, c) =
 // lower: (U0, U0 + s e_x, U0 + s e_y), upper: (U3, U3 - s e_x, U3 - s e_y) of the node
 // (I, J) of side s = 2^lev (lev = 0: texel cell), so u* = corner +- s (l1, l2).
-__device__ inline float hit_term(const QuerySetup& q, int I, int J, int lev, int half, double l1,
-                                 double l2, float det_used, int logn)
+__device__ inline double hit_term(const QuerySetup& q, int I, int J, int lev, int half, double l1,
+                                  double l2, float det_used, int logn)
 {
     const int s = 1 << lev;
     double ux = half ? (double)s * (1.0 - l1) : (double)s * l1;
     double uy = half ? (double)s * (1.0 - l2) : (double)s * l2;
-    float gx = gauss_axis(q.x, q.kx, I * s, s, ux, q.cxlo, q.cxhi, logn);
-    float gy = gauss_axis(q.y, q.ky, J * s, s, uy, q.cylo, q.cyhi, logn);
-    return q.norm * gx * gy / det_used;
+    const double gx = gauss_axis(q.x, q.kx, I * s, s, ux, q.cxlo, q.cxhi, logn);
+    const double gy = gauss_axis(q.y, q.ky, J * s, s, uy, q.cylo, q.cyhi, logn);
+    return q.norm * gx * gy / (double)det_used;
 }
 
 __device__ __forceinline__ uint64_t tri_id(int lev, int I, int J, int half)
 {
     return ((uint64_t)lev << 58) | ((uint64_t)J << 29) | ((uint64_t)I << 1) | (uint64_t)half;
+}
+
+__host__ __device__ __forceinline__ uint32_t morton_spread(uint32_t v)
+{
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__host__ __device__ __forceinline__ uint32_t morton_compact(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0f0f0f0fu;
+    v = (v | (v >> 4)) & 0x00ff00ffu;
+    v = (v | (v >> 8)) & 0x0000ffffu;
+    return v;
+}
+
+__host__ __device__ __forceinline__ uint32_t morton(uint32_t i, uint32_t j)
+{
+    return morton_spread(i) | (morton_spread(j) << 1);
+}
+
+// Block index -> logical index so that each XCD (workgroups are dispatched to the
+// kXcd dies round-robin) walks a contiguous range of the processing order.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t nblocks)
+{
+    const int64_t x = b % kXcd, k = b / kXcd;
+    const int64_t per = (nblocks + kXcd - 1) / kXcd, r = nblocks % kXcd;
+    if (r == 0) return x * per + k;
+    return (x < r ? x * per : r * per + (x - r) * (per - 1)) + k;
 }
 
 // Wave-level helpers (wave64).
@@ -374,12 +454,13 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-__device__ __forceinline__ Fix128 wave_sum_fix(Fix128 v)
+__device__ __forceinline__ Fix192 wave_sum_fix(Fix192 v)
 {
     for (int o = 32; o >= 1; o >>= 1) {
-        Fix128 w;
-        w.lo = __shfl_xor(v.lo, o, 64);
-        w.hi = __shfl_xor(v.hi, o, 64);
+        Fix192 w;
+        w.w0 = __shfl_xor(v.w0, o, 64);
+        w.w1 = __shfl_xor(v.w1, o, 64);
+        w.w2 = __shfl_xor(v.w2, o, 64);
         fix_add(v, w);
     }
     return v;

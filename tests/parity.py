@@ -8,10 +8,14 @@ set.  The reference value is then recomputed with the GPU's include/exclude
 choice for each ambiguous triangle, and |D_gpu - D_ref| <= rtol * D_ref.
 Queries whose cluster cut decision sits within rounding of the threshold
 (oracle flag bit 0) are excluded from the strict comparison and counted.
+The GPU result is a float32: below float32's normal range (FLT_MIN = 2^-126) it
+cannot carry relative precision, so the bound has an absolute floor of
+rtol * FLT_MIN.
 """
 import numpy as np
 
 RTOL = 1e-4
+FLT_MIN = float(np.finfo(np.float32).tiny)
 
 
 def _split(off, vals):
@@ -61,7 +65,7 @@ def compare(ref, d_gpu, gpu_off=None, gpu_ids=None, rtol=RTOL, check_ids=True):
                 # without the GPU's ids, accept any choice on the ambiguous set
                 base = float(sum(t for i, t in zip(h_ids.tolist(), h_terms.tolist()) if i not in amb))
                 lo, hi = base, base + float(np.sum(a_terms))
-                if lo * (1 - rtol) - 1e-30 <= d_gpu[k] <= hi * (1 + rtol) + 1e-30:
+                if lo * (1 - rtol) - rtol * FLT_MIN <= d_gpu[k] <= hi * (1 + rtol) + rtol * FLT_MIN:
                     continue
                 bad.append((k, "value %r outside [%r, %r]" % (d_gpu[k], lo, hi)))
                 continue
@@ -70,10 +74,11 @@ def compare(ref, d_gpu, gpu_off=None, gpu_ids=None, rtol=RTOL, check_ids=True):
             if d_gpu[k] != 0.0:
                 bad.append((k, "gpu %r ref 0" % d_gpu[k]))
             continue
-        err = abs(d_gpu[k] - dref) / dref
-        worst = max(worst, err)
-        if err > rtol:
-            bad.append((k, "rel err %.3g (gpu %r ref %r)" % (err, d_gpu[k], dref)))
+        err = abs(d_gpu[k] - dref)
+        if dref >= FLT_MIN:
+            worst = max(worst, err / dref)
+        if err > rtol * max(dref, FLT_MIN):
+            bad.append((k, "rel err %.3g (gpu %r ref %r)" % (err / dref, d_gpu[k], dref)))
     assert not bad, "%d mismatching queries, first: %s" % (len(bad), bad[:5])
     return dict(worst_rel=worst, ambiguous_queries=n_amb_q, cut_ambiguous=int(skip.sum()),
                 nonzero=int((np.nan_to_num(D) > 0).sum()))

@@ -57,6 +57,7 @@ def setup(P):
     dict(blocks_per_cu=1, split_level=1, queue_factor=64, use_graph=1),
     dict(blocks_per_cu=2, split_level=3, queue_factor=16, use_graph=0),
     dict(blocks_per_cu=4, split_level=5, queue_factor=1, use_graph=1),   # tiny queue: refusals
+    dict(blocks_per_cu=2, split_level=1, queue_factor=1, use_graph=0),   # refused leaf-level donations
 ])
 def test_persistent_equals_plain_bitwise(P, setup, tau, tuning):
     import torch
@@ -74,6 +75,8 @@ def test_persistent_equals_plain_bitwise(P, setup, tau, tuning):
         assert torch.equal(got.view(torch.int32), plain.view(torch.int32)), (rep, st)
     if tuning["split_level"] <= 3:
         assert st["spawned"] > 0
+    if tuning["queue_factor"] == 1 and tuning["split_level"] == 1:
+        assert st["refused"] > 0, st
     plan.close()
 
 
