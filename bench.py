@@ -87,7 +87,7 @@ SERVE_MAPS = (dict(kind="bumps", n=1024, seed=411, count=8192),
 def serve_bench(args):
     """Serving workload: Poisson arrivals of render tiles (64 x 64 px x 4 spp) over three
     resident maps, footprints from synthetic ray differentials; continuous batching
-    (persistent plans on concurrent streams) against FIFO per-tile plain evaluation,
+    (per-batch launches or persistent plans on concurrent streams) against FIFO per-tile plain evaluation,
     at fractions of the plain per-tile throughput."""
     import torch
     import paper_2505_08985_amd as P
@@ -115,11 +115,13 @@ def serve_bench(args):
         P.eval_batch(hiers[m], q, tau=tau)
     torch.cuda.synchronize()
     cost = []
-    for m, q in zip(mids, dq):
+    for k, (m, q) in enumerate(zip(mids, dq)):
         a = time.perf_counter()
         P.eval_batch(hiers[m], q, tau=tau)
         torch.cuda.synchronize()
         cost.append(time.perf_counter() - a)
+        if k % 10 == 9:
+            print("[serve] plain per-tile: %d tiles timed" % (k + 1), file=sys.stderr, flush=True)
     cost = np.array(cost)
     plain_tiles_per_s = ntiles / cost.sum()
     print("[serve] plain per-tile: %.2f tiles/s (median tile %.2f ms, max %.1f ms)"
@@ -127,7 +129,7 @@ def serve_bench(args):
     qpt = tiles[0].shape[0]
     results = []
     srv = P.Server(hiers, slots=args.serve_slots, max_batch_queries=qpt * args.serve_batch_tiles,
-                   max_pending=4 * ntiles, tau=tau)
+                   max_pending=4 * ntiles, tau=tau, algo=args.serve_algo)
     srv.replay(mids[:4], np.zeros(4), tiles[:4])  # warm-up
     for frac in [float(f) for f in args.serve_rates.split(",")]:
         rate = frac * plain_tiles_per_s
@@ -163,7 +165,8 @@ def serve_bench(args):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "serving: Poisson 64x64x4 tiles over bumps1024 / scratched4096 / "
                                    "powerlaw8192", "tau": tau, "sigma_range": [0.5, smax],
-                       "slots": args.serve_slots, "batch_tiles": args.serve_batch_tiles},
+                       "slots": args.serve_slots, "batch_tiles": args.serve_batch_tiles,
+                       "batch_algo": args.serve_algo},
             "plain_per_tile_queries_per_s": plain_tiles_per_s * qpt, "by_rate": results}
     print(json.dumps(line), flush=True)
 
@@ -186,6 +189,8 @@ def main():
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95")
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-batch-tiles", type=int, default=4)
+    ap.add_argument("--serve-algo", default="plain", choices=["plain", "persistent"],
+                    help="how the server evaluates a batch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (3 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -236,7 +241,8 @@ def main():
 
     tuning = None
     if args.algo == "persistent":
-        sample = tq[:min(count, 1 << 16)]
+        sample = tq[:min(count, 1 << 14)]
+        print("[bench] autotuning on %d queries ..." % sample.shape[0], file=sys.stderr, flush=True)
         tuning, tms = P.autotune(hier, sample, tau=tau)
         print("[bench] autotuned %s (%.3f ms on %d queries)" % (tuning, tms, sample.shape[0]),
               file=sys.stderr, flush=True)

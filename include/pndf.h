@@ -179,29 +179,35 @@ const char* pndf_last_error(void);
  *
  * A plan owns the workspace of the persistent traversal for batches of up to
  * max_nq queries: a fixed grid of workers (compute units x blocks_per_cu blocks of
- * four wavefronts) takes queries from a global counter; a query whose entry level
- * is above split_level descends to that level and donates the surviving subtrees
- * to a global task queue, from which idle workers steal.  Each query's terms are
- * summed exactly (192-bit fixed point), so the result is bit-identical to
- * pndf_eval_batch whatever the split, the schedule or the batch composition.
- * The launch sequence (reset, workers, finalize) is instantiated once as a HIP
- * graph and replayed per batch.
+ * four wavefronts) takes queries, in the same spatial order as pndf_eval_batch
+ * (unless PNDF_EVAL_INPUT_ORDER), from a global counter.  Once no query is left to
+ * take, idle workers wait in a global ticket queue and raise a flag; a busy wave
+ * that sees it hands out up to half of the nodes of its highest pending level (if
+ * that level is at least split_level), at most one per waiting worker, as tasks of
+ * that queue; stolen subtrees are split again
+ * the same way, so one huge footprint ends up spread over the whole GPU.  Each
+ * query's terms are summed exactly (192-bit fixed point), so the result is
+ * bit-identical to pndf_eval_batch whatever the split, the schedule or the batch
+ * composition.  The launch sequence (reset, spatial order, workers, finalize) is
+ * instantiated once as a HIP graph and replayed per batch.
  */
 typedef struct pndf_plan pndf_plan;
 
 typedef struct pndf_tuning {
     int32_t blocks_per_cu; /* worker blocks per compute unit (>= 1) */
-    int32_t split_level;   /* donated subtree level, 1..log2 N */
+    int32_t split_level;   /* smallest level whose nodes may be donated, 1..log2 N */
     int32_t queue_factor;  /* task-queue slots per query of max_nq (>= 1); a donation that does not
-                            * fit is descended in place, so capacity only affects balance */
+                            * fit stays with its wave, so capacity only affects balance */
     int32_t use_graph;     /* 1: replay the instantiated graph; 0: three plain launches */
 } pndf_tuning;
 
 typedef struct pndf_plan_stats {
     uint64_t spawned;      /* subtrees donated to the queue in the last run */
-    uint64_t refused;      /* donations that did not fit and were descended in place */
+    uint64_t refused;      /* nodes offered while the queue was full (kept by their wave) */
     uint64_t idle_spins;   /* worker polls that found no work (load-balance diagnostic) */
-    uint32_t error;        /* nonzero: a worker gave up waiting (bit0 idle, bit1 slot); results invalid */
+    uint32_t error;        /* nonzero: a worker gave up after 30 s without work arriving (bit0) or
+                            * without a reserved task being published (bit1), or read a malformed
+                            * task (bit2); the results of that run are invalid */
 } pndf_plan_stats;
 
 /* Default tuning for a hierarchy (used when pndf_plan_create gets tuning == NULL). */
@@ -230,9 +236,10 @@ void pndf_plan_destroy(pndf_plan* plan);
 
 /*
  * Autotuner: time the persistent traversal on the given queries (a representative
- * sample of the workload) for every candidate tuning (blocks per compute unit 1..4,
- * split level 3..8 within the map's levels, graph replay) and return the fastest in
- * *best, with its time per batch in *best_ms (may be NULL).  Synchronises `stream`.
+ * sample of the workload) for every candidate tuning (blocks per compute unit in
+ * {1, 2, 4, 6, 8}, split level 2..8 within the map's levels, graph replay; best of two
+ * timed runs after a warm-up) and return the fastest in *best, with its time per
+ * batch in *best_ms (may be NULL).  Synchronises `stream`.
  */
 pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
                           const pndf_eval_opts* opts, pndf_tuning* best, double* best_ms,
@@ -261,6 +268,9 @@ typedef struct pndf_server_opts {
     float tau;                  /* cluster cut threshold for every request (0 = exact) */
     float sigma_to_r;           /* support half-width in standard deviations (3) */
     pndf_tuning tuning;         /* persistent-plan tuning (blocks_per_cu = 0: default) */
+    int32_t algo;               /* evaluation of a batch: PNDF_ALGO_PLAIN (or AUTO): one
+                                 * pndf_eval_batch on the slot's stream; PNDF_ALGO_PERSISTENT:
+                                 * the slot's persistent plan for the batch's map */
 } pndf_server_opts;
 
 typedef struct pndf_server_stats {

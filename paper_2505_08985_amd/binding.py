@@ -278,10 +278,10 @@ def hier_export_level(hier, level, stream=None):
 class Plan:
     """Persistent work-stealing evaluation plan (workspace + instantiated HIP graph)."""
 
-    def __init__(self, hier, max_nq, tau=0.0, sigma_to_r=3.0, tuning=None, stream=None):
+    def __init__(self, hier, max_nq, tau=0.0, sigma_to_r=3.0, tuning=None, stream=None, input_order=False):
         self.hier = hier  # the hierarchy must outlive the plan
         self.max_nq = int(max_nq)
-        o = _opts(tau, sigma_to_r, "persistent")
+        o = _opts(tau, sigma_to_r, "persistent", flags=EVAL_INPUT_ORDER if input_order else 0)
         t = None
         if tuning is not None:
             t = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
@@ -335,7 +335,7 @@ def autotune(hier, queries, tau=0.0, sigma_to_r=3.0, stream=None):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", _i32), ("max_batch_queries", _i64), ("memory_budget", _i64), ("max_pending", _i32),
-                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning)]
+                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning), ("algo", _i32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -365,7 +365,7 @@ class Server:
     """Continuous-batching server over resident hierarchies (host-side requests)."""
 
     def __init__(self, hiers, slots=2, max_batch_queries=1 << 16, memory_budget=None, max_pending=256,
-                 tau=0.0, sigma_to_r=3.0, tuning=None):
+                 tau=0.0, sigma_to_r=3.0, tuning=None, algo="plain"):
         import numpy as np
         self._np = np
         self.hiers = list(hiers)  # keep the hierarchies alive
@@ -373,7 +373,7 @@ class Server:
             memory_budget = 28 * max_batch_queries * max(4, 2 * slots) + 4096
         t = Tuning(0, 1, 16, 1) if tuning is None else (tuning if isinstance(tuning, Tuning) else Tuning(**tuning))
         o = ServerOpts(int(slots), int(max_batch_queries), int(memory_budget), int(max_pending), float(tau),
-                       float(sigma_to_r), t)
+                       float(sigma_to_r), t, ALGOS[algo] if isinstance(algo, str) else int(algo))
         arr = (_vp * len(self.hiers))(*[h.handle for h in self.hiers])
         h = _vp()
         _check(_server_create(arr, len(self.hiers), ctypes.byref(o), ctypes.byref(h)), "pndf_server_create")

@@ -67,13 +67,6 @@ static void fill_view(pndf_hier* h)
     d.logn = m->L;
     d.eps = m->eps;
     d.rho = (float)std::sqrt(2.0 * (double)m->eps / (3.0 * std::sqrt(3.0)));
-    int64_t off = 0;
-    for (int l = 0; l < kMaxLevels + 2; ++l) d.off[l] = 0;
-    for (int l = 1; l <= m->L; ++l) {
-        d.off[l] = off;
-        off += (int64_t)(m->n >> l) * (m->n >> l);
-    }
-    d.off[m->L + 1] = off;
 }
 
 static void mesh_release(pndf_mesh* m)
@@ -280,7 +273,7 @@ pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_b
     if (!h->cluster && (d_bbox_all || d_clu_n || d_clu_e || d_clu_det))
         return invalid("hierarchy has no clusters");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t off = h->dev.off[level];
+    const int64_t off = level_offset(h->dev.logn, level);
     const size_t m = (size_t)(h->mesh->n >> level) * (h->mesh->n >> level);
     hipError_t e = hipSuccess;
     const int side = h->mesh->n >> level;

@@ -6,15 +6,16 @@
 //   - hierarchical: a breadth-limited, depth-first quad-tree descent.  Each level
 //     has a list in LDS; the wave pops up to 64 nodes of the lowest non-empty level
 //     (one per lane), tests the min-max box (and the cluster cut), and pushes the
-//     surviving children with a ballot prefix.  Level-1 nodes push their four
-//     cells into a leaf queue that is drained 64 cells at a time, so the
-//     triangle tests always run with full waves.
-//   - persistent: a fixed grid of workers takes queries from a global counter;
-//     when a query's descent reaches the split level it donates those subtrees
-//     to a global task queue that idle workers steal from.
-// Triangle tests run in float32; a float32 hit is confirmed and its barycentrics
-// recomputed in FP64 from the float32 vertices, so the recovered uv and the term
-// are accurate even for sliver triangles.  Jacobians come from the mesh build
+//     surviving children with a ballot prefix.  A level-1 node tests the triangles
+//     of its 2 x 2 cells from its leaf record.
+//   - persistent: a fixed grid of workers takes chunks of queries (each XCD from
+//     its own share of the spatial order); once the queries run out, idle workers
+//     ask the busy ones for part of their pending subtrees through a global task
+//     queue.
+// Triangle tests run in float32 and only queue the hits; a queued hit is confirmed
+// and its barycentrics recomputed in FP64 from the float32 vertices 64 at a time
+// (one per lane), so the recovered uv and the term are accurate even for sliver
+// triangles while the traversal itself stays small.  Jacobians come from the mesh build
 // (FP64, clamped), never from the hot loop.  Terms are summed exactly (192-bit
 // fixed point at a per-query binary point), so D does not depend on the order in
 // which hits are found: all algorithms, batch compositions and work splits give
@@ -32,6 +33,7 @@ enum { kModeValue = 0, kModeCount = 1, kModeRecord = 2 };
 struct Acc {
     Fix192 d{0, 0, 0};
     uint32_t nodes = 0, cells = 0, clusters = 0, hits = 0;
+    bool donated = false;  // part of the work was handed to other waves (wave-uniform)
 };
 
 struct Rec {  // hit-record cursor (record mode)
@@ -50,26 +52,42 @@ __device__ __forceinline__ double confirm_and_term(const QuerySetup& q, const do
     return hit_term(q, I, J, lev, half, l1, l2, det_used, logn);
 }
 
-// Per-lane hit sink: value/count modes add the term to the exact accumulator at
-// once; record mode also buffers (id, term) until the wave writes its records in
-// lane order.
+// Per-lane hit sink of one hit-processing round: value/count modes add the term to
+// the exact accumulator at once; record mode also keeps (id, term) until the wave
+// writes its records in lane order.
 template <int MODE>
 struct HitSink {
-    static constexpr int kMax = MODE == kModeRecord ? 8 : 1;
-    uint64_t ids[kMax];
-    float terms[kMax];
+    uint64_t id = 0;
+    float term = 0.f;
     int n = 0;
-    __device__ __forceinline__ void put(const QuerySetup& q, Acc& acc, uint64_t id, double t)
+    __device__ __forceinline__ void put(const QuerySetup& q, Acc& acc, uint64_t tid, double t)
     {
         fix_add_term(acc.d, t, q.fexp);
         acc.hits += 1;
-        if (MODE == kModeRecord && n < kMax) {
-            ids[n] = id;
-            terms[n] = (float)t;
+        if (MODE == kModeRecord) {
+            id = tid;
+            term = (float)t;
         }
-        ++n;
+        n = 1;
     }
 };
+
+// Write the wave's records in lane order, never leaving the query's own CSR slot
+// [pos, end).  Every lane must call it.
+template <int MODE>
+__device__ __forceinline__ void flush_records(HitSink<MODE>& hs, Rec& rec)
+{
+    if (MODE == kModeRecord) {
+        const uint64_t b = __ballot(hs.n);
+        const uint64_t at = rec.pos + __popcll(b & ((1ull << lane_id()) - 1ull));
+        if (hs.n && at < rec.end) {
+            rec.ids[at] = hs.id;
+            rec.terms[at] = hs.term;
+        }
+        rec.pos += __popcll(b);
+    }
+    hs.n = 0;
+}
 
 // Exclusive prefix over the wave of a per-lane count in [0, 15], and the total.
 __device__ __forceinline__ int wave_prefix16(int c, int* total)
@@ -80,34 +98,21 @@ __device__ __forceinline__ int wave_prefix16(int c, int* total)
     return __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt) + 8 * __popcll(b3 & lt);
 }
 
-// Write the wave's buffered records in lane order, never leaving the query's own
-// CSR slot [pos, end).  Every lane must call it.
-template <int MODE>
-__device__ __forceinline__ void flush_records(HitSink<MODE>& hs, Rec& rec)
-{
-    if (MODE == kModeRecord) {
-        int total;
-        const int pos = wave_prefix16(hs.n, &total);
-        for (int k = 0; k < hs.n && k < HitSink<MODE>::kMax; ++k) {
-            const uint64_t at = rec.pos + pos + k;
-            if (at < rec.end) {
-                rec.ids[at] = hs.ids[k];
-                rec.terms[at] = hs.terms[k];
-            }
-        }
-        rec.pos += total;
-    }
-    hs.n = 0;
-}
+// ---- float32 triangle tests.  They only decide which triangles are hit; every hit
+// becomes a 32-bit entry of the wave's hit queue, and the FP64 confirmation,
+// barycentrics and term run later with one hit per lane (hit_entry), so the
+// traversal keeps few registers and the FP64 work runs with full waves.
+//   leaf cell    (0 << 30) | m << 3 | c4 << 1 | half   cell c4 = 2 dj + di of level-1 record m
+//   plane cell   (1 << 30) | j << 14 | i << 1 | half   texel cell (i, j), i, j < 8192
+//   cluster      (2 << 30) | lev << 25 | m << 1 | half   node m (Morton) of level lev >= 1
+// A lane's hits are a bit mask over the low bits of its entry code.
+constexpr uint32_t kHitPlane = 1u << 30, kHitCluster = 2u << 30;
 
-// The two triangles of one cell from its four corner normals and clamp bits.
-template <int MODE>
-__device__ __forceinline__ void cell_triangles(const HierDev& H, const QuerySetup& q, int i, int j,
-                                               float2 n0, float2 n1, float2 n2, float2 n3, uint8_t dg,
-                                               Acc& acc, HitSink<MODE>& hs)
+// The two triangles of a cell from its four corner normals and clamp bits: bit 0
+// lower (n0, n1, n2), bit 1 upper (n3, n2, n1).
+__device__ __forceinline__ uint32_t cell_mask(const QuerySetup& q, float rho, float2 n0, float2 n1, float2 n2,
+                                              float2 n3, uint32_t dg)
 {
-    bool hl, hu;
-    float vl[6], vu[6];
     if (dg == 0) {
         // shared offsets and edge functions of the two triangles (they share n1-n2)
         const float q0x = n0.x - q.hx, q0y = n0.y - q.hy, q1x = n1.x - q.hx, q1y = n1.y - q.hy;
@@ -117,52 +122,33 @@ __device__ __forceinline__ void cell_triangles(const HierDev& H, const QuerySetu
         const float c01 = cross2(q0x, q0y, q1x, q1y);
         const float c13 = cross2(q1x, q1y, q3x, q3y);
         const float c32 = cross2(q3x, q3y, q2x, q2y);
-        hl = (c12 >= 0.f && c20 >= 0.f && c01 >= 0.f) || (c12 <= 0.f && c20 <= 0.f && c01 <= 0.f);
-        hu = (c12 <= 0.f && c13 >= 0.f && c32 >= 0.f) || (c12 >= 0.f && c13 <= 0.f && c32 <= 0.f);
-        if (!(hl || hu)) return;
-        vl[0] = n0.x; vl[1] = n0.y; vl[2] = n1.x; vl[3] = n1.y; vl[4] = n2.x; vl[5] = n2.y;
-        vu[0] = n3.x; vu[1] = n3.y; vu[2] = n2.x; vu[3] = n2.y; vu[4] = n1.x; vu[5] = n1.y;
-    } else {
-        const float cx = 0.5f * (n1.x + n2.x), cy = 0.5f * (n1.y + n2.y);
-        if (dg & 1) eqtri_f32(cx, cy, H.rho, vl);
-        else { vl[0] = n0.x; vl[1] = n0.y; vl[2] = n1.x; vl[3] = n1.y; vl[4] = n2.x; vl[5] = n2.y; }
-        if (dg & 2) eqtri_f32(cx, cy, H.rho, vu);
-        else { vu[0] = n3.x; vu[1] = n3.y; vu[2] = n2.x; vu[3] = n2.y; vu[4] = n1.x; vu[5] = n1.y; }
-        hl = tri_hit_f32(vl, q.hx, q.hy);
-        hu = tri_hit_f32(vu, q.hx, q.hy);
-        if (!(hl || hu)) return;
+        const bool hl = (c12 >= 0.f && c20 >= 0.f && c01 >= 0.f) || (c12 <= 0.f && c20 <= 0.f && c01 <= 0.f);
+        const bool hu = (c12 <= 0.f && c13 >= 0.f && c32 >= 0.f) || (c12 >= 0.f && c13 <= 0.f && c32 <= 0.f);
+        return (uint32_t)hl | ((uint32_t)hu << 1);
     }
-    const float2 dd = H.det[(int64_t)j * H.n + i];
-    for (int half = 0; half < 2; ++half) {
-        if (!(half ? hu : hl)) continue;
-        double v[6];
-        if (dg & (1 << half)) {
-            eqtri_f64(0.5 * ((double)n1.x + (double)n2.x), 0.5 * ((double)n1.y + (double)n2.y),
-                      (double)H.rho, v);
-        } else {
-            const float* f = half ? vu : vl;
-            for (int k = 0; k < 6; ++k) v[k] = (double)f[k];
-        }
-        const double t = confirm_and_term(q, v, i, j, 0, half, half ? dd.y : dd.x, H.logn);
-        if (t >= 0.0) hs.put(q, acc, tri_id(0, i, j, half), t);
-    }
+    float vl[6], vu[6];
+    const float cx = 0.5f * (n1.x + n2.x), cy = 0.5f * (n1.y + n2.y);
+    if (dg & 1) eqtri_f32(cx, cy, rho, vl);
+    else { vl[0] = n0.x; vl[1] = n0.y; vl[2] = n1.x; vl[3] = n1.y; vl[4] = n2.x; vl[5] = n2.y; }
+    if (dg & 2) eqtri_f32(cx, cy, rho, vu);
+    else { vu[0] = n3.x; vu[1] = n3.y; vu[2] = n2.x; vu[3] = n2.y; vu[4] = n1.x; vu[5] = n1.y; }
+    return (uint32_t)tri_hit_f32(vl, q.hx, q.hy) | ((uint32_t)tri_hit_f32(vu, q.hx, q.hy) << 1);
 }
 
 // A texel cell tested from the padded normal plane (brute force, tiny footprints).
-template <int MODE>
-__device__ __forceinline__ void plane_cell(const HierDev& H, const QuerySetup& q, int i, int j, Acc& acc,
-                                           HitSink<MODE>& hs)
+__device__ __forceinline__ uint32_t plane_cell_mask(const HierDev& H, const QuerySetup& q, int i, int j,
+                                                    Acc& acc)
 {
     const int w = H.n + 1;
     const float2* p = H.nrm + (int64_t)j * w + i;
-    cell_triangles<MODE>(H, q, i, j, p[0], p[1], p[w], p[w + 1], H.deg[(int64_t)j * H.n + i], acc, hs);
     acc.cells += 1;
+    return cell_mask(q, H.rho, p[0], p[1], p[w], p[w + 1], H.deg[(int64_t)j * H.n + i]);
 }
 
-// The 2 x 2 cells of level-1 node (I, J) (leaf record m), those overlapping the box.
-template <int MODE>
-__device__ __forceinline__ void leaf_quad(const HierDev& H, const QuerySetup& q, int I, int J, uint32_t m,
-                                          Acc& acc, HitSink<MODE>& hs)
+// The 2 x 2 cells of level-1 node (I, J) (leaf record m), those overlapping the box:
+// bit 2 c4 + half for cell c4 = 2 dj + di.
+__device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const QuerySetup& q, int I, int J,
+                                                   uint32_t m, Acc& acc)
 {
     const float4* r = reinterpret_cast<const float4*>(H.quad + m);
     const float4 a = r[0], b = r[1], c = r[2], d = r[3], e = r[4];
@@ -175,24 +161,25 @@ __device__ __forceinline__ void leaf_quad(const HierDev& H, const QuerySetup& q,
     const bool x1 = axis_overlap(2 * I + 1, 1, q.cxlo, q.cxhi, logn);
     const bool y0 = axis_overlap(2 * J, 1, q.cylo, q.cyhi, logn);
     const bool y1 = axis_overlap(2 * J + 1, 1, q.cylo, q.cyhi, logn);
+    uint32_t mask = 0;
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
         const int di = c4 & 1, dj = c4 >> 1;
         if (!((di ? x1 : x0) && (dj ? y1 : y0))) continue;
         acc.cells += 1;
-        cell_triangles<MODE>(H, q, 2 * I + di, 2 * J + dj, t[3 * dj + di], t[3 * dj + di + 1],
-                             t[3 * dj + di + 3], t[3 * dj + di + 4], (uint8_t)(dg4 >> (8 * c4)), acc, hs);
+        mask |= cell_mask(q, H.rho, t[3 * dj + di], t[3 * dj + di + 1], t[3 * dj + di + 3], t[3 * dj + di + 4],
+                          (dg4 >> (8 * c4)) & 0xffu)
+                << (2 * c4);
     }
+    return mask;
 }
 
-// The two cluster triangles of node (lev, I, J) with packed index idx.
-template <int MODE>
-__device__ __forceinline__ void cluster_pair(const HierDev& H, const QuerySetup& q, int lev, int I, int J,
-                                             int64_t idx, Acc& acc, HitSink<MODE>& hs)
+// The two cluster triangles of node idx (level lev): bit half.
+__device__ __forceinline__ uint32_t cluster_mask(const HierDev& H, const QuerySetup& q, int lev, int64_t idx,
+                                                 Acc& acc)
 {
     const float4 a = H.clu_n[2 * idx], b = H.clu_n[2 * idx + 1];
-    const uint8_t dg = H.clu_deg[idx];
-    const float2 dd = H.clu_det[idx];
+    const uint32_t dg = H.clu_deg[idx];
     const float rho = H.rho * (float)(1 << lev);
     const float cx = 0.5f * (a.z + b.x), cy = 0.5f * (a.w + b.y);
     float vl[6], vu[6];
@@ -201,29 +188,98 @@ __device__ __forceinline__ void cluster_pair(const HierDev& H, const QuerySetup&
     if (dg & 2) eqtri_f32(cx, cy, rho, vu);
     else { vu[0] = b.z; vu[1] = b.w; vu[2] = b.x; vu[3] = b.y; vu[4] = a.z; vu[5] = a.w; }
     acc.clusters += 1;
-    for (int half = 0; half < 2; ++half) {
-        const float* f = half ? vu : vl;
-        if (!tri_hit_f32(f, q.hx, q.hy)) continue;
-        double v[6];
-        if (dg & (1 << half))
-            eqtri_f64(0.5 * ((double)a.z + (double)b.x), 0.5 * ((double)a.w + (double)b.y), (double)rho, v);
-        else
-            for (int k = 0; k < 6; ++k) v[k] = (double)f[k];
-        const double t = confirm_and_term(q, v, I, J, lev, half, half ? dd.y : dd.x, H.logn);
-        if (t >= 0.0) hs.put(q, acc, tri_id(lev, I, J, half), t);
-    }
+    return (uint32_t)tri_hit_f32(vl, q.hx, q.hy) | ((uint32_t)tri_hit_f32(vu, q.hx, q.hy) << 1);
 }
 
-// Reserve `count` task slots; returns the first slot or ~0ull if the queue is full.
-__device__ __forceinline__ unsigned long long queue_reserve(const TaskQueue& Q, unsigned count)
+// ---- FP64 stage: one queued hit.
+template <int MODE>
+__device__ __forceinline__ void hit_entry(const HierDev& H, const QuerySetup& q, uint32_t e, Acc& acc,
+                                          HitSink<MODE>& hs)
 {
-    unsigned long long old = __hip_atomic_load(&Q.ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (true) {
-        if (old + count > Q.capacity) return ~0ull;
-        if (__hip_atomic_compare_exchange_strong(&Q.ctl->tail, &old, old + count, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            return old;
+    const int half = (int)(e & 1u);
+    const uint32_t kind = e >> 30;
+    double v[6];
+    float det_used;
+    int I, J, lev;
+    if (kind == (kHitCluster >> 30)) {
+        lev = (int)((e >> 25) & 0xfu);
+        const uint32_t m = (e >> 1) & 0xffffffu;
+        const int64_t idx = level_offset(H.logn, lev) + m;
+        I = (int)morton_compact(m);
+        J = (int)morton_compact(m >> 1);
+        const float4 a = H.clu_n[2 * idx], b = H.clu_n[2 * idx + 1];
+        const float2 dd = H.clu_det[idx];
+        det_used = half ? dd.y : dd.x;
+        if (H.clu_deg[idx] & (1u << half)) {
+            eqtri_f64(0.5 * ((double)a.z + (double)b.x), 0.5 * ((double)a.w + (double)b.y),
+                      (double)(H.rho * (float)(1 << lev)), v);
+        } else if (half == 0) {
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
+        } else {
+            v[0] = b.z; v[1] = b.w; v[2] = b.x; v[3] = b.y; v[4] = a.z; v[5] = a.w;
+        }
+    } else {
+        float2 n0, n1, n2, n3;
+        uint32_t dg;
+        lev = 0;
+        if (kind == 0) {
+            const uint32_t m = (e >> 3) & 0xffffffu;
+            const int c4 = (int)((e >> 1) & 3u), di = c4 & 1, dj = c4 >> 1;
+            const QuadRec* r = H.quad + m;
+            const int k = 3 * dj + di;
+            n0 = r->t[k]; n1 = r->t[k + 1]; n2 = r->t[k + 3]; n3 = r->t[k + 4];
+            dg = r->deg[c4];
+            I = 2 * (int)morton_compact(m) + di;
+            J = 2 * (int)morton_compact(m >> 1) + dj;
+        } else {
+            I = (int)((e >> 1) & 0x1fffu);
+            J = (int)((e >> 14) & 0x1fffu);
+            const int w = H.n + 1;
+            const float2* p = H.nrm + (int64_t)J * w + I;
+            n0 = p[0]; n1 = p[1]; n2 = p[w]; n3 = p[w + 1];
+            dg = H.deg[(int64_t)J * H.n + I];
+        }
+        const float2 dd = H.det[(int64_t)J * H.n + I];
+        det_used = half ? dd.y : dd.x;
+        if (dg & (1u << half)) {
+            eqtri_f64(0.5 * ((double)n1.x + (double)n2.x), 0.5 * ((double)n1.y + (double)n2.y), (double)H.rho, v);
+        } else if (half == 0) {
+            v[0] = n0.x; v[1] = n0.y; v[2] = n1.x; v[3] = n1.y; v[4] = n2.x; v[5] = n2.y;
+        } else {
+            v[0] = n3.x; v[1] = n3.y; v[2] = n2.x; v[3] = n2.y; v[4] = n1.x; v[5] = n1.y;
+        }
     }
+    const double t = confirm_and_term(q, v, I, J, lev, half, det_used, H.logn);
+    if (t >= 0.0) hs.put(q, acc, tri_id(lev, I, J, half), t);
+}
+
+// The wave's hit queue: hq (kHitCap entries in LDS), hn entries (wave-uniform).
+// Each lane's float32 hits wait in a bit mask (entry ebase | bit) until they are
+// queued; the traversal loops run a round of the FP64 stage (hit_round, one call
+// site per kernel so it is inlined once) whenever 64 hits are queued and at the end.
+template <int MODE>
+__device__ __forceinline__ void hit_round(const HierDev& H, const QuerySetup& q, const uint32_t* src, int cnt,
+                                          Acc& acc, Rec& rec)
+{
+    HitSink<MODE> hs;
+    if (lane_id() < cnt) hit_entry<MODE>(H, q, src[lane_id()], acc, hs);
+    flush_records<MODE>(hs, rec);
+    wave_sync();
+}
+
+// Move the lanes' pending hits into the queue (as many as fit, in lane order).
+__device__ __forceinline__ void queue_hits(uint32_t* hq, int& hn, uint32_t& pend, uint32_t ebase)
+{
+    int total;
+    const int pos = wave_prefix16(__popc(pend), &total);
+    if (total == 0) return;
+    int at = hn + pos;
+    while (pend && at < kHitCap) {
+        hq[at++] = ebase | (uint32_t)(__ffs(pend) - 1);
+        pend &= pend - 1u;
+    }
+    hn = min(hn + total, kHitCap);
+    wave_sync();
 }
 
 __device__ __forceinline__ bool in_box(const QuerySetup& q, const float4& bb)
@@ -237,9 +293,11 @@ __device__ __forceinline__ bool in_box(const QuerySetup& q, const float4& bb)
 // its leaf record; any other node loads its (up to) four overlapping children's
 // boxes together and pushes those that contain h.  Roots: every lane with root_ok
 // holds a root of level root_level (level 0: texel cell packed i | j << 16; else a
-// Morton code), box-tested here unless roots_tested.  With SPAWN, a node of level
-// split_level is donated to the task queue instead of expanded (when the queue has
-// room; otherwise it is expanded here).
+// Morton code), box-tested here unless roots_tested.  With SPAWN (persistent
+// workers), while some worker of the plan is idle the wave gives away part of its
+// pending work before each step: half of the items of its highest non-empty list
+// (the largest subtrees it holds), if that level is at least split_level, become
+// tasks of the global queue.  A full queue simply leaves them here.
 template <int MODE, bool CUT, bool SPAWN>
 __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, int root_level,
                         bool root_ok, uint32_t root_item, bool roots_tested, int split_level,
@@ -249,19 +307,22 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
     const int lane = threadIdx.x & 63;
     const int logn = H.logn;
     const float4* __restrict__ boxes = CUT ? H.bbox_all : H.bbox;
-    HitSink<MODE> hs;
-    if (root_level == 0) {
-        if (root_ok) plane_cell<MODE>(H, q, (int)(root_item & 0xffffu), (int)(root_item >> 16), acc, hs);
-        flush_records<MODE>(hs, rec);
-        return;
-    }
+    uint32_t* hq = lists + H.L * kListCap;  // hit queue
+    int hn = 0;                             // queued hits (wave-uniform)
+    uint32_t pend = 0, ebase = 0;           // this lane's float32 hits not yet queued
     uint32_t nonempty = 0;   // bit l: list of level l non-empty (wave-uniform)
     int cntv = 0;            // lane l holds the size of list l
-    {
+    if (root_level == 0) {
+        const int i = (int)(root_item & 0xffffu), j = (int)(root_item >> 16);
+        if (root_ok) {
+            pend = plane_cell_mask(H, q, i, j, acc);
+            ebase = kHitPlane | ((uint32_t)j << 14) | ((uint32_t)i << 1);
+        }
+    } else {
         bool ok = root_ok;
         if (ok && !roots_tested) {
             acc.nodes += 1;
-            ok = in_box(q, boxes[H.off[root_level] + root_item]);
+            ok = in_box(q, boxes[level_offset(H.logn, root_level) + root_item]);
         }
         const uint64_t bal = __ballot(ok);
         const int pos = __popcll(bal & ((1ull << lane) - 1ull));
@@ -271,101 +332,138 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         if (tot) nonempty |= 1u << root_level;
         wave_sync();
     }
-    while (nonempty) {
+    // SPAWN: the starving flag, loaded at the start of a step (its latency hides behind
+    // the step's own loads) and acted on before the next one
+    unsigned hungry = 0;
+    while (true) {
+        queue_hits(hq, hn, pend, ebase);
+        if (hn >= 64 || (hn > 0 && !nonempty)) {
+            // (lanes still holding hits imply a full queue, so they get here too)
+            const int c = min(hn, 64);
+            hn -= c;
+            hit_round<MODE>(H, q, hq + hn, c, acc, rec);
+            continue;
+        }
+        if (!nonempty) break;
+        if (SPAWN && hungry) {
+            // some workers wait for tasks: give away up to half of the highest list,
+            // at most one node per waiting worker
+            const int lh = 31 - __builtin_clz(nonempty);
+            if (lh >= split_level) {
+                const int ch = __builtin_amdgcn_readlane(cntv, lh);
+                // keep at least one item: a lone top item is given only when lower lists hold work
+                int d = min(ch >= 2 ? ch / 2 : ((nonempty & ~(1u << lh)) ? 1 : 0), 64);
+                unsigned long long slot = 0;
+                if (lane == 0 && d > 0) {
+                    const long long waiting = (long long)__hip_atomic_load(&Q.ctl->head, __ATOMIC_RELAXED,
+                                                                           __HIP_MEMORY_SCOPE_AGENT) -
+                                              (long long)__hip_atomic_load(&Q.ctl->tail, __ATOMIC_RELAXED,
+                                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    d = (int)min((long long)d, max(0ll, waiting));
+                    if (d > 0) {
+                        slot = __hip_atomic_fetch_add(&Q.ctl->tail, (unsigned long long)d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        // slots past the capacity are not used: those nodes stay here
+                        const long long room = (long long)Q.capacity - (long long)slot;
+                        const int dd = (int)max(0ll, min((long long)d, room));
+                        if (dd < d) atomicAdd(&Q.ctl->refused, (unsigned long long)(d - dd));
+                        d = dd;
+                        if (d > 0) {
+                            // counted before they become visible
+                            __hip_atomic_fetch_add(&Q.ctl->outstanding, (unsigned long long)d, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            atomicAdd(&Q.ctl->spawned, (unsigned long long)d);
+                        }
+                    }
+                    if (d == 0)
+                        __hip_atomic_store(&Q.ctl->starving[blockIdx.x & (kStarveCopies - 1)].v, 0u,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                d = __builtin_amdgcn_readfirstlane(d);
+                slot = uniform_u64(slot);
+                if (d > 0) {
+                    if (lane < d) {
+                        const uint32_t mm = lists[(lh - 1) * kListCap + ch - 1 - lane];  // the top d items
+                        Q.tasks[slot + lane] = (qidx << 32) | ((unsigned long long)lh << 26) | (unsigned long long)mm;
+                        // the release store orders the task word before its flag
+                        __hip_atomic_store(&Q.flags[slot + lane], Q.ctl->epoch, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (lane == lh) cntv = ch - d;
+                    if (ch == d) nonempty &= ~(1u << lh);
+                    acc.donated = true;
+                    wave_sync();
+                    if (!nonempty) break;  // (cannot happen: one item is always kept)
+                }
+            }
+        }
         const int l = __builtin_ctz(nonempty);
         const int cnt = __builtin_amdgcn_readlane(cntv, l);
         const int k = min(cnt, 64), base = cnt - k;
+        unsigned hv = 0;
+        if (SPAWN && lane == 0 && 31 - __builtin_clz(nonempty) >= split_level)
+            hv = __hip_atomic_load(&Q.ctl->starving[blockIdx.x & (kStarveCopies - 1)].v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         if (lane == l) cntv = base;
         if (base == 0) nonempty &= ~(1u << l);
         uint32_t ch[4];
         int nch = 0;
-        bool give = false;
+        uint32_t tested = 0;  // child boxes read by this lane
         uint32_t m = 0;
         if (lane < k) {
             m = lists[(l - 1) * kListCap + base + lane];
             const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
-            const int64_t idx = H.off[l] + m;
+            const int64_t idx = level_offset(H.logn, l) + m;
             if (CUT && l <= q.l0 && H.clu_e[idx] <= q.t) {
-                cluster_pair<MODE>(H, q, l, I, J, idx, acc, hs);
-            } else if (SPAWN && l == split_level) {
-                give = true;
+                pend = cluster_mask(H, q, l, idx, acc);
+                ebase = kHitCluster | ((uint32_t)l << 25) | (m << 1);
             } else if (l == 1) {
-                leaf_quad<MODE>(H, q, I, J, m, acc, hs);
+                pend = leaf_quad_mask(H, q, I, J, m, acc);
+                ebase = m << 3;
             } else {
                 const int side = 1 << (l - 1);
                 const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
                 const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
                 const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
                 const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
-                const float4* cb = boxes + H.off[l - 1] + 4 * (int64_t)m;
+                const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
                 float4 b0 = make_float4(1.f, 1.f, -1.f, -1.f), b1 = b0, b2 = b0, b3 = b0;
                 if (x0 && y0) b0 = cb[0];
                 if (x1 && y0) b1 = cb[1];
                 if (x0 && y1) b2 = cb[2];
                 if (x1 && y1) b3 = cb[3];
-                acc.nodes += (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
+                tested = (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
                 if (in_box(q, b0)) ch[nch++] = 4 * m;
                 if (in_box(q, b1)) ch[nch++] = 4 * m + 1;
                 if (in_box(q, b2)) ch[nch++] = 4 * m + 2;
                 if (in_box(q, b3)) ch[nch++] = 4 * m + 3;
             }
         }
-        if (SPAWN) {
-            const uint64_t gb = __ballot(give);
-            if (gb) {
-                const unsigned total = (unsigned)__popcll(gb);
-                unsigned long long slot = 0;
-                if (lane == 0) {
-                    // count the tasks before they become visible, then reserve
-                    __hip_atomic_fetch_add(&Q.ctl->outstanding, (unsigned long long)total, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    slot = queue_reserve(Q, total);
-                    if (slot == ~0ull) {
-                        __hip_atomic_fetch_add(&Q.ctl->outstanding, (unsigned long long)(-(long long)total),
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        atomicAdd(&Q.ctl->refused, (unsigned long long)total);
-                    } else {
-                        atomicAdd(&Q.ctl->spawned, (unsigned long long)total);
-                    }
-                }
-                slot = __shfl(slot, 0, 64);
-                if (slot != ~0ull) {
-                    if (give) {
-                        const unsigned long long at = slot + __popcll(gb & ((1ull << lane) - 1ull));
-                        Q.tasks[at] = (qidx << 32) | ((unsigned long long)l << 26) | (unsigned long long)m;
-                        __threadfence();
-                        __hip_atomic_store(&Q.flags[at], Q.ctl->epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                } else if (give) {
-                    // queue full: handle this node here like any other list item
-                    const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
-                    if (l == 1) {
-                        leaf_quad<MODE>(H, q, I, J, m, acc, hs);
-                    } else {
-                        const int side = 1 << (l - 1);
-                        const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
-                        const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
-                        const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
-                        const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
-                        const float4* cb = boxes + H.off[l - 1] + 4 * (int64_t)m;
-                        acc.nodes += (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
-                        if (x0 && y0 && in_box(q, cb[0])) ch[nch++] = 4 * m;
-                        if (x1 && y0 && in_box(q, cb[1])) ch[nch++] = 4 * m + 1;
-                        if (x0 && y1 && in_box(q, cb[2])) ch[nch++] = 4 * m + 2;
-                        if (x1 && y1 && in_box(q, cb[3])) ch[nch++] = 4 * m + 3;
-                    }
-                }
-            }
-        }
-        flush_records<MODE>(hs, rec);
         if (l >= 2) {
             int total;
             const int pos = wave_prefix_small(nch, &total);
+            // A parent whose children would run past the end of the level below goes
+            // back to its own list whole and is expanded again once that list has
+            // drained.  Child positions grow with the lane, so the parents that fit
+            // are a prefix and at least the first one with children always fits.
+            const bool back = nch > 0 && pos + nch > kListCap;
+            const uint64_t bb = __ballot(back);
             uint32_t* dst = lists + (l - 2) * kListCap;
-            for (int c = 0; c < nch; ++c) dst[pos + c] = ch[c];
-            if (lane == l - 1) cntv = total;
-            if (total) nonempty |= 1u << (l - 1);
+            if (!back) {
+                for (int c = 0; c < nch; ++c) dst[pos + c] = ch[c];
+                acc.nodes += tested;
+            }
+            const int pushed = bb ? __builtin_amdgcn_readlane(pos, __builtin_ctzll(bb)) : total;
+            if (lane == l - 1) cntv = pushed;
+            if (pushed) nonempty |= 1u << (l - 1);
+            if (bb) {
+                const int nb = __popcll(bb);
+                if (back) lists[(l - 1) * kListCap + base + __popcll(bb & ((1ull << lane) - 1ull))] = m;
+                if (lane == l) cntv = base + nb;
+                nonempty |= 1u << l;
+            }
         }
+        if (SPAWN) hungry = (unsigned)__builtin_amdgcn_readfirstlane((int)hv);
         wave_sync();
     }
 }
@@ -421,7 +519,7 @@ __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
     if (local >= a.slots) return;
     const int64_t qi = a.slot0 + local;
     const int lane = threadIdx.x & 63;
-    const QuerySetup q = setup_query(a.q[qi], a.s2r, 0.f, H.L, H.eps);
+    const QuerySetup q = uniform_query(setup_query(a.q[qi], a.s2r, 0.f, H.L, H.eps));
     if (!q.valid) { invalid<MODE>(a, qi); return; }
     const int n = H.n, msk = n - 1;
     const int spanx = q.cxhi - q.cxlo + 1, spany = q.cyhi - q.cylo + 1;
@@ -430,16 +528,29 @@ __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
     Acc acc;
     Rec rec{a.ids, a.terms, MODE == kModeRecord ? a.offsets[qi] : 0,
             MODE == kModeRecord ? a.offsets[qi + 1] : 0};
-    HitSink<MODE> hs;
-    for (int base = 0; base < total; base += 64) {
+    __shared__ uint32_t hq_all[4 * kHitCap];
+    uint32_t* hq = hq_all + (threadIdx.x >> 6) * kHitCap;
+    int hn = 0;
+    uint32_t pend = 0, ebase = 0;
+    int base = 0;
+    while (true) {
+        queue_hits(hq, hn, pend, ebase);
+        if (hn >= 64 || (hn > 0 && base >= total)) {
+            const int c = min(hn, 64);
+            hn -= c;
+            hit_round<MODE>(H, q, hq + hn, c, acc, rec);
+            continue;
+        }
+        if (base >= total) break;
         const int idx = base + lane;
         if (idx < total) {
             const int ca = idx % nx, cb = idx / nx;
             const int i = spanx >= n ? ca : ((q.cxlo + ca) & msk);
             const int j = spany >= n ? cb : ((q.cylo + cb) & msk);
-            plane_cell<MODE>(H, q, i, j, acc, hs);
+            pend = plane_cell_mask(H, q, i, j, acc);
+            ebase = kHitPlane | ((uint32_t)j << 14) | ((uint32_t)i << 1);
         }
-        flush_records<MODE>(hs, rec);
+        base += 64;
     }
     finish<MODE>(a, qi, q, acc);
 }
@@ -457,7 +568,7 @@ __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
     const int64_t slot = a.slot0 + local;
     const int64_t qi = a.order ? (int64_t)a.order[slot] : slot;
     uint32_t* lists = lds;
-    const QuerySetup q = setup_query(a.q[qi], a.s2r, CUT ? a.tau : 0.f, H.L, H.eps);
+    const QuerySetup q = uniform_query(setup_query(a.q[qi], a.s2r, CUT ? a.tau : 0.f, H.L, H.eps));
     if (!q.valid) { invalid<MODE>(a, qi); return; }
     Acc acc;
     Rec rec{a.ids, a.terms, MODE == kModeRecord ? a.offsets[qi] : 0,
@@ -493,7 +604,7 @@ __device__ __forceinline__ void acc_atomic_add(Fix192* dst, const Fix192& v)
 }
 
 __global__ void k_persist_reset(QueueCtl* ctl, Fix192* acc, int* fexp, const pndf_query* q,
-                                long long nq, float* out, unsigned epoch)
+                                long long nq, float* out, unsigned epoch, uint32_t* hist, int nb)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (long long i = t; i < nq; i += (long long)gridDim.x * blockDim.x) {
@@ -502,11 +613,14 @@ __global__ void k_persist_reset(QueueCtl* ctl, Fix192* acc, int* fexp, const pnd
         acc[i].w2 = 0;
         fexp[i] = 0;
     }
+    if (hist)
+        for (long long i = t; i < nb; i += (long long)gridDim.x * blockDim.x) hist[i] = 0;
     if (t == 0) {
-        ctl->qhead = 0;
+        for (int x = 0; x < kXcds; ++x) ctl->qhead[x].v = 0;
         ctl->head = 0;
         ctl->tail = 0;
         ctl->outstanding = 0;
+        for (int c = 0; c < kStarveCopies; ++c) ctl->starving[c].v = ctl->done[c].v = 0;
         ctl->spawned = ctl->refused = ctl->spins = 0;
         ctl->epoch = epoch;
         ctl->error = 0;
@@ -516,8 +630,52 @@ __global__ void k_persist_reset(QueueCtl* ctl, Fix192* acc, int* fexp, const pnd
     }
 }
 
+// Queries taken by one worker at a time: a few while the batch is long (fewer
+// counter updates), one at a time for its last part, so no wave ends up holding
+// several large footprints in a row.
+constexpr int kMaxChunk = 4;
+
+__device__ __forceinline__ unsigned long long ld_relaxed(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_relaxed(unsigned long long* p, long long v)
+{
+    __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool all_taken(QueueCtl* ctl, long long nq)
+{
+    for (int x = 0; x < kXcds; ++x)
+        if ((long long)ld_relaxed(&ctl->qhead[x].v) < nq * (x + 1) / kXcds - nq * x / kXcds) return false;
+    return true;
+}
+
+// A unit of work (a query chunk, a task, or a failed attempt at a chunk) is over.
+// The decrement that leaves nothing outstanding after every query was taken ends
+// the run: it raises the done flags the waiting workers poll.  (Units only start
+// while queries remain or from inside a running unit, so the count cannot leave
+// zero for real work once every query is taken.)
+__device__ __forceinline__ void unit_done(QueueCtl* ctl, long long nq)
+{
+    const unsigned long long old = __hip_atomic_fetch_add(&ctl->outstanding, (unsigned long long)-1ll,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 1 && all_taken(ctl, nq))
+        for (int c = 0; c < kStarveCopies; ++c)
+            __hip_atomic_store(&ctl->done[c].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Worker waves of a persistent run.  A wave takes chunks of consecutive queries of
+// the processing order, from its XCD's eighth of the order first (shrinking towards
+// single queries as a share runs out, so the last ones spread over all workers).
+// Once no query is left it takes a ticket of the task queue and waits for that
+// slot's task (a subtree some busy wave gave away), polling only that slot's flag
+// with a short exponential back-off and, now and then, whether the run is over
+// (every query taken and nothing outstanding).
+// (5 waves per SIMD fit without spilling vector registers)
 template <bool CUT>
-__global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_persist(HierDev H, PersistArgs pa)
 {
     extern __shared__ uint32_t lds[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -526,128 +684,169 @@ __global__ __launch_bounds__(256) void k_persist(HierDev H, PersistArgs pa)
     const long long nq = ctl->nq;
     const pndf_query* qs = ctl->q;
     const unsigned epoch = ctl->epoch;
+    // worker waves per XCD (block b runs on XCD b mod 8)
+    const long long xworkers = max(1ll, (long long)gridDim.x * (blockDim.x >> 6) / kXcds);
+    const int home = blockIdx.x & (kXcds - 1);
     Rec rec{nullptr, nullptr, 0, 0};
-    const unsigned long long kSpinLimit = 1ull << 24;  // consecutive idle polls before giving up
-    unsigned long long idle = 0, spins = 0;
+    // a wave that has waited pa.wait_ticks of the constant-rate clock without any
+    // work arriving gives up and flags the run (a broken count would otherwise hang)
+    long long idle_since = -1;
+    int backoff = 1;
+    unsigned long long spins = 0;
+    long long qb = 0, qe = 0;  // the wave's current chunk of query slots
+    long long ticket = -1;     // the wave's place in the task queue while it waits for a task
+    int polls = 0;
     while (true) {
-        // 1) stolen work first: a published task below `tail`
         long long task_slot = -1;
-        long long query = -1;
-        if (lane == 0) {
-            unsigned long long h = __hip_atomic_load(&ctl->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (true) {
-                const unsigned long long t = __hip_atomic_load(&ctl->tail, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
-                if (h >= t) break;
-                if (__hip_atomic_compare_exchange_strong(&ctl->head, &h, h + 1, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    task_slot = (long long)h;
-                    break;
-                }
-            }
-            // 2) a new query, counted as outstanding before it is taken
-            if (task_slot < 0 && (long long)__hip_atomic_load(&ctl->qhead, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT) < nq) {
-                __hip_atomic_fetch_add(&ctl->outstanding, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long qn = __hip_atomic_fetch_add(&ctl->qhead, 1ull, __ATOMIC_RELAXED,
-                                                                     __HIP_MEMORY_SCOPE_AGENT);
-                if ((long long)qn < nq) {
-                    query = (long long)qn;
-                } else {
-                    __hip_atomic_fetch_add(&ctl->outstanding, (unsigned long long)-1ll, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-        }
-        task_slot = __shfl(task_slot, 0, 64);
-        query = __shfl(query, 0, 64);
-        if (task_slot < 0 && query < 0) {
-            // nothing available now: finished once every query is taken and nothing
-            // is outstanding, otherwise wait for donated tasks
-            int done = 0;
+        if (qb >= qe) {
+            long long nb = -1, ne = -1;
             if (lane == 0) {
-                const unsigned long long qh = __hip_atomic_load(&ctl->qhead, __ATOMIC_SEQ_CST,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long os = __hip_atomic_load(&ctl->outstanding, __ATOMIC_SEQ_CST,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                done = ((long long)qh >= nq && os == 0) ? 1 : 0;
-                ++spins;
-                if (!done && ++idle > kSpinLimit) {
-                    atomicOr(&ctl->error, 1u);
-                    done = 1;
+                if (ticket < 0) {
+                    // a chunk of queries, counted as outstanding before it is taken: from
+                    // this XCD's share of the processing order first (neighbouring queries,
+                    // so the XCD's L2 holds their nodes), then from the other shares
+                    for (int k = 0; nb < 0 && k < kXcds; ++k) {
+                        const int x = (home + k) & (kXcds - 1);
+                        const long long lo = nq * x / kXcds, len = nq * (x + 1) / kXcds - lo;
+                        const long long qh = (long long)ld_relaxed(&ctl->qhead[x].v);
+                        if (qh >= len) continue;
+                        const long long c = max(1ll, min((long long)kMaxChunk, (len - qh) / (64 * xworkers)));
+                        add_relaxed(&ctl->outstanding, 1);
+                        const long long qn = (long long)__hip_atomic_fetch_add(
+                            &ctl->qhead[x].v, (unsigned long long)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (qn < len) {
+                            nb = lo + qn;
+                            ne = lo + min(qn + c, len);
+                        } else {
+                            unit_done(ctl, nq);
+                        }
+                    }
+                    if (nb < 0) {
+                        // no query left: take a ticket (the next task slot in order) and tell
+                        // the busy waves that workers are waiting
+                        ticket = (long long)__hip_atomic_fetch_add(&ctl->head, 1ull, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        polls = 0;
+                        for (int c = 0; c < kStarveCopies; ++c)
+                            __hip_atomic_store(&ctl->starving[c].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                // a relaxed poll (an acquire load would invalidate this CU's L1 under the
+                // busy waves at every poll); the acquire fence only once the task is there
+                if (nb < 0 && ticket >= 0 && ticket < (long long)pa.Q.capacity &&
+                    __hip_atomic_load(&pa.Q.flags[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    task_slot = ticket;
+                    ticket = -1;
                 }
             }
-            done = __shfl(done, 0, 64);
-            if (done) break;
-            __builtin_amdgcn_s_sleep(8);
-            continue;
+            task_slot = (long long)uniform_u64((unsigned long long)task_slot);
+            nb = (long long)uniform_u64((unsigned long long)nb);
+            ne = (long long)uniform_u64((unsigned long long)ne);
+            ticket = (long long)uniform_u64((unsigned long long)ticket);
+            if (task_slot < 0 && nb < 0) {
+                // waiting for the ticket's task (a slot past the capacity never gets one);
+                // the run is over once every query is taken and nothing is outstanding
+                int done = 0;
+                if (lane == 0) {
+                    ++spins;
+                    done = __hip_atomic_load(&ctl->done[home].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+                    if (!done && (++polls & 63) == 0) {
+                        // now and then the full condition too, and a reminder to the busy waves
+                        done = (all_taken(ctl, nq) && ld_relaxed(&ctl->outstanding) == 0) ? 1 : 0;
+                        if (!done)
+                            for (int c = 0; c < kStarveCopies; ++c)
+                                __hip_atomic_store(&ctl->starving[c].v, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    const long long now = wall_clock64();
+                    if (idle_since < 0) idle_since = now;
+                    if (!done && now - idle_since > pa.wait_ticks) {
+                        atomicOr(&ctl->error, 1u);
+                        done = 1;
+                    }
+                }
+                done = __builtin_amdgcn_readfirstlane(done);
+                if (done) break;
+                for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(16);
+                backoff = min(backoff * 2, 8);
+                continue;
+            }
+            idle_since = -1;
+            backoff = 1;
+            if (nb >= 0) {
+                qb = nb;
+                qe = ne;
+            }
         }
-        idle = 0;
-        Acc acc;
+        // one work item: a stolen subtree, or the next query of the chunk
+        long long qi;
+        int lev;
+        uint32_t item;
+        bool root_ok, tested;
         if (task_slot >= 0) {
-            // wait for the donor to publish the slot; never use an unpublished or
+            // the slot is published (its flag carries this run's epoch); never use a
             // malformed task word
             unsigned long long word = 0;
             int ok = 0;
             if (lane == 0) {
-                unsigned long long w = 0;
+                word = pa.Q.tasks[task_slot];
+                const long long wq = (long long)(word >> 32);
+                const int wl = (int)((word >> 26) & 0x3fu);
+                const uint64_t wm = word & 0x3ffffffu;
                 ok = 1;
-                while (__hip_atomic_load(&pa.Q.flags[task_slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
-                       epoch) {
-                    if (++w > kSpinLimit) {
-                        atomicOr(&ctl->error, 2u);
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (ok) {
-                    word = pa.Q.tasks[task_slot];
-                    const long long wq = (long long)(word >> 32);
-                    const int wl = (int)((word >> 26) & 0x3fu);
-                    const uint64_t wm = word & 0x3ffffffu;
-                    if (wq >= nq || wl < 1 || wl > H.L ||
-                        wm >= (uint64_t)(H.n >> wl) * (uint64_t)(H.n >> wl)) {
-                        atomicOr(&ctl->error, 4u);
-                        ok = 0;
-                    }
+                if (wq >= nq || wl < 1 || wl > H.L || wm >= (uint64_t)(H.n >> wl) * (uint64_t)(H.n >> wl)) {
+                    atomicOr(&ctl->error, 4u);
+                    ok = 0;
                 }
             }
-            ok = __shfl(ok, 0, 64);
-            word = __shfl(word, 0, 64);
-            if (ok) {
-                const long long qi = (long long)(word >> 32);
-                const int lev = (int)((word >> 26) & 0x3fu);
-                const uint32_t item = (uint32_t)(word & 0x3ffffffu);
-                const QuerySetup q = setup_query(qs[qi], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps);
-                descend<kModeValue, CUT, false>(H, q, lists, lev, lane == 0, item, true, 0, 0, pa.Q, acc, rec);
-                const Fix192 d = wave_sum_fix(acc.d);
-                if (lane == 0) acc_atomic_add(&pa.acc[qi], d);
+            ok = __builtin_amdgcn_readfirstlane(ok);
+            word = uniform_u64(word);
+            if (!ok) {
+                if (lane == 0) unit_done(ctl, nq);
+                continue;
             }
-            if (lane == 0) {
-                __threadfence();
-                __hip_atomic_fetch_add(&ctl->outstanding, (unsigned long long)-1ll, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
+            qi = (long long)(word >> 32);
+            lev = (int)((word >> 26) & 0x3fu);
+            item = (uint32_t)(word & 0x3ffffffu);
+            root_ok = lane == 0;
+            tested = true;
         } else {
-            const QuerySetup q = setup_query(qs[query], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps);
-            if (q.valid) {
-                bool ok;
-                const uint32_t item = root_item(H, q, &ok);
-                if (q.l0 > pa.split_level)
-                    descend<kModeValue, CUT, true>(H, q, lists, q.l0, ok, item, false, pa.split_level,
-                                                   (unsigned long long)query, pa.Q, acc, rec);
+            qi = pa.order ? (long long)pa.order[qb] : qb;
+            qi = (long long)uniform_u64((unsigned long long)qi);
+            ++qb;
+            lev = -1;  // set below from the query
+            item = 0;
+            root_ok = false;
+            tested = false;
+        }
+        const QuerySetup q = uniform_query(setup_query(qs[qi], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps));
+        Acc acc;
+        if (lev < 0) {
+            lev = q.l0;
+            item = root_item(H, q, &root_ok);
+        }
+        // a query whose levels are all below split_level never donates; a stolen
+        // subtree may be split again
+        if (q.valid)
+            descend<kModeValue, CUT, true>(H, q, lists, lev, root_ok, item, tested, pa.split_level,
+                                           (unsigned long long)qi, pa.Q, acc, rec);
+        const Fix192 d = wave_sum_fix(acc.d);
+        if (lane == 0) {
+            if (task_slot >= 0) {
+                acc_atomic_add(&pa.acc[qi], d);
+            } else {
+                pa.fexp[qi] = q.valid ? q.fexp : 0x7fffffff;
+                if (acc.donated)
+                    acc_atomic_add(&pa.acc[qi], d);  // tasks of this query add theirs too
                 else
-                    descend<kModeValue, CUT, false>(H, q, lists, q.l0, ok, item, false, 0, 0, pa.Q, acc, rec);
+                    pa.acc[qi] = d;                  // the only contribution
             }
-            const Fix192 d = wave_sum_fix(acc.d);
-            if (lane == 0) {
-                pa.fexp[query] = q.valid ? q.fexp : 0x7fffffff;
-                acc_atomic_add(&pa.acc[query], d);
-                __threadfence();
-                __hip_atomic_fetch_add(&ctl->outstanding, (unsigned long long)-1ll, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
+        }
+        if (task_slot >= 0 || qb >= qe) {
+            // the task, or the last query of the chunk, is finished.  No fence: the count
+            // only decides when workers stop; the sums are read after the kernel ends.
+            if (lane == 0) unit_done(ctl, nq);
         }
     }
     if (lane == 0 && spins) atomicAdd(&ctl->spins, spins);
@@ -699,8 +898,8 @@ __global__ void k_order_zero(uint32_t* hist, int nb)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) hist[i] = 0;
 }
 
-__global__ void k_order_hist(const pndf_query* __restrict__ q, int64_t nq, int n, int bshift,
-                             uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
+__device__ __forceinline__ void order_hist(const pndf_query* __restrict__ q, int64_t nq, int n, int bshift,
+                                           uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -745,8 +944,8 @@ __global__ __launch_bounds__(1024) void k_order_scan(uint32_t* hist, int nb)
     }
 }
 
-__global__ void k_order_scatter(const uint32_t* __restrict__ key, int64_t nq, uint32_t* __restrict__ cursor,
-                                uint32_t* __restrict__ order)
+__device__ __forceinline__ void order_scatter(const uint32_t* __restrict__ key, int64_t nq,
+                                              uint32_t* __restrict__ cursor, uint32_t* __restrict__ order)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -755,14 +954,46 @@ __global__ void k_order_scatter(const uint32_t* __restrict__ key, int64_t nq, ui
     }
 }
 
+__global__ void k_order_hist(const pndf_query* __restrict__ q, int64_t nq, int n, int bshift,
+                             uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
+{
+    order_hist(q, nq, n, bshift, key, hist);
+}
+
+__global__ void k_order_scatter(const uint32_t* __restrict__ key, int64_t nq, uint32_t* __restrict__ cursor,
+                                uint32_t* __restrict__ order)
+{
+    order_scatter(key, nq, cursor, order);
+}
+
+// The same two passes for a persistent plan, reading the batch from its control
+// block (so the launch graph needs no per-run arguments for them).
+__global__ void k_porder_hist(const QueueCtl* ctl, int n, int bshift, uint32_t* __restrict__ key,
+                              uint32_t* __restrict__ hist)
+{
+    order_hist(ctl->q, ctl->nq, n, bshift, key, hist);
+}
+
+__global__ void k_porder_scatter(const QueueCtl* ctl, const uint32_t* __restrict__ key,
+                                 uint32_t* __restrict__ cursor, uint32_t* __restrict__ order)
+{
+    order_scatter(key, ctl->nq, cursor, order);
+}
+
 }  // namespace
+
+void order_shape(int logn, int* nb, int* bshift)
+{
+    const int bits = logn < kOrderBits ? logn : kOrderBits;
+    *nb = 1 << (2 * bits);
+    *bshift = logn - bits;
+}
 
 hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s)
 {
     *order = nullptr;
-    const int bits = H.logn < kOrderBits ? H.logn : kOrderBits;
-    const int nb = 1 << (2 * bits);
-    const int bshift = H.logn - bits;
+    int nb, bshift;
+    order_shape(H.logn, &nb, &bshift);
     uint32_t* buf = nullptr;  // order[nq] | key[nq] | hist[nb]
     hipError_t e = hipMallocAsync((void**)&buf, sizeof(uint32_t) * (2 * (size_t)nq + nb), s);
     if (e != hipSuccess) return e;
@@ -811,6 +1042,8 @@ static void reset_params(PersistPlan& P, const pndf_query* q, long long nq, floa
     P.rargs[4] = &P.rnq;
     P.rargs[5] = &P.rout;
     P.rargs[6] = &P.epoch;
+    P.rargs[7] = &P.ohist;
+    P.rargs[8] = &P.order_nb;
     P.reset.func = (void*)k_persist_reset;
     P.reset.gridDim = dim3((unsigned)std::min<long long>(1024, (P.max_nq + 255) / 256 + 1));
     P.reset.blockDim = dim3(256);
@@ -819,18 +1052,70 @@ static void reset_params(PersistPlan& P, const pndf_query* q, long long nq, floa
     P.reset.extra = nullptr;
 }
 
-hipError_t persist_graph_build(const HierDev& H, PersistPlan& P)
+static unsigned order_grid(long long nq)
+{
+    return (unsigned)std::min<long long>(2048, (nq + 255) / 256 + 1);
+}
+
+// Kernel-node parameters of the three order passes (spatial order of the batch).
+static void order_params(PersistPlan& P, hipKernelNodeParams* hist, hipKernelNodeParams* scan,
+                         hipKernelNodeParams* scat)
+{
+    P.hargs[0] = &P.ctl;
+    P.hargs[1] = &P.on;
+    P.hargs[2] = &P.order_bshift;
+    P.hargs[3] = &P.okey;
+    P.hargs[4] = &P.ohist;
+    P.sargs[0] = &P.ohist;
+    P.sargs[1] = &P.order_nb;
+    P.cargs[0] = &P.ctl;
+    P.cargs[1] = &P.okey;
+    P.cargs[2] = &P.ohist;
+    P.cargs[3] = &P.order;
+    *hist = hipKernelNodeParams{};
+    hist->func = (void*)k_porder_hist;
+    hist->gridDim = dim3(order_grid(P.max_nq));
+    hist->blockDim = dim3(256);
+    hist->kernelParams = P.hargs;
+    *scan = hipKernelNodeParams{};
+    scan->func = (void*)k_order_scan;
+    scan->gridDim = dim3(1);
+    scan->blockDim = dim3(1024);
+    scan->kernelParams = P.sargs;
+    *scat = hipKernelNodeParams{};
+    scat->func = (void*)k_porder_scatter;
+    scat->gridDim = dim3(order_grid(P.max_nq));
+    scat->blockDim = dim3(256);
+    scat->kernelParams = P.cargs;
+}
+
+void persist_prepare(const HierDev& H, PersistPlan& P)
 {
     P.H = H;
     P.pa.Q.ctl = P.ctl;
     P.pa.Q.tasks = P.tasks;
     P.pa.Q.flags = P.flags;
     P.pa.Q.capacity = P.capacity;
+    P.pa.order = P.order;
     P.pa.acc = P.acc;
     P.pa.fexp = P.fexp;
     P.pa.tau = P.tau;
     P.pa.s2r = P.s2r;
     P.pa.split_level = P.split_level;
+    P.pa.wait_ticks = P.wait_ticks;
+    P.okey = P.ohist = nullptr;
+    if (P.order) {
+        P.okey = P.order + P.max_nq;
+        P.ohist = P.okey + P.max_nq;
+    }
+    P.on = H.n;
+}
+
+hipError_t persist_graph_build(const HierDev& H, PersistPlan& P)
+{
+    persist_prepare(H, P);
+    hipKernelNodeParams ohist{}, oscan{}, oscat{};
+    if (P.order) order_params(P, &ohist, &oscan, &oscat);
     reset_params(P, nullptr, 0, nullptr);
     P.wargs[0] = &P.H;
     P.wargs[1] = &P.pa;
@@ -852,9 +1137,16 @@ hipError_t persist_graph_build(const HierDev& H, PersistPlan& P)
     fin.kernelParams = P.fargs;
     fin.extra = nullptr;
     hipError_t e = hipGraphCreate(&P.graph, 0);
-    hipGraphNode_t nw, nf;
+    hipGraphNode_t nw = nullptr, nf = nullptr, nh = nullptr, ns = nullptr, nc = nullptr;
     if (e == hipSuccess) e = hipGraphAddKernelNode(&P.reset_node, P.graph, nullptr, 0, &P.reset);
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&nw, P.graph, &P.reset_node, 1, &work);
+    hipGraphNode_t before_work = P.reset_node;
+    if (P.order) {
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&nh, P.graph, &P.reset_node, 1, &ohist);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&ns, P.graph, &nh, 1, &oscan);
+        if (e == hipSuccess) e = hipGraphAddKernelNode(&nc, P.graph, &ns, 1, &oscat);
+        before_work = nc;
+    }
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&nw, P.graph, &before_work, 1, &work);
     if (e == hipSuccess) e = hipGraphAddKernelNode(&nf, P.graph, &nw, 1, &fin);
     if (e == hipSuccess) e = hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0);
     return e;
@@ -871,7 +1163,14 @@ hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float*
         return e;
     }
     hipLaunchKernelGGL(k_persist_reset, P.reset.gridDim, P.reset.blockDim, 0, s, P.ctl, P.acc, P.fexp,
-                       q, nq, out, P.epoch);
+                       q, nq, out, P.epoch, P.ohist, P.order_nb);
+    if (P.order) {
+        hipLaunchKernelGGL(k_porder_hist, dim3(order_grid(P.max_nq)), dim3(256), 0, s, P.ctl, P.on,
+                           P.order_bshift, P.okey, P.ohist);
+        hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, P.ohist, P.order_nb);
+        hipLaunchKernelGGL(k_porder_scatter, dim3(order_grid(P.max_nq)), dim3(256), 0, s, P.ctl, P.okey,
+                           P.ohist, P.order);
+    }
     const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(P.H.L);
     if (P.tau > 0.f)
         hipLaunchKernelGGL(k_persist<true>, dim3((unsigned)P.blocks), dim3(256), lds, s, P.H, P.pa);

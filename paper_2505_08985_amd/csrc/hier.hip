@@ -348,7 +348,7 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
     }
     auto out_for = [&](int level) {
         LevelOut o;
-        const int64_t off = H.off[level];
+        const int64_t off = level_offset(H.logn, level);
         o.bbox = h->bbox + off;
         o.bbox_all = h->cluster ? h->bbox_all + off : nullptr;
         o.clu_n = h->cluster ? h->clu_n + 2 * off : nullptr;
@@ -363,7 +363,7 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
     err = hipGetLastError();
     for (int level = 2; level <= H.L && err == hipSuccess; ++level) {
         const int64_t m = (int64_t)(n >> level) * (n >> level);
-        const int64_t coff = H.off[level - 1];
+        const int64_t coff = level_offset(H.logn, level - 1);
         const double* cm = mom[(level - 2) & 1];
         double* om = mom[(level - 1) & 1];
         hipLaunchKernelGGL(k_level_up, dim3((unsigned)((m + bs - 1) / bs)), dim3(bs), 0, s, H,

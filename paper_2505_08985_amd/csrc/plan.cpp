@@ -31,6 +31,16 @@ static int compute_units()
     return cus;
 }
 
+// Ticks of the device's constant-rate clock in `seconds` (100 MHz if unknown).
+static long long wall_ticks(double seconds)
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;
+    return (long long)(seconds * 1e3 * (double)khz);
+}
+
 static void plan_free(pndf_plan* p)
 {
     if (!p) return;
@@ -42,6 +52,7 @@ static void plan_free(pndf_plan* p)
     (void)hipFree(P.fexp);
     (void)hipFree(P.tasks);
     (void)hipFree(P.flags);
+    (void)hipFree(P.order);
     delete p;
 }
 
@@ -54,8 +65,8 @@ extern "C" {
 pndf_status pndf_default_tuning(const pndf_hier* h, pndf_tuning* out)
 {
     if (!h || !out) return plan_invalid("NULL argument");
-    out->blocks_per_cu = 2;
-    out->split_level = std::min(h->L, 5);
+    out->blocks_per_cu = 4;
+    out->split_level = std::min(h->L, 4);
     out->queue_factor = 16;
     out->use_graph = 1;
     return PNDF_OK;
@@ -95,6 +106,9 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     P.capacity = (unsigned long long)max_nq * (unsigned long long)t.queue_factor;
     P.blocks = compute_units() * t.blocks_per_cu;
     P.split_level = t.split_level;
+    // no single piece of undonatable work takes this long; a worker that waits
+    // longer reports an error instead of hanging
+    P.wait_ticks = wall_ticks(30.0);
     P.tau = o.tau;
     P.s2r = o.sigma_to_r;
     hipError_t e = hipMalloc(&P.ctl, sizeof(QueueCtl));
@@ -102,6 +116,11 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     if (e == hipSuccess) e = hipMalloc(&P.fexp, sizeof(int) * (size_t)max_nq);
     if (e == hipSuccess) e = hipMalloc(&P.tasks, sizeof(unsigned long long) * P.capacity);
     if (e == hipSuccess) e = hipMalloc(&P.flags, sizeof(unsigned) * P.capacity);
+    if (e == hipSuccess && !(o.flags & PNDF_EVAL_INPUT_ORDER)) {
+        // workers take the queries in spatial (Morton bucket) order
+        order_shape(h->dev.logn, &P.order_nb, &P.order_bshift);
+        e = hipMalloc(&P.order, sizeof(uint32_t) * (2 * (size_t)max_nq + (size_t)P.order_nb));
+    }
     // flags start at 0; the first run publishes with epoch 1
     if (e == hipSuccess) e = hipMemsetAsync(P.flags, 0, sizeof(unsigned) * P.capacity, (hipStream_t)stream);
     if (e == hipSuccess) e = hipMemsetAsync(P.ctl, 0, sizeof(QueueCtl), (hipStream_t)stream);
@@ -111,18 +130,7 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
         plan_free(p);
         return hip_fail(e, "pndf_plan_create");
     }
-    if (!t.use_graph) {
-        P.H = h->dev;
-        P.pa.Q.ctl = P.ctl;
-        P.pa.Q.tasks = P.tasks;
-        P.pa.Q.flags = P.flags;
-        P.pa.Q.capacity = P.capacity;
-        P.pa.acc = P.acc;
-        P.pa.fexp = P.fexp;
-        P.pa.tau = P.tau;
-        P.pa.s2r = P.s2r;
-        P.pa.split_level = P.split_level;
-    }
+    if (!t.use_graph) persist_prepare(h->dev, P);
     *out = p;
     return PNDF_OK;
 }
@@ -176,8 +184,10 @@ pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
     pndf_tuning bt;
     pndf_default_tuning(h, &bt);
     pndf_status st = PNDF_OK;
-    const int lo = std::min(3, h->L), hi = std::min(8, h->L);
-    for (int bpc = 1; bpc <= 4 && st == PNDF_OK; ++bpc) {
+    const int lo = std::min(2, h->L), hi = std::min(8, h->L);
+    static const int kBpc[] = {1, 2, 4, 6, 8};
+    for (int bpc : kBpc) {
+        if (st != PNDF_OK) break;
         for (int sl = lo; sl <= hi && st == PNDF_OK; ++sl) {
             pndf_tuning t{bpc, sl, 16, 1};
             pndf_plan* p = nullptr;
@@ -185,7 +195,7 @@ pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
             if (st != PNDF_OK) break;
             st = pndf_plan_eval(p, d_q, nq, d_out, stream);  // warm-up
             float ms_best = 1e30f;
-            for (int r = 0; r < 3 && st == PNDF_OK; ++r) {
+            for (int r = 0; r < 2 && st == PNDF_OK; ++r) {
                 (void)hipEventRecord(e0, s);
                 st = pndf_plan_eval(p, d_q, nq, d_out, stream);
                 (void)hipEventRecord(e1, s);

@@ -15,10 +15,22 @@ namespace pndf {
 
 constexpr int kMaxLevels = 13;   // N <= 8192
 constexpr int kWave = 64;
-constexpr int kListCap = 256;    // per-level traversal list (64 parents x 4 children)
+#ifndef PNDF_LIST_CAP
+#define PNDF_LIST_CAP 128
+#endif
+// Per-level traversal list entries.  A wave expands up to 64 parents at a time;
+// parents whose children do not fit wait in their own list, so any capacity of at
+// least 16 (the roots of a query) is correct; smaller lists mean more waves per CU.
+constexpr int kListCap = PNDF_LIST_CAP;
+static_assert(kListCap >= 16, "the list of the entry level holds up to 16 roots");
 
-// 32-bit LDS words per wavefront of the descent: one node list per level 1..L.
-__host__ __device__ inline size_t wave_lds_words(int L) { return (size_t)L * kListCap; }
+// Hit queue of a wavefront: float32 hits wait here for the FP64 stage, which takes
+// them 64 at a time (fewer than 64 wait between steps; one step adds at most 64 x 8).
+constexpr int kHitCap = 128;
+
+// 32-bit LDS words per wavefront of the descent: one node list per level 1..L, then
+// the hit queue.
+__host__ __device__ inline size_t wave_lds_words(int L) { return (size_t)L * kListCap + kHitCap; }
 
 // Level-1 leaf record: the 3 x 3 texel normals of a 2 x 2 cell block (row-major,
 // texel (2I + x, 2J + y) at t[3 y + x], periodic) and the clamp bits of its four
@@ -32,7 +44,7 @@ static_assert(sizeof(QuadRec) == 80, "QuadRec is five 16-byte words");
 
 // Device-side view of a mesh + hierarchy, passed to kernels by value.  Every
 // per-node array is stored per level in Morton (Z) order: node (I, J) of level l at
-// off[l] + morton(I, J), so the four children of node m are 4m .. 4m + 3.
+// level_offset(logn, l) + morton(I, J), so the four children of node m are 4m .. 4m + 3.
 struct HierDev {
     const float2* nrm;      // (n+1) x (n+1) padded texel normals (last row/column wrap)
     const uint8_t* deg;     // n x n clamp bits (bit0 lower, bit1 upper)
@@ -47,8 +59,14 @@ struct HierDev {
     int n, L, logn;
     float eps;
     float rho;              // circumradius of the clamp replacement triangle (area eps / 2)
-    int64_t off[kMaxLevels + 2]; // first node of level l in the packed arrays (off[1] = 0)
 };
+
+// First node of level l (1 <= l <= logn + 1) in the packed per-level arrays: the
+// levels below hold sum_{k=1}^{l-1} (n / 2^k)^2 = (n^2 - (n / 2^(l-1))^2) / 3 nodes.
+__host__ __device__ __forceinline__ int64_t level_offset(int logn, int l)
+{
+    return ((int64_t)1 << (2 * logn)) / 3 - ((int64_t)1 << (2 * (logn - l + 1))) / 3;
+}
 
 // ---- exact accumulation: unsigned 192-bit fixed point w0 + 2^64 w1 + 2^128 w2, in
 // units of 2^fexp.  Adding the float32 terms of a query in any order gives the same
@@ -58,16 +76,29 @@ struct Fix192 {
     uint64_t w0, w1, w2;
 };
 
-// Global task queue of the persistent traversal.  Slots are reserved by a CAS on
-// `tail` (never beyond capacity), written, then published by storing the launch's
-// epoch into the slot flag; takers claim slots below `tail` by a CAS on `head`
-// and wait for the flag.  `outstanding` counts queries and tasks taken but not
+// Global task queue of the persistent traversal, a ticket queue: a worker with no
+// query left takes a ticket (fetch-add on `head`) and waits for that slot only; a
+// busy wave that sees workers waiting (head > tail) reserves slots with a fetch-add
+// on `tail`, writes the tasks and publishes each by storing the launch's epoch into
+// its flag.  No CAS retry loop, so thousands of waiting workers do not serialise on
+// one word.  `outstanding` counts query chunks and tasks taken or published but not
 // finished; a worker exits once every query is taken and nothing is outstanding.
+// Every word of the control block that many waves touch sits on its own 128-byte
+// line, so the pollers of one do not queue behind the users of another.
+constexpr int kStarveCopies = 8;  // replicas of the starving flag (by block index)
+constexpr int kXcds = 8;          // workgroups are dispatched to the 8 XCDs round-robin
 struct QueueCtl {
-    unsigned long long qhead;       // next query index
-    unsigned long long head, tail;  // task slots taken / reserved
-    unsigned long long outstanding;
-    unsigned long long spawned, refused, spins;  // statistics
+    struct alignas(128) Head {
+        unsigned long long v;
+    } qhead[kXcds];                               // next query slot of each XCD's share of the order
+    alignas(128) unsigned long long head;         // tickets handed out (task slots waited for)
+    alignas(128) unsigned long long tail;         // task slots reserved by donors
+    alignas(128) unsigned long long outstanding;  // query chunks and tasks taken or published, not finished
+    struct alignas(128) Flag {
+        unsigned int v;
+    } starving[kStarveCopies];                    // set by idle workers, cleared by a donation
+    Flag done[kStarveCopies];                     // set once every query is taken and nothing is outstanding
+    alignas(128) unsigned long long spawned, refused, spins;  // statistics
     unsigned int epoch, error;      // error bit0: idle wait gave up, bit1: slot wait gave up, bit2: bad task
     const pndf_query* q;
     float* out;
@@ -76,17 +107,19 @@ struct QueueCtl {
 
 struct TaskQueue {
     QueueCtl* ctl;
-    unsigned long long* tasks;  // (query << 32) | (level << 26) | (J << 13) | I
+    unsigned long long* tasks;  // (query << 32) | (level << 26) | Morton code of the node
     unsigned int* flags;        // epoch of the launch that published the slot
     unsigned long long capacity;
 };
 
 struct PersistArgs {
     TaskQueue Q;
+    const uint32_t* order;  // processing order of the queries (nullptr: input order)
     Fix192* acc;     // per-query exact sums
     int* fexp;       // per-query binary point (written by the query's root task)
     float tau, s2r;
-    int split_level; // donate subtrees rooted at this level (>= 1)
+    int split_level;      // smallest level whose nodes may be donated (>= 1)
+    long long wait_ticks; // give-up bound of a worker's waits, in wall_clock64 ticks
 };
 
 // Device resources and the instantiated launch graph of a persistent plan.
@@ -97,8 +130,11 @@ struct PersistPlan {
     unsigned long long* tasks = nullptr;
     unsigned int* flags = nullptr;
     unsigned long long capacity = 0;
+    uint32_t* order = nullptr;  // order[max_nq] | key[max_nq] | hist[order_nb] (nullptr: input order)
+    int order_nb = 0, order_bshift = 0;
     long long max_nq = 0;
     int blocks = 0, split_level = 1;
+    long long wait_ticks = 0;
     float tau = 0.f, s2r = 3.f;
     unsigned epoch = 0;
     HierDev H{};
@@ -111,11 +147,20 @@ struct PersistPlan {
     const pndf_query* rq = nullptr;
     long long rnq = 0;
     float* rout = nullptr;
-    void* rargs[7];
+    uint32_t* okey = nullptr;   // views into `order`
+    uint32_t* ohist = nullptr;
+    int on = 0;
+    void* rargs[9];
     void* wargs[2];
     void* fargs[3];
+    void* hargs[5];  // order passes: histogram, scan, scatter
+    void* sargs[2];
+    void* cargs[4];
 };
 
+// Fill the device arguments of a plan whose buffers are allocated.
+void persist_prepare(const HierDev& H, PersistPlan& P);
+// persist_prepare, then build and instantiate the launch graph.
 hipError_t persist_graph_build(const HierDev& H, PersistPlan& P);
 hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float* out, bool use_graph,
                        hipStream_t s);
@@ -180,6 +225,8 @@ hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_
 // Spatial processing order of a batch: queries bucketed by the Morton code of their
 // centre cell (64 x 64 buckets over the torus), stream-ordered workspace.
 hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s);
+// Bucket count and coordinate shift of the spatial order for a map of side 2^logn.
+void order_shape(int logn, int* nb, int* bshift);
 void free_order(uint32_t* order, hipStream_t s);
 
 // ---------------------------------------------------------------- device side
@@ -248,6 +295,39 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     frexp(bound, &e2);
     q.fexp = e2 + 1 - 190;
     return q;
+}
+
+// The setup of a query owned by a whole wave is the same in every lane: keep it in
+// scalar registers (frees vector registers for the traversal).
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ QuerySetup uniform_query(const QuerySetup& q)
+{
+    QuerySetup u;
+    u.x = uniform_f32(q.x); u.y = uniform_f32(q.y); u.hx = uniform_f32(q.hx); u.hy = uniform_f32(q.hy);
+    u.cxlo = __builtin_amdgcn_readfirstlane(q.cxlo); u.cxhi = __builtin_amdgcn_readfirstlane(q.cxhi);
+    u.cylo = __builtin_amdgcn_readfirstlane(q.cylo); u.cyhi = __builtin_amdgcn_readfirstlane(q.cyhi);
+    u.l0 = __builtin_amdgcn_readfirstlane(q.l0);
+    u.t = uniform_f32(q.t);
+    u.kx = uniform_f64(q.kx); u.ky = uniform_f64(q.ky); u.norm = uniform_f64(q.norm);
+    u.fexp = __builtin_amdgcn_readfirstlane(q.fexp);
+    u.valid = __builtin_amdgcn_readfirstlane((int)q.valid) != 0;
+    return u;
 }
 
 // FP64 term t >= 0 added exactly down to 2^fexp: t = m 2^(ex - 1075) = (m 2^sh) 2^fexp,

@@ -6,8 +6,10 @@
 // staging, and (2) fills every idle slot with a new batch: the oldest admitted
 // request fixes the map, then later requests of that map join in arrival order
 // while they fit.  A batch is H2D copies into the slot's contiguous query buffer,
-// one persistent-plan evaluation, D2H copies into staging and an event, all on
-// the slot's stream, so slots run concurrently on the device.
+// one evaluation (a plain per-batch launch or the slot's persistent plan), D2H
+// copies into staging and an event, all on the slot's stream, so the batches of
+// different slots overlap on the device: one batch's tail runs beside the next
+// batch's bulk.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -186,7 +188,13 @@ hipError_t launch_slot(pndf_server* s, Slot& sl)
         off += r->nq;
     }
     if (e == hipSuccess) {
-        pndf_status st = pndf_plan_eval(sl.plans[map], sl.d_q, off, sl.d_out, sl.stream);
+        pndf_status st;
+        if (s->opts.algo == PNDF_ALGO_PERSISTENT) {
+            st = pndf_plan_eval(sl.plans[map], sl.d_q, off, sl.d_out, sl.stream);
+        } else {
+            const pndf_eval_opts eo{PNDF_KERNEL_GAUSSIAN, s->opts.tau, s->opts.sigma_to_r, PNDF_ALGO_PLAIN, 0};
+            st = pndf_eval_batch(s->maps[map], sl.d_q, off, &eo, sl.d_out, sl.stream);
+        }
         if (st != PNDF_OK) e = hipErrorLaunchFailure;
     }
     off = 0;
@@ -337,6 +345,8 @@ pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, cons
     if (o.max_batch_queries < 1 || o.max_batch_queries >= ((int64_t)1 << 31)) return fail("bad max_batch_queries");
     if (o.max_pending < 1) return fail("max_pending must be >= 1");
     if (o.memory_budget < (int64_t)(28 * o.max_batch_queries + 512)) return fail("memory budget below one batch");
+    if (o.algo != PNDF_ALGO_AUTO && o.algo != PNDF_ALGO_PLAIN && o.algo != PNDF_ALGO_PERSISTENT)
+        return fail("algo must be AUTO, PLAIN or PERSISTENT");
     if (o.tau > 0.f)
         for (int k = 0; k < nmaps; ++k)
             if (!maps[k]->cluster) return fail("tau > 0 needs hierarchies built with clusters");
@@ -344,6 +354,7 @@ pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, cons
     if (!s) return PNDF_ENOMEM;
     s->maps.assign(maps, maps + nmaps);
     s->opts = o;
+    if (s->opts.sigma_to_r <= 0.f) s->opts.sigma_to_r = 3.f;
     if (!s->pool.init((size_t)o.memory_budget)) {
         delete s;
         return fail("pinned staging allocation failed", PNDF_ENOMEM);
@@ -361,7 +372,7 @@ pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, cons
             st = pndf::hip_fail(e, "pndf_server_create");
             break;
         }
-        for (int k = 0; k < nmaps && st == PNDF_OK; ++k) {
+        for (int k = 0; k < nmaps && st == PNDF_OK && o.algo == PNDF_ALGO_PERSISTENT; ++k) {
             pndf_plan* p = nullptr;
             st = pndf_plan_create(maps[k], o.max_batch_queries, &eo, o.tuning.blocks_per_cu > 0 ? &o.tuning : nullptr,
                                   sl.stream, &p);

@@ -56,27 +56,48 @@ def setup(P):
 @pytest.mark.parametrize("tuning", [
     dict(blocks_per_cu=1, split_level=1, queue_factor=64, use_graph=1),
     dict(blocks_per_cu=2, split_level=3, queue_factor=16, use_graph=0),
-    dict(blocks_per_cu=4, split_level=5, queue_factor=1, use_graph=1),   # tiny queue: refusals
-    dict(blocks_per_cu=2, split_level=1, queue_factor=1, use_graph=0),   # refused leaf-level donations
+    dict(blocks_per_cu=4, split_level=5, queue_factor=1, use_graph=1),
+    dict(blocks_per_cu=8, split_level=1, queue_factor=1, use_graph=0),
 ])
-def test_persistent_equals_plain_bitwise(P, setup, tau, tuning):
+@pytest.mark.parametrize("input_order", [False, True])
+def test_persistent_equals_plain_bitwise(P, setup, tau, tuning, input_order):
     import torch
     nrm, hier = setup
-    announce("persistent %s tau=%g" % (tuning, tau))
+    announce("persistent %s tau=%g input_order=%s" % (tuning, tau, input_order))
     q = mixed(256, 3001, 3, 0.05, 120.0, 0.4)
     tq = to_dev(q)
     plain = P.eval_batch(hier, tq, tau=tau)
-    plan = P.Plan(hier, 4096, tau=tau, tuning=tuning)
+    plan = P.Plan(hier, 4096, tau=tau, tuning=tuning, input_order=input_order)
     for rep in range(3):
         got = plan.eval(tq)
         torch.cuda.synchronize()
         st = plan.stats()
         assert st["error"] == 0, st
         assert torch.equal(got.view(torch.int32), plain.view(torch.int32)), (rep, st)
-    if tuning["split_level"] <= 3:
-        assert st["spawned"] > 0
-    if tuning["queue_factor"] == 1 and tuning["split_level"] == 1:
-        assert st["refused"] > 0, st
+    # a few footprints cover the whole map: once the small ones are done, the idle
+    # workers must have been fed with pieces of the big ones
+    assert st["spawned"] > 0, st
+    plan.close()
+
+
+@pytest.mark.parametrize("split_level", [1, 3])
+def test_persistent_queue_full(P, setup, split_level):
+    """Eight whole-map footprints and a queue of eight slots: the queue fills at once
+    and later offers are refused (the nodes stay with their wave); the result is
+    still the plain kernel's, bit for bit."""
+    import torch
+    nrm, hier = setup
+    announce("persistent queue full, split_level=%d" % split_level)
+    q = mixed(256, 8, 31, 100.0, 120.0, 0.3)
+    tq = to_dev(q)
+    plain = P.eval_batch(hier, tq, tau=0.0)
+    plan = P.Plan(hier, 8, tuning=dict(blocks_per_cu=2, split_level=split_level, queue_factor=1, use_graph=1))
+    for rep in range(2):
+        got = plan.eval(tq)
+        st = plan.stats()
+        assert st["error"] == 0, st
+        assert torch.equal(got.view(torch.int32), plain.view(torch.int32)), (rep, st)
+    assert st["spawned"] > 0 and st["refused"] > 0, st
     plan.close()
 
 
@@ -131,7 +152,7 @@ def test_autotuner(P, setup):
     q = mixed(256, 4096, 21, 0.5, 100.0, 0.4)
     tq = to_dev(q)
     best, ms = P.autotune(hier, tq)
-    assert 1 <= best["blocks_per_cu"] <= 4 and 1 <= best["split_level"] <= 8 and ms > 0
+    assert best["blocks_per_cu"] in (1, 2, 4, 6, 8) and 2 <= best["split_level"] <= 8 and ms > 0
     plan = P.Plan(hier, 4096, tuning=best)
     got = plan.eval(tq)
     assert torch.equal(got.view(torch.int32), P.eval_batch(hier, tq).view(torch.int32))

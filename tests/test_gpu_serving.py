@@ -45,13 +45,14 @@ def tiles(maps, count, seed, tile=16):
     return mids, qs
 
 
+@pytest.mark.parametrize("algo", ["plain", "persistent"])
 @pytest.mark.parametrize("tau", [0.0, 1e-3])
-def test_served_results_equal_alone(maps, tau):
+def test_served_results_equal_alone(maps, tau, algo):
     import torch
     import paper_2505_08985_amd as P
-    announce("serving: mixed tiles over 3 maps, tau=%g" % tau)
+    announce("serving: mixed tiles over 3 maps, tau=%g, %s batches" % (tau, algo))
     mids, qs = tiles(maps, 40, 7)
-    srv = P.Server([h for _, h in maps], slots=3, max_batch_queries=4096, max_pending=64, tau=tau)
+    srv = P.Server([h for _, h in maps], slots=3, max_batch_queries=4096, max_pending=64, tau=tau, algo=algo)
     arrivals = np.cumsum(np.random.default_rng(1).exponential(0.002, len(qs)))
     outs, lat = srv.replay(mids, arrivals, qs)
     st = srv.stats()
@@ -62,11 +63,12 @@ def test_served_results_equal_alone(maps, tau):
     srv.close()
 
 
-def test_batches_mix_requests(maps):
+@pytest.mark.parametrize("algo", ["plain", "persistent"])
+def test_batches_mix_requests(maps, algo):
     import paper_2505_08985_amd as P
-    announce("serving: burst arrivals share batches")
+    announce("serving: burst arrivals share batches (%s)" % algo)
     mids, qs = tiles(maps, 30, 11, tile=8)
-    srv = P.Server([h for _, h in maps], slots=1, max_batch_queries=8192, max_pending=64)
+    srv = P.Server([h for _, h in maps], slots=1, max_batch_queries=8192, max_pending=64, algo=algo)
     outs, lat = srv.replay(mids, np.zeros(len(qs)), qs)
     st = srv.stats()
     assert st["completed"] == 30 and st["mean_batch_requests"] > 1.5, st
@@ -110,3 +112,5 @@ def test_submit_validation(maps):
     with pytest.raises(P.PndfError):
         srv.wait(12345)
     srv.close()
+    with pytest.raises(P.PndfError):
+        P.Server([h for _, h in maps], slots=1, max_batch_queries=256, algo="brute")
