@@ -357,7 +357,7 @@ typedef struct {
 typedef struct {
     double D;
     long nhit, namb;
-    int flags; /* bit0: a cut decision sits within rounding of the threshold */
+    int flags; /* bit0: a cut decision that matters sits within rounding of the threshold */
     /* optional record buffers (NULL = count only) */
     uint64_t* hid; double* hterm;
     uint64_t* aid; double* aterm; uint8_t* ahit;
@@ -507,7 +507,19 @@ static void descend(const map_t* m, const query_t* q, acc_t* acc, int level, lon
     long mm = m->n >> level;
     float e = m->clu_e[level_offset(m->n, level) + J * mm + I];
     double de = (double)e - (double)q->t;
-    if (fabs(de) <= 1e-5 * fabs((double)q->t)) acc->flags |= 1;
+    if (fabs(de) <= 1e-5 * fabs((double)q->t)) {
+        /* the decision sits within rounding of the threshold; it can change the
+         * result only if one of its two outcomes (this node's cluster triangles,
+         * or the cut beneath it) holds a hit or an edge-ambiguous triangle */
+        acc_t a, b;
+        memset(&a, 0, sizeof a);
+        memset(&b, 0, sizeof b);
+        test_cluster(m, q, &a, level, I, J);
+        for (int dj = 0; dj < 2; dj++)
+            for (int di = 0; di < 2; di++) descend(m, q, &b, level - 1, 2 * I + di, 2 * J + dj);
+        if (a.nhit || a.namb || b.nhit || b.namb) acc->flags |= 1;
+        acc->flags |= b.flags;
+    }
     if (e <= q->t) { test_cluster(m, q, acc, level, I, J); return; }
     for (int dj = 0; dj < 2; dj++)
         for (int di = 0; di < 2; di++) descend(m, q, acc, level - 1, 2 * I + di, 2 * J + dj);
@@ -586,7 +598,8 @@ static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
  *  D[k]      the P-NDF value (NaN for an invalid query: non-finite input, sigma <= 0,
  *            |x|, |y| or r above 2^24)
  *  nhit[k]   number of hit triangles, namb[k] number of triangles within `band` of h
- *  flags[k]  bit0 = some cut decision is within 1e-5 relative of the threshold
+ *  flags[k]  bit0 = some cut decision is within 1e-5 relative of the threshold and
+ *            one of its two outcomes holds a hit or an edge-ambiguous triangle
  * If hoff/aoff (prefix offsets from a previous counting call) are given, the
  * records are written: hit ids + terms, ambiguous ids + terms + hit flags.
  * tau > 0 requires clu_n / clu_e (all levels packed).

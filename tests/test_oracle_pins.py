@@ -567,3 +567,34 @@ def test_cut_threshold_rule(oracle_mod):
         want_cut = e_num[b * m + a] <= t
         assert ((a, b) in cut_nodes) == want_cut
         assert ((a, b) in cell_nodes) == (not want_cut)
+
+
+def test_cut_ambiguity_flag_only_when_it_matters(oracle_mod):
+    """A cut decision within rounding of the threshold (e^l vs r_x r_y tau) is
+    flagged only when one of its outcomes (the node's cluster triangles, or the
+    cut beneath it) contributes a hit or an edge-ambiguous triangle: for a query
+    normal far outside every normal of the map the two outcomes are both empty and
+    the decision is irrelevant; for the node's own mean normal it matters."""
+    n = 8
+    nrm = random_disk_map(n, 41, radius=0.35)
+    clusters = oracle_mod.cluster_all(nrm)
+    m = n // 2
+    ns, e = clusters["levels"][1]
+    I0, J0 = 1, 1
+    e0 = np.float32(e[J0 * m + I0])
+    s = np.float32(0.5)                        # r = 1.5: entry level 1, roots (1..2, 1..2)
+    rr = np.float32(np.float32(3) * s) ** 2
+    tau = np.float32(e0 / rr)                  # threshold within float rounding of e0
+    t = np.float32(rr * tau)
+    assert abs(float(t) - float(e0)) <= 1e-5 * float(e0)
+    inside = nrm[2 * J0:2 * J0 + 2, 2 * I0:2 * I0 + 2].reshape(-1, 2).astype(np.float64).mean(0)
+    qs = np.array([[4.0, 4.0, s, s, 0.95, 0.0],                    # no normal anywhere near
+                   [4.0, 4.0, s, s, inside[0], inside[1]]], dtype=np.float32)
+    res = oracle_mod.evaluate(nrm, qs, tau=float(tau), clusters=clusters, records=True)
+    assert res["nhit"][0] == 0 and res["namb"][0] == 0
+    assert res["flags"][0] == 0
+    assert res["nhit"][1] > 0
+    assert res["flags"][1] & 1
+    # far from the threshold nothing is flagged, whatever h
+    res2 = oracle_mod.evaluate(nrm, qs, tau=float(tau) * 4, clusters=clusters)
+    assert not (res2["flags"] & 1).any()
