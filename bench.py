@@ -7,13 +7,17 @@ A step is one pndf_eval_batch over the whole query batch (queries and the mesh /
 hierarchy already resident in HBM).  Prints one JSON line.
 
 Roofline: the dominant (and only) kernel of a step is the evaluation kernel.  Its
-algorithmic bytes per launch are the per-query work units counted by an
-instrumented launch (nodes, leaf cells, clusters, hits) times the bytes each unit
-must read, plus the query record and the output:
-    B = 28 + (16 + 4 [tau > 0]) nodes + 9 cells + 41 clusters + 4 hits
-and its duration is measured with HIP events on the stream the kernel runs on.
-HBM traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded under
-profiles/ (null when the kernel source changed since they were taken).
+work is counted per query by an instrumented launch (nodes, leaf cells, clusters,
+hits) and priced two ways:
+    bytes it must read   B = 28 + (16 + 4 [tau > 0]) nodes + 9 cells + 41 clusters + 4 hits
+    vector ALU lane-ops  F = 12 nodes + 40 cells + 40 clusters + 30 hits
+The kernel's counters show it issue-bound on the vector ALU (about 90 % VALU busy),
+so `roofline` is the ALU one: F per launch over the launch time, against 256 CUs x
+64 lanes x 2.4 GHz = 39.3 T lane-ops/s (one 32-bit operation per lane per clock,
+no packed-FP32 or FMA double counting); `roofline_hbm` gives B against 8 TB/s.
+The duration is measured with HIP events on the stream the kernel runs on.  HBM
+traffic comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded under profiles/
+(null when the kernel source changed since they were taken).
 """
 import argparse
 import hashlib
@@ -30,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "P-NDF queries/sec at 1 MI355X vs footprint size; p99 tile latency (serving)"
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane operations per second, in T
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_plain_powerlaw2048.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2505_08985_amd", "csrc", f)
               for f in ("eval.hip", "pndf_internal.h")]
@@ -40,6 +45,11 @@ def kernel_hash():
     for p in KERNEL_SRC:
         h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
+
+
+def algorithmic_ops(counts):
+    c = counts.astype(np.float64)
+    return float(np.sum(12.0 * c[:, 0] + 40.0 * c[:, 1] + 40.0 * c[:, 2] + 30.0 * c[:, 3]))
 
 
 def algorithmic_bytes(counts, tau):
@@ -187,7 +197,7 @@ def main():
     ap.add_argument("--serve-tiles", type=int, default=200)
     ap.add_argument("--serve-sigma-max", type=float, default=4096.0)
     ap.add_argument("--serve-rates", default="0.5,0.8,0.95")
-    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-batch-tiles", type=int, default=4)
     ap.add_argument("--serve-algo", default="plain", choices=["plain", "persistent"],
                     help="how the server evaluates a batch")
@@ -283,10 +293,12 @@ def main():
     counts = counts.cpu().numpy()
     abytes = algorithmic_bytes(counts, tau)
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    aops = algorithmic_ops(counts)
+    achieved_ops = aops / (kernel_ms * 1e-3) / 1e12
     traffic = load_traffic(args.workload, args.algo)
     work = {"nodes_per_query": float(counts[:, 0].mean()), "cells_per_query": float(counts[:, 1].mean()),
             "clusters_per_query": float(counts[:, 2].mean()), "hits_per_query": float(counts[:, 3].mean()),
-            "algorithmic_bytes_per_launch": abytes}
+            "algorithmic_bytes_per_launch": abytes, "algorithmic_alu_ops_per_launch": aops}
 
     octaves = None
     if not args.no_octaves and isinstance(qc["sigma"], tuple):
@@ -335,8 +347,10 @@ def main():
                    "sigma": list(qc["sigma"]) if isinstance(qc["sigma"], tuple) else qc["sigma"],
                    "h_radius": qc["radius"], "tau": tau, "algo": args.algo, "sigma_to_r": 3.0,
                    "tuning": tuning},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": {"bound": "alu", "achieved": achieved_ops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": achieved_ops / ALU_PEAK_TOPS, "traffic": traffic},
+        "roofline_hbm": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
         "kernel_ms": kernel_ms,
         "build_s": build_s,

@@ -66,7 +66,7 @@ pndf_status pndf_default_tuning(const pndf_hier* h, pndf_tuning* out)
 {
     if (!h || !out) return plan_invalid("NULL argument");
     out->blocks_per_cu = 4;
-    out->split_level = std::min(h->L, 4);
+    out->split_level = std::min(h->L, 7);
     out->queue_factor = 16;
     out->use_graph = 1;
     return PNDF_OK;
