@@ -108,6 +108,11 @@ __device__ __forceinline__ int wave_prefix16(int c, int* total)
 // A lane's hits are a bit mask over the low bits of its entry code.
 constexpr uint32_t kHitPlane = 1u << 30, kHitCluster = 2u << 30;
 
+// Traversal list items are Morton codes (at most 24 bits); the top bit marks a node
+// whose region lies wholly inside the query's box, so that its descendants skip the
+// spatial tests.
+constexpr uint32_t kInside = 1u << 31;
+
 // The two triangles of a cell from its four corner normals and clamp bits: bit 0
 // lower (n0, n1, n2), bit 1 upper (n3, n2, n1).
 __device__ __forceinline__ uint32_t cell_mask(const QuerySetup& q, float rho, float2 n0, float2 n1, float2 n2,
@@ -145,10 +150,10 @@ __device__ __forceinline__ uint32_t plane_cell_mask(const HierDev& H, const Quer
     return cell_mask(q, H.rho, p[0], p[1], p[w], p[w + 1], H.deg[(int64_t)j * H.n + i]);
 }
 
-// The 2 x 2 cells of level-1 node (I, J) (leaf record m), those overlapping the box:
-// bit 2 c4 + half for cell c4 = 2 dj + di.
-__device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const QuerySetup& q, int I, int J,
-                                                   uint32_t m, Acc& acc)
+// The 2 x 2 cells of level-1 node m (its leaf record), those overlapping the box
+// (all four when the node lies inside it): bit 2 c4 + half for cell c4 = 2 dj + di.
+__device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const QuerySetup& q, uint32_t m, bool inside,
+                                                   Acc& acc)
 {
     const float4* r = reinterpret_cast<const float4*>(H.quad + m);
     const float4 a = r[0], b = r[1], c = r[2], d = r[3], e = r[4];
@@ -156,11 +161,15 @@ __device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const Query
                          make_float2(b.z, b.w), make_float2(c.x, c.y), make_float2(c.z, c.w),
                          make_float2(d.x, d.y), make_float2(d.z, d.w), make_float2(e.x, e.y)};
     const uint32_t dg4 = __float_as_uint(e.z);
-    const int logn = H.logn;
-    const bool x0 = axis_overlap(2 * I, 1, q.cxlo, q.cxhi, logn);
-    const bool x1 = axis_overlap(2 * I + 1, 1, q.cxlo, q.cxhi, logn);
-    const bool y0 = axis_overlap(2 * J, 1, q.cylo, q.cyhi, logn);
-    const bool y1 = axis_overlap(2 * J + 1, 1, q.cylo, q.cyhi, logn);
+    bool x0 = true, x1 = true, y0 = true, y1 = true;
+    if (!inside) {
+        const int logn = H.logn;
+        const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
+        x0 = axis_overlap(2 * I, 1, q.cxlo, q.cxhi, logn);
+        x1 = axis_overlap(2 * I + 1, 1, q.cxlo, q.cxhi, logn);
+        y0 = axis_overlap(2 * J, 1, q.cylo, q.cyhi, logn);
+        y1 = axis_overlap(2 * J + 1, 1, q.cylo, q.cyhi, logn);
+    }
     uint32_t mask = 0;
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
@@ -270,6 +279,7 @@ __device__ __forceinline__ void hit_round(const HierDev& H, const QuerySetup& q,
 // Move the lanes' pending hits into the queue (as many as fit, in lane order).
 __device__ __forceinline__ void queue_hits(uint32_t* hq, int& hn, uint32_t& pend, uint32_t ebase)
 {
+    if (__ballot(pend != 0u) == 0ull) return;
     int total;
     const int pos = wave_prefix16(__popc(pend), &total);
     if (total == 0) return;
@@ -322,7 +332,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         bool ok = root_ok;
         if (ok && !roots_tested) {
             acc.nodes += 1;
-            ok = in_box(q, boxes[level_offset(H.logn, root_level) + root_item]);
+            ok = in_box(q, boxes[level_offset(H.logn, root_level) + (root_item & ~kInside)]);
         }
         const uint64_t bal = __ballot(ok);
         const int pos = __popcll(bal & ((1ull << lane) - 1ull));
@@ -383,7 +393,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 slot = uniform_u64(slot);
                 if (d > 0) {
                     if (lane < d) {
-                        const uint32_t mm = lists[(lh - 1) * kListCap + ch - 1 - lane];  // the top d items
+                        const uint32_t mm = lists[(lh - 1) * kListCap + ch - 1 - lane] & ~kInside;  // the top d items
                         Q.tasks[slot + lane] = (qidx << 32) | ((unsigned long long)lh << 26) | (unsigned long long)mm;
                         // the release store orders the task word before its flag
                         __hip_atomic_store(&Q.flags[slot + lane], Q.ctl->epoch, __ATOMIC_RELEASE,
@@ -397,8 +407,17 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 }
             }
         }
-        const int l = __builtin_ctz(nonempty);
-        const int cnt = __builtin_amdgcn_readlane(cntv, l);
+        int l = __builtin_ctz(nonempty);
+        int cnt = __builtin_amdgcn_readlane(cntv, l);
+        if (cnt < 64) {
+            // the lowest list is short: expand the next higher level first, so the
+            // lower levels run with full waves (what does not fit is re-queued)
+            const uint32_t higher = nonempty & ~((2u << l) - 1u);
+            if (higher) {
+                l = __builtin_ctz(higher);
+                cnt = __builtin_amdgcn_readlane(cntv, l);
+            }
+        }
         const int k = min(cnt, 64), base = cnt - k;
         unsigned hv = 0;
         if (SPAWN && lane == 0 && 31 - __builtin_clz(nonempty) >= split_level)
@@ -409,56 +428,75 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         uint32_t ch[4];
         int nch = 0;
         uint32_t tested = 0;  // child boxes read by this lane
-        uint32_t m = 0;
+        uint32_t entry = 0;   // the lane's list item (Morton code | kInside)
         if (lane < k) {
-            m = lists[(l - 1) * kListCap + base + lane];
-            const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
+            entry = lists[(l - 1) * kListCap + base + lane];
+            const uint32_t m = entry & ~kInside;
+            const bool inside = (entry & kInside) != 0u;
             const int64_t idx = level_offset(H.logn, l) + m;
             if (CUT && l <= q.l0 && H.clu_e[idx] <= q.t) {
                 pend = cluster_mask(H, q, l, idx, acc);
                 ebase = kHitCluster | ((uint32_t)l << 25) | (m << 1);
             } else if (l == 1) {
-                pend = leaf_quad_mask(H, q, I, J, m, acc);
+                pend = leaf_quad_mask(H, q, m, inside, acc);
                 ebase = m << 3;
             } else {
-                const int side = 1 << (l - 1);
-                const bool x0 = axis_overlap(2 * I * side, side, q.cxlo, q.cxhi, logn);
-                const bool x1 = axis_overlap((2 * I + 1) * side, side, q.cxlo, q.cxhi, logn);
-                const bool y0 = axis_overlap(2 * J * side, side, q.cylo, q.cyhi, logn);
-                const bool y1 = axis_overlap((2 * J + 1) * side, side, q.cylo, q.cyhi, logn);
                 const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
-                float4 b0 = make_float4(1.f, 1.f, -1.f, -1.f), b1 = b0, b2 = b0, b3 = b0;
-                if (x0 && y0) b0 = cb[0];
-                if (x1 && y0) b1 = cb[1];
-                if (x0 && y1) b2 = cb[2];
-                if (x1 && y1) b3 = cb[3];
-                tested = (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
-                if (in_box(q, b0)) ch[nch++] = 4 * m;
-                if (in_box(q, b1)) ch[nch++] = 4 * m + 1;
-                if (in_box(q, b2)) ch[nch++] = 4 * m + 2;
-                if (in_box(q, b3)) ch[nch++] = 4 * m + 3;
+                float4 b0, b1, b2, b3;
+                uint32_t cin = 0xfu;  // children wholly inside the box (bit c)
+                if (inside) {
+                    // the node lies inside the box, so do all its descendants
+                    b0 = cb[0]; b1 = cb[1]; b2 = cb[2]; b3 = cb[3];
+                    tested = 4;
+                } else {
+                    const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
+                    const int side = 1 << (l - 1);
+                    const int sx0 = 2 * I * side, sx1 = sx0 + side, sy0 = 2 * J * side, sy1 = sy0 + side;
+                    const bool x0 = axis_overlap(sx0, side, q.cxlo, q.cxhi, logn);
+                    const bool x1 = axis_overlap(sx1, side, q.cxlo, q.cxhi, logn);
+                    const bool y0 = axis_overlap(sy0, side, q.cylo, q.cyhi, logn);
+                    const bool y1 = axis_overlap(sy1, side, q.cylo, q.cyhi, logn);
+                    b0 = b1 = b2 = b3 = make_float4(1.f, 1.f, -1.f, -1.f);
+                    if (x0 && y0) b0 = cb[0];
+                    if (x1 && y0) b1 = cb[1];
+                    if (x0 && y1) b2 = cb[2];
+                    if (x1 && y1) b3 = cb[3];
+                    tested = (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
+                    const bool fx0 = axis_inside(sx0, side, q.cxlo, q.cxhi, logn);
+                    const bool fx1 = axis_inside(sx1, side, q.cxlo, q.cxhi, logn);
+                    const bool fy0 = axis_inside(sy0, side, q.cylo, q.cyhi, logn);
+                    const bool fy1 = axis_inside(sy1, side, q.cylo, q.cyhi, logn);
+                    cin = (uint32_t)(fx0 && fy0) | ((uint32_t)(fx1 && fy0) << 1) | ((uint32_t)(fx0 && fy1) << 2) |
+                          ((uint32_t)(fx1 && fy1) << 3);
+                }
+                if (in_box(q, b0)) ch[nch++] = (4 * m) | ((cin & 1u) ? kInside : 0u);
+                if (in_box(q, b1)) ch[nch++] = (4 * m + 1) | ((cin & 2u) ? kInside : 0u);
+                if (in_box(q, b2)) ch[nch++] = (4 * m + 2) | ((cin & 4u) ? kInside : 0u);
+                if (in_box(q, b3)) ch[nch++] = (4 * m + 3) | ((cin & 8u) ? kInside : 0u);
             }
         }
         if (l >= 2) {
             int total;
             const int pos = wave_prefix_small(nch, &total);
-            // A parent whose children would run past the end of the level below goes
-            // back to its own list whole and is expanded again once that list has
-            // drained.  Child positions grow with the lane, so the parents that fit
-            // are a prefix and at least the first one with children always fits.
-            const bool back = nch > 0 && pos + nch > kListCap;
+            // The children are appended to the level below (which holds fewer than 64
+            // items: it is empty or the short lowest list).  A parent whose children
+            // would run past the end goes back to its own list whole and is expanded
+            // again later.  Child positions grow with the lane, so the parents that fit
+            // are a prefix and the first one with children always fits.
+            const int below = __builtin_amdgcn_readlane(cntv, l - 1);
+            const bool back = nch > 0 && below + pos + nch > kListCap;
             const uint64_t bb = __ballot(back);
-            uint32_t* dst = lists + (l - 2) * kListCap;
+            uint32_t* dst = lists + (l - 2) * kListCap + below;
             if (!back) {
                 for (int c = 0; c < nch; ++c) dst[pos + c] = ch[c];
                 acc.nodes += tested;
             }
             const int pushed = bb ? __builtin_amdgcn_readlane(pos, __builtin_ctzll(bb)) : total;
-            if (lane == l - 1) cntv = pushed;
+            if (lane == l - 1) cntv = below + pushed;
             if (pushed) nonempty |= 1u << (l - 1);
             if (bb) {
                 const int nb = __popcll(bb);
-                if (back) lists[(l - 1) * kListCap + base + __popcll(bb & ((1ull << lane) - 1ull))] = m;
+                if (back) lists[(l - 1) * kListCap + base + __popcll(bb & ((1ull << lane) - 1ull))] = entry;
                 if (lane == l) cntv = base + nb;
                 nonempty |= 1u << l;
             }
@@ -480,7 +518,11 @@ __device__ __forceinline__ uint32_t root_item(const HierDev& H, const QuerySetup
     const int ra = lane & 3, rb = lane >> 2;
     *ok = lane < 16 && ra < nkx && rb < nky;
     const uint32_t I = (uint32_t)((kx0 + ra) & mm), J = (uint32_t)((ky0 + rb) & mm);
-    return l0 == 0 ? (I | (J << 16)) : morton(I, J);
+    if (l0 == 0) return I | (J << 16);
+    const int side = 1 << l0;
+    const bool inside = axis_inside((int)I * side, side, q.cxlo, q.cxhi, H.logn) &&
+                        axis_inside((int)J * side, side, q.cylo, q.cyhi, H.logn);
+    return morton(I, J) | (inside ? kInside : 0u);
 }
 
 template <int MODE>

@@ -387,6 +387,13 @@ __device__ __forceinline__ float fix_to_float(const Fix192& a, int fexp)
 
 // Does a node of side 2^lev starting at torus cell `start` have a periodic image
 // with a cell inside the unrolled cell range [clo, chi]?
+// Some periodic image [start + pN, start + side - 1 + pN] lies wholly inside the cell
+// range [clo, chi]: the first image starting at or after clo ends by chi.
+__device__ __forceinline__ bool axis_inside(int start, int side, int clo, int chi, int logn)
+{
+    return start + (ceil_div_pow2(clo - start, logn) << logn) + side - 1 <= chi;
+}
+
 __device__ __forceinline__ bool axis_overlap(int start, int side, int clo, int chi, int logn)
 {
     return ceil_div_pow2(clo - start - side + 1, logn) <= floor_div_pow2(chi - start, logn);
