@@ -425,8 +425,9 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                                    __HIP_MEMORY_SCOPE_AGENT);
         if (lane == l) cntv = base;
         if (base == 0) nonempty &= ~(1u << l);
-        uint32_t ch[4];
-        int nch = 0;
+        uint32_t chm = 0;     // children whose boxes contain h (bit c: child 4m + c)
+        uint32_t cin = 0;     // children wholly inside the box (bit c)
+        uint32_t m4 = 0;      // 4m: the first child's code
         uint32_t tested = 0;  // child boxes read by this lane
         uint32_t entry = 0;   // the lane's list item (Morton code | kInside)
         if (lane < k) {
@@ -443,7 +444,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             } else {
                 const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
                 float4 b0, b1, b2, b3;
-                uint32_t cin = 0xfu;  // children wholly inside the box (bit c)
+                cin = 0xfu;
                 if (inside) {
                     // the node lies inside the box, so do all its descendants
                     b0 = cb[0]; b1 = cb[1]; b2 = cb[2]; b3 = cb[3];
@@ -469,14 +470,14 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                     cin = (uint32_t)(fx0 && fy0) | ((uint32_t)(fx1 && fy0) << 1) | ((uint32_t)(fx0 && fy1) << 2) |
                           ((uint32_t)(fx1 && fy1) << 3);
                 }
-                if (in_box(q, b0)) ch[nch++] = (4 * m) | ((cin & 1u) ? kInside : 0u);
-                if (in_box(q, b1)) ch[nch++] = (4 * m + 1) | ((cin & 2u) ? kInside : 0u);
-                if (in_box(q, b2)) ch[nch++] = (4 * m + 2) | ((cin & 4u) ? kInside : 0u);
-                if (in_box(q, b3)) ch[nch++] = (4 * m + 3) | ((cin & 8u) ? kInside : 0u);
+                chm = (uint32_t)in_box(q, b0) | ((uint32_t)in_box(q, b1) << 1) | ((uint32_t)in_box(q, b2) << 2) |
+                      ((uint32_t)in_box(q, b3) << 3);
+                m4 = 4 * m;
             }
         }
         if (l >= 2) {
             int total;
+            const int nch = __popc(chm);
             const int pos = wave_prefix_small(nch, &total);
             // The children are appended to the level below (which holds fewer than 64
             // items: it is empty or the short lowest list).  A parent whose children
@@ -488,7 +489,11 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             const uint64_t bb = __ballot(back);
             uint32_t* dst = lists + (l - 2) * kListCap + below;
             if (!back) {
-                for (int c = 0; c < nch; ++c) dst[pos + c] = ch[c];
+                // child c goes to pos + (number of passing children before it)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (chm & (1u << c))
+                        dst[pos + __popc(chm & ((1u << c) - 1u))] = (m4 + c) | ((cin >> c) & 1u ? kInside : 0u);
                 acc.nodes += tested;
             }
             const int pushed = bb ? __builtin_amdgcn_readlane(pos, __builtin_ctzll(bb)) : total;
