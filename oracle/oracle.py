@@ -49,9 +49,13 @@ def load():
                             ctypes.c_float, ctypes.c_float, ctypes.c_double,
                             _dp, _i64p, _i64p, _i32p,
                             _i64p, _u64p, _dp, _i64p, _u64p, _dp, _u8p]
+    lib.or_eval_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, _fp, _fp, ctypes.c_int64,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_int,
+                              _dp, _i64p, _i64p, _i32p,
+                              _i64p, _u64p, _dp, _i64p, _u64p, _dp, _u8p]
     lib.or_sample_normals.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, ctypes.c_int64, _dp]
     lib.or_num_threads.argtypes = []
-    for f in (lib.or_mesh, lib.or_cluster_nodes, lib.or_fine_contrib, lib.or_eval,
+    for f in (lib.or_mesh, lib.or_cluster_nodes, lib.or_fine_contrib, lib.or_eval, lib.or_eval_k,
               lib.or_sample_normals, lib.or_num_threads):
         f.restype = ctypes.c_int
     _lib = lib
@@ -132,11 +136,18 @@ def fine_contrib(a, i, j, half, nv):
     return A.reshape(4, 4), B.reshape(4, 2), float(C[0]), ch
 
 
+KERNELS = {"gaussian": 0, "disk": 1, "box": 2}
+
+
 def evaluate(nrm, queries, tau=0.0, eps=1e-6, sigma_to_r=3.0, band=1e-6, clusters=None,
-             records=False):
+             records=False, kernel="gaussian"):
     """Evaluate queries (Q, 6) float32.  Returns dict with D (FP64), nhit, namb, flags
     and, with records=True, per-query hit and ambiguous-triangle lists as CSR:
-    hit_off, hit_id, hit_term, amb_off, amb_id, amb_term, amb_hit."""
+    hit_off, hit_id, hit_term, amb_off, amb_id, amb_term, amb_hit.
+    kernel: "gaussian" (sigma the standard deviation, support r = sigma_to_r sigma),
+    "disk" or "box" (normalised over the ellipse / rectangle of half-axes
+    r = sigma_to_r sigma, truncated at the hit point)."""
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     nrm = _map(nrm)
     n = nrm.shape[0]
     q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, 6)
@@ -151,8 +162,8 @@ def evaluate(nrm, queries, tau=0.0, eps=1e-6, sigma_to_r=3.0, band=1e-6, cluster
     flags = np.empty(nq, dtype=np.int32)
     lib = load()
     args = [n, _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp), nq, tau, sigma_to_r,
-            band, _p(D, _dp), _p(nhit, _i64p), _p(namb, _i64p), _p(flags, _i32p)]
-    rc = lib.or_eval(*args, None, None, None, None, None, None, None)
+            band, kid, _p(D, _dp), _p(nhit, _i64p), _p(namb, _i64p), _p(flags, _i32p)]
+    rc = lib.or_eval_k(*args, None, None, None, None, None, None, None)
     if rc:
         raise ValueError("or_eval failed (%d)" % rc)
     out = dict(D=D, nhit=nhit, namb=namb, flags=flags)
@@ -168,8 +179,8 @@ def evaluate(nrm, queries, tau=0.0, eps=1e-6, sigma_to_r=3.0, band=1e-6, cluster
     aterm = np.zeros(max(1, aoff[-1]), dtype=np.float64)
     ahit = np.zeros(max(1, aoff[-1]), dtype=np.uint8)
     D2 = np.empty(nq, dtype=np.float64)
-    rc = lib.or_eval(n, _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp), nq, tau,
-                     sigma_to_r, band, _p(D2, _dp), _p(nhit, _i64p), _p(namb, _i64p),
+    rc = lib.or_eval_k(n, _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp), nq, tau,
+                     sigma_to_r, band, kid, _p(D2, _dp), _p(nhit, _i64p), _p(namb, _i64p),
                      _p(flags, _i32p), _p(hoff, _i64p), _p(hid, _u64p), _p(hterm, _dp),
                      _p(aoff, _i64p), _p(aid, _u64p), _p(aterm, _dp), _p(ahit, _u8p))
     if rc:

@@ -347,17 +347,24 @@ static long level_offset(int n, int level) /* first node of `level` in packed ar
 
 typedef struct {
     double x, y, sx, sy, h[2];
+    double rx, ry; /* support half-widths r = fl32(sigma_to_r * sigma) */
     long cxlo, cxhi, cylo, cyhi;
     int l0;
     float t; /* cut threshold (float, as fixed by the definition) */
     int use_cut;
+    int kernel; /* 0 Gaussian, 1 disk, 2 box */
     double band;
 } query_t;
+
+/* relative band around the edge of the disk / box support within which the
+ * inclusion of a hit point can flip under rounding (flags bit 1) */
+#define OR_KERNEL_BAND 1e-9
 
 typedef struct {
     double D;
     long nhit, namb;
-    int flags; /* bit0: a cut decision that matters sits within rounding of the threshold */
+    int flags; /* bit0: a cut decision that matters sits within rounding of the threshold;
+                * bit1: a hit point sits within rounding of the disk / box support edge */
     /* optional record buffers (NULL = count only) */
     uint64_t* hid; double* hterm;
     uint64_t* aid; double* aterm; uint8_t* ahit;
@@ -388,6 +395,42 @@ static double gauss_sum(double ucoord, long start, long s, long clo, long chi, l
     return g;
 }
 
+/* Box footprint (Table notation: k_r of size 2r_x x 2r_y, zero beyond r), one axis:
+ * the number of included periodic images of the point u within distance r of x */
+static double box_count(double ucoord, long start, long s, long clo, long chi, long n, double x, double r,
+                        int* amb)
+{
+    long p0, p1;
+    image_range(start, s, clo, chi, n, &p0, &p1);
+    double c = 0.0;
+    for (long p = p0; p <= p1; p++) {
+        double d = fabs(ucoord + (double)p * (double)n - x);
+        if (fabs(d - r) <= OR_KERNEL_BAND * r) *amb = 1;
+        if (d <= r) c += 1.0;
+    }
+    return c;
+}
+
+/* Disk footprint (an ellipse of half-axes r_x, r_y): the number of included
+ * periodic images (p, q) of u inside it */
+static double disk_count(double ux, double uy, long I, long J, long s, const query_t* q, long n, int* amb)
+{
+    long p0, p1, q0, q1;
+    image_range(I * s, s, q->cxlo, q->cxhi, n, &p0, &p1);
+    image_range(J * s, s, q->cylo, q->cyhi, n, &q0, &q1);
+    double c = 0.0;
+    for (long p = p0; p <= p1; p++) {
+        double dx = (ux + (double)p * (double)n - q->x) / q->rx;
+        for (long r = q0; r <= q1; r++) {
+            double dy = (uy + (double)r * (double)n - q->y) / q->ry;
+            double e = dx * dx + dy * dy;
+            if (fabs(e - 1.0) <= OR_KERNEL_BAND) *amb = 1;
+            if (e <= 1.0) c += 1.0;
+        }
+    }
+    return c;
+}
+
 /* Test one triangle with normal-space vertices nv (a, b, c) and uv vertices
  * (a, b, c); Jacobian det_used; node (level, I, J) of side s for the images. */
 static void test_tri(const map_t* m, const query_t* q, acc_t* acc, uint64_t id,
@@ -409,9 +452,23 @@ static void test_tri(const map_t* m, const query_t* q, acc_t* acc, uint64_t id,
     if (!hit && !amb) return;
     double ux = uv[0][0] * l0 + uv[1][0] * l1 + uv[2][0] * l2;
     double uy = uv[0][1] * l0 + uv[1][1] * l1 + uv[2][1] * l2;
-    double gx = gauss_sum(ux, I * s, s, q->cxlo, q->cxhi, m->n, q->x, q->sx);
-    double gy = gauss_sum(uy, J * s, s, q->cylo, q->cyhi, m->n, q->y, q->sy);
-    double term = gx * gy / (2.0 * OR_PI * q->sx * q->sy) / det_used;
+    double w; /* footprint kernel k_r(u* - x) summed over the included periodic images */
+    if (q->kernel == 0) {
+        double gx = gauss_sum(ux, I * s, s, q->cxlo, q->cxhi, m->n, q->x, q->sx);
+        double gy = gauss_sum(uy, J * s, s, q->cylo, q->cyhi, m->n, q->y, q->sy);
+        w = gx * gy / (2.0 * OR_PI * q->sx * q->sy);
+    } else {
+        int kamb = 0;
+        if (q->kernel == 2) {
+            double cx = box_count(ux, I * s, s, q->cxlo, q->cxhi, m->n, q->x, q->rx, &kamb);
+            double cy = box_count(uy, J * s, s, q->cylo, q->cyhi, m->n, q->y, q->ry, &kamb);
+            w = cx * cy / (4.0 * q->rx * q->ry);
+        } else {
+            w = disk_count(ux, uy, I, J, s, q, m->n, &kamb) / (OR_PI * q->rx * q->ry);
+        }
+        if (kamb && hit) acc->flags |= 2;
+    }
+    double term = w / det_used;
     if (hit) {
         if (acc->hid) { acc->hid[acc->nhit] = id; acc->hterm[acc->nhit] = term; }
         acc->nhit++;
@@ -525,7 +582,7 @@ static void descend(const map_t* m, const query_t* q, acc_t* acc, int level, lon
         for (int di = 0; di < 2; di++) descend(m, q, acc, level - 1, 2 * I + di, 2 * J + dj);
 }
 
-static int setup_query(const map_t* m, const float* qr, float tau, float s2r, double band,
+static int setup_query(const map_t* m, const float* qr, float tau, float s2r, double band, int kernel,
                        query_t* q)
 {
     float x = qr[0], y = qr[1], sx = qr[2], sy = qr[3], hx = qr[4], hy = qr[5];
@@ -538,6 +595,8 @@ static int setup_query(const map_t* m, const float* qr, float tau, float s2r, do
     if (!(fabsf(x) <= lim && fabsf(y) <= lim && rx <= lim && ry <= lim)) return 1;
     float lox = x - rx, hix = x + rx, loy = y - ry, hiy = y + ry;
     q->x = x; q->y = y; q->sx = sx; q->sy = sy; q->h[0] = hx; q->h[1] = hy;
+    q->rx = rx; q->ry = ry;
+    q->kernel = kernel;
     q->cxlo = (long)ceilf(lox) - 1; q->cxhi = (long)floorf(hix);
     q->cylo = (long)ceilf(loy) - 1; q->cyhi = (long)floorf(hiy);
     float rmax = rx > ry ? rx : ry;
@@ -599,17 +658,23 @@ static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
  *            |x|, |y| or r above 2^24)
  *  nhit[k]   number of hit triangles, namb[k] number of triangles within `band` of h
  *  flags[k]  bit0 = some cut decision is within 1e-5 relative of the threshold and
- *            one of its two outcomes holds a hit or an edge-ambiguous triangle
+ *            one of its two outcomes holds a hit or an edge-ambiguous triangle;
+ *            bit1 = (disk / box) a hit point lies within 1e-9 relative of the support edge
+ * kernel: 0 Gaussian (sigma the standard deviation, support r = s2r sigma), 1 disk
+ * (the ellipse of half-axes r), 2 box (|u - x| <= r per axis); disk and box are
+ * normalised over their support and truncated at the hit point (Table notation:
+ * k_r is zero beyond r), the cells included are those meeting the support box.
  * If hoff/aoff (prefix offsets from a previous counting call) are given, the
  * records are written: hit ids + terms, ambiguous ids + terms + hit flags.
  * tau > 0 requires clu_n / clu_e (all levels packed).
  */
-int or_eval(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
-            const float* queries, int64_t nq, float tau, float s2r, double band,
-            double* D, int64_t* nhit, int64_t* namb, int32_t* flags,
-            const int64_t* hoff, uint64_t* hid, double* hterm,
-            const int64_t* aoff, uint64_t* aid, double* aterm, uint8_t* ahit)
+int or_eval_k(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+              const float* queries, int64_t nq, float tau, float s2r, double band, int kernel,
+              double* D, int64_t* nhit, int64_t* namb, int32_t* flags,
+              const int64_t* hoff, uint64_t* hid, double* hterm,
+              const int64_t* aoff, uint64_t* aid, double* aterm, uint8_t* ahit)
 {
+    if (kernel < 0 || kernel > 2) return 3;
     map_t m;
     m.n = n;
     m.L = ilog2_exact(n);
@@ -624,7 +689,7 @@ int or_eval(int n, const float* nrm, float eps, const float* clu_n, const float*
         query_t q;
         acc_t acc;
         memset(&acc, 0, sizeof acc);
-        if (setup_query(&m, queries + 6 * k, tau, s2r, band, &q)) {
+        if (setup_query(&m, queries + 6 * k, tau, s2r, band, kernel, &q)) {
             D[k] = NAN;
             if (nhit) nhit[k] = 0;
             if (namb) namb[k] = 0;
@@ -640,6 +705,17 @@ int or_eval(int n, const float* nrm, float eps, const float* clu_n, const float*
         if (flags) flags[k] = acc.flags;
     }
     return 0;
+}
+
+/* or_eval_k with the Gaussian footprint kernel */
+int or_eval(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+            const float* queries, int64_t nq, float tau, float s2r, double band,
+            double* D, int64_t* nhit, int64_t* namb, int32_t* flags,
+            const int64_t* hoff, uint64_t* hid, double* hterm,
+            const int64_t* aoff, uint64_t* aid, double* aterm, uint8_t* ahit)
+{
+    return or_eval_k(n, nrm, eps, clu_n, clu_e, queries, nq, tau, s2r, band, 0, D, nhit, namb, flags, hoff, hid,
+                     hterm, aoff, aid, aterm, ahit);
 }
 
 /* the normal field n(u) of Eq. (interpolation) at texture coordinates u (periodic),

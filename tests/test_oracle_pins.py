@@ -598,3 +598,67 @@ def test_cut_ambiguity_flag_only_when_it_matters(oracle_mod):
     # far from the threshold nothing is flagged, whatever h
     res2 = oracle_mod.evaluate(nrm, qs, tau=float(tau) * 4, clusters=clusters)
     assert not (res2["flags"] & 1).any()
+
+
+# ----------------------------------------------------- disk and box footprints
+@pytest.mark.parametrize("kernel", ["box", "disk"])
+def test_linear_field_disk_box_closed_form(oracle_mod, kernel):
+    """Table notation: k_r of size 2 r_x x 2 r_y, zero beyond r; with a disk or box
+    footprint (normalised over its support, 1 / (4 r_x r_y) or 1 / (pi r_x r_y)) a
+    linear field gives D(h) = k(u(h) - x) / |det G| at the single preimage u(h):
+    the footprint weight switches on exactly where the preimage enters the support."""
+    nrm, G, nc, uc = linear_map()
+    dG = abs(np.linalg.det(G))
+    rng = np.random.default_rng(17)
+    s2r = 1.5
+    qs, refs, near, cells = [], [], [], []
+    for _ in range(60):
+        x, y = np.float32(rng.uniform(26, 38)), np.float32(rng.uniform(26, 38))
+        sx, sy = np.float32(rng.uniform(0.6, 3.0)), np.float32(rng.uniform(0.6, 3.0))
+        rx = float(np.float32(s2r) * sx)
+        ry = float(np.float32(s2r) * sy)
+        upre = np.array([x, y], dtype=np.float64) + rng.uniform(-1.4, 1.4, 2) * np.array([rx, ry])
+        h = (nc + G @ (upre - uc)).astype(np.float32)
+        u = uc + np.linalg.solve(G, h.astype(np.float64) - nc)
+        dx, dy = (u[0] - float(x)) / rx, (u[1] - float(y)) / ry
+        if kernel == "box":
+            inside = abs(dx) <= 1 and abs(dy) <= 1
+            edge = min(abs(abs(dx) - 1), abs(abs(dy) - 1))
+            w = 1.0 / (4 * rx * ry)
+        else:
+            inside = dx * dx + dy * dy <= 1
+            edge = abs(dx * dx + dy * dy - 1)
+            w = 1.0 / (math.pi * rx * ry)
+        refs.append(w / dG if inside else 0.0)
+        near.append(edge < 1e-6)
+        (clo, chi), (dlo, dhi) = cell_range(x, sx, s2r), cell_range(y, sy, s2r)
+        cells.append(clo <= u[0] <= chi + 1 and dlo <= u[1] <= dhi + 1)
+        qs.append([x, y, sx, sy, h[0], h[1]])
+    qs = np.array(qs, dtype=np.float32)
+    res = oracle_mod.evaluate(nrm, qs, sigma_to_r=s2r, kernel=kernel)
+    ok = (res["namb"] == 0) & ~np.array(near)
+    refs = np.array(refs)
+    assert ok.sum() >= 50 and (refs[ok] > 0).sum() >= 15 and (refs[ok] == 0).sum() >= 10
+    np.testing.assert_allclose(res["D"][ok], refs[ok], rtol=1e-9, atol=0)
+    # the hit is there whenever the preimage's cell is included, even with zero weight
+    cells = np.array(cells)
+    assert (res["nhit"][ok] == cells[ok].astype(int)).all()
+    assert (cells[ok] & (refs[ok] == 0)).sum() >= 3
+
+
+@pytest.mark.parametrize("kernel", ["box", "disk"])
+@pytest.mark.parametrize("n,x,y,s", [(8, 3.3, 4.6, 0.9), (4, 1.7, 2.2, 3.0)])
+def test_disk_box_mass_is_one(oracle_mod, kernel, n, x, y, s):
+    """Change of variables (Eq. gndf) with a normalised disk or box footprint: the
+    integral of D over the normal plane is the kernel's mass, 1 (the support lies
+    inside the included cells; the second case spans several periods)."""
+    nrm = random_disk_map(n, 11)
+    x, y, s = np.float32(x), np.float32(y), np.float32(s)
+    k = 1200
+    g = ((np.arange(k) + 0.5) / k * 1.2 - 0.6).astype(np.float32)
+    mx, my = np.meshgrid(g, g)
+    qs = np.zeros((k * k, 6), dtype=np.float32)
+    qs[:, 0], qs[:, 1], qs[:, 2], qs[:, 3] = x, y, s, s
+    qs[:, 4], qs[:, 5] = mx.ravel(), my.ravel()
+    D = oracle_mod.evaluate(nrm, qs, sigma_to_r=1.5, kernel=kernel)["D"]
+    assert D.sum() * (1.2 / k) ** 2 == pytest.approx(1.0, rel=1e-2)
