@@ -58,19 +58,20 @@ def algorithmic_bytes(counts, tau):
     return float(np.sum(28.0 + per_node * c[:, 0] + 9.0 * c[:, 1] + 41.0 * c[:, 2] + 4.0 * c[:, 3]))
 
 
-def load_traffic(workload, algo):
+def load_traffic(workload, algo, kernel="gaussian"):
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         t = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
-    if t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload or t.get("algo") != algo:
+    if (t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload or t.get("algo") != algo
+            or t.get("kernel", "gaussian") != kernel):
         return None
     return float(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(nrm, q, tau, budget_s=15.0):
+def cpu_baseline(nrm, q, tau, budget_s=15.0, kernel="gaussian", sigma_to_r=3.0):
     """The FP64 oracle, as it stands, on a bounded prefix of the same (randomly
     ordered) query stream, all host threads."""
     import oracle
@@ -78,11 +79,11 @@ def cpu_baseline(nrm, q, tau, budget_s=15.0):
     threads = oracle.num_threads()
     k = 256
     t0 = time.perf_counter()
-    oracle.evaluate(nrm, q[:k], tau=tau)
+    oracle.evaluate(nrm, q[:k], tau=tau, kernel=kernel, sigma_to_r=sigma_to_r)
     dt = time.perf_counter() - t0
     k2 = int(min(len(q), max(k, budget_s / max(dt, 1e-6) * k)))
     t0 = time.perf_counter()
-    oracle.evaluate(nrm, q[:k2], tau=tau)
+    oracle.evaluate(nrm, q[:k2], tau=tau, kernel=kernel, sigma_to_r=sigma_to_r)
     dt2 = time.perf_counter() - t0
     return {"value": k2 / dt2, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": "first %d queries of the same seeded stream (%.1f s, FP64 brute force over "
@@ -137,6 +138,21 @@ def serve_bench(args):
     print("[serve] plain per-tile: %.2f tiles/s (median tile %.2f ms, max %.1f ms)"
           % (plain_tiles_per_s, 1e3 * np.median(cost), 1e3 * cost.max()), file=sys.stderr, flush=True)
     qpt = tiles[0].shape[0]
+    # persistent per-tile cost (one plan per map, default tuning), each tile alone
+    plans = [P.Plan(h, qpt, tau=tau) for h in hiers]
+    for m, q in zip(mids[:4], dq[:4]):
+        plans[m].eval(q)
+    torch.cuda.synchronize()
+    cost_p = []
+    for m, q in zip(mids, dq):
+        a = time.perf_counter()
+        plans[m].eval(q)
+        torch.cuda.synchronize()
+        cost_p.append(time.perf_counter() - a)
+    cost_p = np.array(cost_p)
+    del plans
+    print("[serve] persistent per-tile: %.2f tiles/s (median tile %.2f ms, max %.1f ms)"
+          % (ntiles / cost_p.sum(), 1e3 * np.median(cost_p), 1e3 * cost_p.max()), file=sys.stderr, flush=True)
     results = []
     srv = P.Server(hiers, slots=args.serve_slots, max_batch_queries=qpt * args.serve_batch_tiles,
                    max_pending=4 * ntiles, tau=tau, algo=args.serve_algo)
@@ -145,12 +161,17 @@ def serve_bench(args):
         rate = frac * plain_tiles_per_s
         arr = np.cumsum(rng.exponential(1.0 / rate, ntiles))
         arr -= arr[0]
-        # FIFO per-tile plain evaluation at the same arrivals (simulated from measured costs)
-        free, lat_fifo = 0.0, []
-        for a, c in zip(arr, cost):
-            start = max(a, free)
-            free = start + c
-            lat_fifo.append(1e3 * (free - a))
+        # FIFO per-tile plain / persistent evaluation at the same arrivals (simulated
+        # from the measured costs)
+        def fifo(cst):
+            free, lat_f = 0.0, []
+            for a, c in zip(arr, cst):
+                start = max(a, free)
+                free = start + c
+                lat_f.append(1e3 * (free - a))
+            return lat_f, free
+        lat_fifo, free = fifo(cost)
+        lat_fifo_p, _ = fifo(cost_p)
         srv.reset_stats()
         a = time.perf_counter()
         outs, lat = srv.replay(mids, arr, tiles)
@@ -162,7 +183,9 @@ def serve_bench(args):
                         "mean_batch_tiles": st["mean_batch_requests"],
                         "fifo_plain_p50_ms": float(np.percentile(lat_fifo, 50)),
                         "fifo_plain_p99_ms": float(np.percentile(lat_fifo, 99)),
-                        "fifo_plain_queries_per_s": ntiles * qpt / max(free, arr[-1])})
+                        "fifo_plain_queries_per_s": ntiles * qpt / max(free, arr[-1]),
+                        "fifo_persistent_p50_ms": float(np.percentile(lat_fifo_p, 50)),
+                        "fifo_persistent_p99_ms": float(np.percentile(lat_fifo_p, 99))})
         print("[serve] %s" % json.dumps(results[-1]), file=sys.stderr, flush=True)
     # saturation throughput: everything arrives at once
     srv.reset_stats()
@@ -177,7 +200,12 @@ def serve_bench(args):
                                    "powerlaw8192", "tau": tau, "sigma_range": [0.5, smax],
                        "slots": args.serve_slots, "batch_tiles": args.serve_batch_tiles,
                        "batch_algo": args.serve_algo},
-            "plain_per_tile_queries_per_s": plain_tiles_per_s * qpt, "by_rate": results}
+            "plain_per_tile_queries_per_s": plain_tiles_per_s * qpt,
+            "persistent_per_tile_queries_per_s": ntiles * qpt / cost_p.sum(),
+            "per_tile_ms": {"plain_median": 1e3 * float(np.median(cost)), "plain_max": 1e3 * float(cost.max()),
+                            "persistent_median": 1e3 * float(np.median(cost_p)),
+                            "persistent_max": 1e3 * float(cost_p.max())},
+            "by_rate": results}
     print(json.dumps(line), flush=True)
 
 
@@ -192,6 +220,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-octaves", action="store_true")
     ap.add_argument("--input-order", action="store_true", help="keep the query order (no spatial ordering)")
+    ap.add_argument("--kernel", default="gaussian", choices=["gaussian", "disk", "box"],
+                    help="footprint kernel")
+    ap.add_argument("--sigma-to-r", type=float, default=None,
+                    help="support half-width in sigma (default 3 for gaussian, 1.5 for disk and box)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (continuous batching)")
     ap.add_argument("--serve-tau", type=float, default=1e-3)
     ap.add_argument("--serve-tiles", type=int, default=200)
@@ -226,6 +258,9 @@ def main():
     import paper_2505_08985_amd as P
     import workloads
 
+    kern = args.kernel
+    s2r = args.sigma_to_r if args.sigma_to_r is not None else (3.0 if kern == "gaussian" else 1.5)
+    kw = dict(kernel=kern, sigma_to_r=s2r)
     cfg = workloads.CONFIGS[args.workload]
     mc, qc, tau = cfg["map"], cfg["queries"], float(cfg["tau"])
     n = mc["n"]
@@ -253,16 +288,16 @@ def main():
     if args.algo == "persistent":
         sample = tq[:min(count, 1 << 14)]
         print("[bench] autotuning on %d queries ..." % sample.shape[0], file=sys.stderr, flush=True)
-        tuning, tms = P.autotune(hier, sample, tau=tau)
+        tuning, tms = P.autotune(hier, sample, tau=tau, **kw)
         print("[bench] autotuned %s (%.3f ms on %d queries)" % (tuning, tms, sample.shape[0]),
               file=sys.stderr, flush=True)
-        plan = P.Plan(hier, count, tau=tau, tuning=tuning)
+        plan = P.Plan(hier, count, tau=tau, tuning=tuning, **kw)
 
         def step():
             plan.eval(tq, out=out)
     else:
         def step():
-            P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out, input_order=args.input_order)
+            P.eval_batch(hier, tq, tau=tau, algo=args.algo, out=out, input_order=args.input_order, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -286,16 +321,16 @@ def main():
     if args.algo == "persistent":
         st = plan.stats()
         assert st["error"] == 0, st
-        ref = P.eval_batch(hier, tq, tau=tau)
+        ref = P.eval_batch(hier, tq, tau=tau, **kw)
         assert torch.equal(ref.view(torch.int32), out.view(torch.int32)), "persistent != plain"
     # instrumented launch: work units for the algorithmic byte count
-    _, counts = P.eval_counts(hier, tq, tau=tau, algo="brute" if args.algo == "brute" else "plain")
+    _, counts = P.eval_counts(hier, tq, tau=tau, algo="brute" if args.algo == "brute" else "plain", **kw)
     counts = counts.cpu().numpy()
     abytes = algorithmic_bytes(counts, tau)
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
     aops = algorithmic_ops(counts)
     achieved_ops = aops / (kernel_ms * 1e-3) / 1e12
-    traffic = load_traffic(args.workload, args.algo)
+    traffic = load_traffic(args.workload, args.algo, kern)
     work = {"nodes_per_query": float(counts[:, 0].mean()), "cells_per_query": float(counts[:, 1].mean()),
             "clusters_per_query": float(counts[:, 2].mean()), "hits_per_query": float(counts[:, 3].mean()),
             "algorithmic_bytes_per_launch": abytes, "algorithmic_alu_ops_per_launch": aops}
@@ -312,14 +347,14 @@ def main():
                 sq = tq[torch.from_numpy(sel).cuda()]
                 so = torch.empty(len(sel), dtype=torch.float32, device="cuda")
                 oalgo = "plain" if args.algo == "persistent" else args.algo
-                P.eval_batch(hier, sq, tau=tau, algo=oalgo, out=so)
+                P.eval_batch(hier, sq, tau=tau, algo=oalgo, out=so, **kw)
                 torch.cuda.synchronize()
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 reps = 3
                 for _ in range(reps):
-                    P.eval_batch(hier, sq, tau=tau, algo=oalgo, out=so)
+                    P.eval_batch(hier, sq, tau=tau, algo=oalgo, out=so, **kw)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 octaves["sigma %g-%g" % (a, b)] = len(sel) * reps / (e0.elapsed_time(e1) * 1e-3)
@@ -328,7 +363,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(nrm, q, tau)
+        cpu = cpu_baseline(nrm, q, tau, **kw)
 
     line = {
         "metric": METRIC,
@@ -345,7 +380,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "map": "%s %dx%d" % (mc["kind"], n, n), "queries": count,
                    "sigma": list(qc["sigma"]) if isinstance(qc["sigma"], tuple) else qc["sigma"],
-                   "h_radius": qc["radius"], "tau": tau, "algo": args.algo, "sigma_to_r": 3.0,
+                   "h_radius": qc["radius"], "tau": tau, "algo": args.algo, "kernel": kern, "sigma_to_r": s2r,
                    "tuning": tuning},
         "roofline": {"bound": "alu", "achieved": achieved_ops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
                      "frac": achieved_ops / ALU_PEAK_TOPS, "traffic": traffic},

@@ -19,12 +19,13 @@
  *     texel column 0, and footprints wider than the map sum every periodic image.
  *   - Normals and query normals are the xy components of unit vectors on the
  *     projected hemisphere (section "Preliminaries").
- *   - The footprint kernel is the normalised axis-aligned Gaussian of standard
- *     deviations (sx, sy); its support half-width is r = sigma_to_r * sigma (3 by
- *     default: the "(6 sigma)^2 footprint" of the ablation section), truncated at
- *     texel-cell granularity: every triangle of every periodic cell image whose
+ *   - The footprint kernel is by default the normalised axis-aligned Gaussian of
+ *     standard deviations (sx, sy); its support half-width is r = sigma_to_r * sigma
+ *     (3 by default: the "(6 sigma)^2 footprint" of the ablation section), truncated
+ *     at texel-cell granularity: every triangle of every periodic cell image whose
  *     closed unit square meets [x - r, x + r] (r, x - r, x + r rounded to float32)
- *     contributes, with the untruncated Gaussian.
+ *     contributes, with the untruncated Gaussian.  Disk and box kernels (see
+ *     PNDF_KERNEL_*) use the same cells and weigh each hit point by the kernel.
  *   - Triangles with Jacobian below eps (evaluated in FP64 from the float32 normals,
  *     strict <) are replaced by an equilateral triangle of area eps/2 centred at the
  *     cell-centre normal n(floor(u) + 1/2) = (n1 + n2)/2 (section "Preventing
@@ -65,7 +66,17 @@ typedef struct pndf_query {
     float x, y, sx, sy, hx, hy;
 } pndf_query;
 
-enum { PNDF_KERNEL_GAUSSIAN = 0 };
+/* Footprint kernels (Table notation: k_r of size 2 r_x x 2 r_y, zero beyond r).
+ * r = sigma_to_r * sigma per axis (float32 product) for every kernel.
+ *   GAUSSIAN  the normalised Gaussian of standard deviations (sx, sy), evaluated
+ *             untruncated at every contributing hit (cells meeting the support box);
+ *   DISK      1 / (pi r_x r_y) inside the ellipse of half-axes r around x, 0 outside;
+ *   BOX       1 / (4 r_x r_y) where |u - x| <= r per axis, 0 outside.
+ * DISK and BOX are truncated at the hit point (u* outside the support weighs 0; the
+ * triangle still counts as hit).  The ablation section ("Different footprint
+ * kernel") matches a Gaussian's (6 sigma)^2 footprint with a disk / box of
+ * (3 sigma)^2, i.e. sigma_to_r = 1.5 for the disk / box against 3 for the Gaussian. */
+enum { PNDF_KERNEL_GAUSSIAN = 0, PNDF_KERNEL_DISK = 1, PNDF_KERNEL_BOX = 2 };
 
 /* Evaluation algorithm.  All give the same result (the set of triangles is fixed
  * by the definition, not by the algorithm); they differ in speed. */
@@ -77,10 +88,10 @@ enum {
 };
 
 typedef struct pndf_eval_opts {
-    int32_t kernel;     /* PNDF_KERNEL_GAUSSIAN (the only kernel; anything else -> PNDF_EUNSUPPORTED) */
+    int32_t kernel;     /* PNDF_KERNEL_GAUSSIAN, _DISK or _BOX (anything else -> PNDF_EINVAL) */
     float tau;          /* cluster cut threshold: a node of level l >= 1 at or below the entry level is
                          * used as two cluster triangles when e^l <= fl(fl(r_x r_y) tau); 0 = exact */
-    float sigma_to_r;   /* support half-width in standard deviations; the paper's Gaussian uses 3 */
+    float sigma_to_r;   /* support half-width r = sigma_to_r * sigma; the paper's Gaussian uses 3 */
     int32_t algo;       /* PNDF_ALGO_* */
     int32_t flags;      /* PNDF_EVAL_INPUT_ORDER or 0 */
 } pndf_eval_opts;
@@ -271,6 +282,7 @@ typedef struct pndf_server_opts {
     int32_t algo;               /* evaluation of a batch: PNDF_ALGO_PLAIN (or AUTO): one
                                  * pndf_eval_batch on the slot's stream; PNDF_ALGO_PERSISTENT:
                                  * the slot's persistent plan for the batch's map */
+    int32_t kernel;             /* footprint kernel of every request (pndf_kernel) */
 } pndf_server_opts;
 
 typedef struct pndf_server_stats {

@@ -178,7 +178,11 @@ def build_hierarchy(mesh, cluster=True, stream=None):
 EVAL_INPUT_ORDER = 1
 
 
+KERNELS = {"gaussian": 0, "disk": 1, "box": 2}
+
+
 def _opts(tau, sigma_to_r, algo, kernel=0, flags=0):
+    kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     return EvalOpts(int(kernel), float(tau), float(sigma_to_r), ALGOS[algo] if isinstance(algo, str) else int(algo),
                     int(flags))
 
@@ -200,24 +204,24 @@ def eval_batch(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, st
     return out
 
 
-def eval_counts(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", stream=None):
+def eval_counts(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", stream=None, kernel=0):
     """Returns (D, counts (Q, 4) int32: nodes, cells, clusters, hits)."""
     qp, nq = _queries(queries)
     out = torch.empty(nq, dtype=torch.float32, device=queries.device)
     counts = torch.zeros((nq, 4), dtype=torch.int32, device=queries.device)
-    o = _opts(tau, sigma_to_r, algo)
+    o = _opts(tau, sigma_to_r, algo, kernel)
     _check(_eval_counts(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
                         _dev_ptr(counts, torch.int32, "counts"), _stream(stream)), "pndf_eval_counts")
     return out, counts
 
 
-def eval_hits(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", capacity=None, stream=None):
+def eval_hits(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", capacity=None, stream=None, kernel=0):
     """Returns (D, offsets (Q+1,) int64, ids (H,) int64, terms (H,) float32)."""
     qp, nq = _queries(queries)
     dev = queries.device
     out = torch.empty(nq, dtype=torch.float32, device=dev)
     offs = torch.zeros(nq + 1, dtype=torch.int64, device=dev)
-    o = _opts(tau, sigma_to_r, algo)
+    o = _opts(tau, sigma_to_r, algo, kernel)
     req = _u64(0)
     cap = 0 if capacity is None else int(capacity)
     ids = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
@@ -278,10 +282,11 @@ def hier_export_level(hier, level, stream=None):
 class Plan:
     """Persistent work-stealing evaluation plan (workspace + instantiated HIP graph)."""
 
-    def __init__(self, hier, max_nq, tau=0.0, sigma_to_r=3.0, tuning=None, stream=None, input_order=False):
+    def __init__(self, hier, max_nq, tau=0.0, sigma_to_r=3.0, tuning=None, stream=None, input_order=False,
+                 kernel=0):
         self.hier = hier  # the hierarchy must outlive the plan
         self.max_nq = int(max_nq)
-        o = _opts(tau, sigma_to_r, "persistent", flags=EVAL_INPUT_ORDER if input_order else 0)
+        o = _opts(tau, sigma_to_r, "persistent", kernel, flags=EVAL_INPUT_ORDER if input_order else 0)
         t = None
         if tuning is not None:
             t = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
@@ -322,10 +327,10 @@ def default_tuning(hier):
     return t.as_dict()
 
 
-def autotune(hier, queries, tau=0.0, sigma_to_r=3.0, stream=None):
+def autotune(hier, queries, tau=0.0, sigma_to_r=3.0, stream=None, kernel=0):
     """Returns (best tuning dict, ms per batch of `queries`)."""
     qp, nq = _queries(queries)
-    o = _opts(tau, sigma_to_r, "persistent")
+    o = _opts(tau, sigma_to_r, "persistent", kernel)
     t = Tuning()
     ms = ctypes.c_double(0)
     _check(_autotune(hier.handle, qp, nq, ctypes.byref(o), ctypes.byref(t), ctypes.byref(ms), _stream(stream)),
@@ -335,7 +340,7 @@ def autotune(hier, queries, tau=0.0, sigma_to_r=3.0, stream=None):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", _i32), ("max_batch_queries", _i64), ("memory_budget", _i64), ("max_pending", _i32),
-                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning), ("algo", _i32)]
+                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning), ("algo", _i32), ("kernel", _i32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -365,7 +370,7 @@ class Server:
     """Continuous-batching server over resident hierarchies (host-side requests)."""
 
     def __init__(self, hiers, slots=2, max_batch_queries=1 << 16, memory_budget=None, max_pending=256,
-                 tau=0.0, sigma_to_r=3.0, tuning=None, algo="plain"):
+                 tau=0.0, sigma_to_r=3.0, tuning=None, algo="plain", kernel=0):
         import numpy as np
         self._np = np
         self.hiers = list(hiers)  # keep the hierarchies alive
@@ -373,7 +378,8 @@ class Server:
             memory_budget = 28 * max_batch_queries * max(4, 2 * slots) + 4096
         t = Tuning(0, 1, 16, 1) if tuning is None else (tuning if isinstance(tuning, Tuning) else Tuning(**tuning))
         o = ServerOpts(int(slots), int(max_batch_queries), int(memory_budget), int(max_pending), float(tau),
-                       float(sigma_to_r), t, ALGOS[algo] if isinstance(algo, str) else int(algo))
+                       float(sigma_to_r), t, ALGOS[algo] if isinstance(algo, str) else int(algo),
+                       KERNELS[kernel] if isinstance(kernel, str) else int(kernel))
         arr = (_vp * len(self.hiers))(*[h.handle for h in self.hiers])
         h = _vp()
         _check(_server_create(arr, len(self.hiers), ctypes.byref(o), ctypes.byref(h)), "pndf_server_create")

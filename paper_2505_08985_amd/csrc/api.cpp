@@ -89,10 +89,8 @@ static pndf_status resolve_opts(const pndf_hier* h, const pndf_eval_opts* o, pnd
     d.algo = PNDF_ALGO_AUTO;
     d.flags = 0;
     if (o) d = *o;
-    if (d.kernel != PNDF_KERNEL_GAUSSIAN) {
-        set_error("only the Gaussian footprint kernel is implemented");
-        return PNDF_EUNSUPPORTED;
-    }
+    if (d.kernel != PNDF_KERNEL_GAUSSIAN && d.kernel != PNDF_KERNEL_DISK && d.kernel != PNDF_KERNEL_BOX)
+        return invalid("unknown footprint kernel");
     if (!(std::isfinite(d.tau) && d.tau >= 0.f)) return invalid("tau must be finite and >= 0");
     if (!(std::isfinite(d.sigma_to_r) && d.sigma_to_r > 0.f))
         return invalid("sigma_to_r must be finite and > 0");
@@ -314,7 +312,7 @@ pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t n
     hipError_t e = hipSuccess;
     if (nq >= kOrderMin && o.algo != PNDF_ALGO_BRUTE && !(o.flags & PNDF_EVAL_INPUT_ORDER))
         e = make_order(h->dev, d_q, nq, &order, s);
-    EvalArgs a{d_q, order, nq, 0, 0, d_out, nullptr, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    EvalArgs a{d_q, order, nq, 0, 0, d_out, nullptr, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r, o.kernel};
     if (e == hipSuccess) e = launch_eval(h->dev, a, o.algo, s);
     free_order(order, s);
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_batch");
@@ -328,7 +326,7 @@ pndf_status pndf_eval_counts(const pndf_hier* h, const pndf_query* d_q, int64_t 
     pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
     if (st != PNDF_OK) return st;
     if (nq > 0 && !d_counts) return invalid("counts pointer is NULL");
-    EvalArgs a{d_q, nullptr, nq, 0, 0, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    EvalArgs a{d_q, nullptr, nq, 0, 0, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r, o.kernel};
     hipError_t e = launch_eval(h->dev, a, o.algo, (hipStream_t)stream);
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_counts");
 }
@@ -350,7 +348,7 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
     uint32_t* d_counts = nullptr;
     hipError_t e = hipMalloc(&d_counts, sizeof(uint32_t) * 4 * (size_t)nq);
     if (e != hipSuccess) return hip_fail(e, "pndf_eval_hits");
-    EvalArgs a{d_q, nullptr, nq, 0, 0, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r};
+    EvalArgs a{d_q, nullptr, nq, 0, 0, d_out, d_counts, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r, o.kernel};
     e = launch_eval(h->dev, a, o.algo, s);
     std::vector<uint32_t> counts((size_t)nq * 4);
     if (e == hipSuccess)
@@ -362,7 +360,7 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
         e = hipMemcpyAsync(d_offsets, offs.data(), sizeof(uint64_t) * (nq + 1), hipMemcpyHostToDevice, s);
     *required = offs[nq];
     if (e == hipSuccess && offs[nq] <= capacity && offs[nq] > 0) {
-        EvalArgs b{d_q, nullptr, nq, 0, 0, d_out, nullptr, d_offsets, d_ids, d_terms, o.tau, o.sigma_to_r};
+        EvalArgs b{d_q, nullptr, nq, 0, 0, d_out, nullptr, d_offsets, d_ids, d_terms, o.tau, o.sigma_to_r, o.kernel};
         e = launch_eval(h->dev, b, o.algo, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -43,13 +43,14 @@ struct Rec {  // hit-record cursor (record mode)
 };
 
 // FP64 confirmation of a float32 hit, barycentrics and term; < 0 if rejected.
+template <int KER>
 __device__ __forceinline__ double confirm_and_term(const QuerySetup& q, const double v[6], int I,
                                                    int J, int lev, int half, float det_used,
                                                    int logn)
 {
     double l1, l2;
     if (!tri_bary_f64(v, (double)q.hx, (double)q.hy, &l1, &l2)) return -1.0;
-    return hit_term(q, I, J, lev, half, l1, l2, det_used, logn);
+    return hit_term<KER>(q, I, J, lev, half, l1, l2, det_used, logn);
 }
 
 // Per-lane hit sink of one hit-processing round: value/count modes add the term to
@@ -201,7 +202,7 @@ __device__ __forceinline__ uint32_t cluster_mask(const HierDev& H, const QuerySe
 }
 
 // ---- FP64 stage: one queued hit.
-template <int MODE>
+template <int MODE, int KER>
 __device__ __forceinline__ void hit_entry(const HierDev& H, const QuerySetup& q, uint32_t e, Acc& acc,
                                           HitSink<MODE>& hs)
 {
@@ -258,7 +259,7 @@ __device__ __forceinline__ void hit_entry(const HierDev& H, const QuerySetup& q,
             v[0] = n3.x; v[1] = n3.y; v[2] = n2.x; v[3] = n2.y; v[4] = n1.x; v[5] = n1.y;
         }
     }
-    const double t = confirm_and_term(q, v, I, J, lev, half, det_used, H.logn);
+    const double t = confirm_and_term<KER>(q, v, I, J, lev, half, det_used, H.logn);
     if (t >= 0.0) hs.put(q, acc, tri_id(lev, I, J, half), t);
 }
 
@@ -266,12 +267,12 @@ __device__ __forceinline__ void hit_entry(const HierDev& H, const QuerySetup& q,
 // Each lane's float32 hits wait in a bit mask (entry ebase | bit) until they are
 // queued; the traversal loops run a round of the FP64 stage (hit_round, one call
 // site per kernel so it is inlined once) whenever 64 hits are queued and at the end.
-template <int MODE>
+template <int MODE, int KER>
 __device__ __forceinline__ void hit_round(const HierDev& H, const QuerySetup& q, const uint32_t* src, int cnt,
                                           Acc& acc, Rec& rec)
 {
     HitSink<MODE> hs;
-    if (lane_id() < cnt) hit_entry<MODE>(H, q, src[lane_id()], acc, hs);
+    if (lane_id() < cnt) hit_entry<MODE, KER>(H, q, src[lane_id()], acc, hs);
     flush_records<MODE>(hs, rec);
     wave_sync();
 }
@@ -308,7 +309,7 @@ __device__ __forceinline__ bool in_box(const QuerySetup& q, const float4& bb)
 // pending work before each step: half of the items of its highest non-empty list
 // (the largest subtrees it holds), if that level is at least split_level, become
 // tasks of the global queue.  A full queue simply leaves them here.
-template <int MODE, bool CUT, bool SPAWN>
+template <int MODE, bool CUT, bool SPAWN, int KER>
 __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, int root_level,
                         bool root_ok, uint32_t root_item, bool roots_tested, int split_level,
                         unsigned long long qidx, const TaskQueue& Q, Acc& acc, Rec& rec)
@@ -351,7 +352,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             // (lanes still holding hits imply a full queue, so they get here too)
             const int c = min(hn, 64);
             hn -= c;
-            hit_round<MODE>(H, q, hq + hn, c, acc, rec);
+            hit_round<MODE, KER>(H, q, hq + hn, c, acc, rec);
             continue;
         }
         if (!nonempty) break;
@@ -559,14 +560,14 @@ __device__ __forceinline__ void invalid(const EvalArgs& a, int64_t qi)
 }
 
 // ------------------------------------------------------------ brute force
-template <int MODE>
+template <int MODE, int KER>
 __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
 {
     const int64_t local = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (local >= a.slots) return;
     const int64_t qi = a.slot0 + local;
     const int lane = threadIdx.x & 63;
-    const QuerySetup q = uniform_query(setup_query(a.q[qi], a.s2r, 0.f, H.L, H.eps));
+    const QuerySetup q = uniform_query(setup_query(a.q[qi], a.s2r, 0.f, H.L, H.eps, a.kernel));
     if (!q.valid) { invalid<MODE>(a, qi); return; }
     const int n = H.n, msk = n - 1;
     const int spanx = q.cxhi - q.cxlo + 1, spany = q.cyhi - q.cylo + 1;
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
         if (hn >= 64 || (hn > 0 && base >= total)) {
             const int c = min(hn, 64);
             hn -= c;
-            hit_round<MODE>(H, q, hq + hn, c, acc, rec);
+            hit_round<MODE, KER>(H, q, hq + hn, c, acc, rec);
             continue;
         }
         if (base >= total) break;
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
 
 // One wavefront per workgroup (a long query holds only its own LDS).  LDS: L lists
 // of kListCap node entries (levels 1..L) + the leaf queue.
-template <int MODE, bool CUT>
+template <int MODE, bool CUT, int KER>
 __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
 {
     extern __shared__ uint32_t lds[];
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
     const int64_t slot = a.slot0 + local;
     const int64_t qi = a.order ? (int64_t)a.order[slot] : slot;
     uint32_t* lists = lds;
-    const QuerySetup q = uniform_query(setup_query(a.q[qi], a.s2r, CUT ? a.tau : 0.f, H.L, H.eps));
+    const QuerySetup q = uniform_query(setup_query(a.q[qi], a.s2r, CUT ? a.tau : 0.f, H.L, H.eps, a.kernel));
     if (!q.valid) { invalid<MODE>(a, qi); return; }
     Acc acc;
     Rec rec{a.ids, a.terms, MODE == kModeRecord ? a.offsets[qi] : 0,
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
     bool ok;
     const uint32_t item = root_item(H, q, &ok);
     TaskQueue none{};
-    descend<MODE, CUT, false>(H, q, lists, q.l0, ok, item, false, 0, 0, none, acc, rec);
+    descend<MODE, CUT, false, KER>(H, q, lists, q.l0, ok, item, false, 0, 0, none, acc, rec);
     finish<MODE>(a, qi, q, acc);
 }
 
@@ -721,7 +722,7 @@ __device__ __forceinline__ void unit_done(QueueCtl* ctl, long long nq)
 // with a short exponential back-off and, now and then, whether the run is over
 // (every query taken and nothing outstanding).
 // (5 waves per SIMD fit without spilling vector registers)
-template <bool CUT>
+template <bool CUT, int KER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_persist(HierDev H, PersistArgs pa)
 {
     extern __shared__ uint32_t lds[];
@@ -867,7 +868,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             root_ok = false;
             tested = false;
         }
-        const QuerySetup q = uniform_query(setup_query(qs[qi], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps));
+        const QuerySetup q = uniform_query(setup_query(qs[qi], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps, pa.kernel));
         Acc acc;
         if (lev < 0) {
             lev = q.l0;
@@ -876,7 +877,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         // a query whose levels are all below split_level never donates; a stolen
         // subtree may be split again
         if (q.valid)
-            descend<kModeValue, CUT, true>(H, q, lists, lev, root_ok, item, tested, pa.split_level,
+            descend<kModeValue, CUT, true, KER>(H, q, lists, lev, root_ok, item, tested, pa.split_level,
                                            (unsigned long long)qi, pa.Q, acc, rec);
         const Fix192 d = wave_sum_fix(acc.d);
         if (lane == 0) {
@@ -913,7 +914,7 @@ __global__ void k_persist_finalize(const QueueCtl* ctl, const Fix192* acc, const
 // Launches cover at most kChunk queries (grid dimensions stay far below 2^32 work-items).
 constexpr int64_t kChunk = (int64_t)1 << 24;
 
-template <int MODE>
+template <int MODE, int KER>
 hipError_t launch_mode(const HierDev& H, const EvalArgs& a0, int algo, hipStream_t s)
 {
     for (int64_t off = 0; off < a0.nq; off += kChunk) {
@@ -922,19 +923,27 @@ hipError_t launch_mode(const HierDev& H, const EvalArgs& a0, int algo, hipStream
         a.slots = std::min<int64_t>(kChunk, a0.nq - off);
         if (algo == PNDF_ALGO_BRUTE) {
             const unsigned blocks = (unsigned)((a.slots + 3) / 4);
-            hipLaunchKernelGGL(k_eval_brute<MODE>, dim3(blocks), dim3(256), 0, s, H, a);
+            hipLaunchKernelGGL((k_eval_brute<MODE, KER>), dim3(blocks), dim3(256), 0, s, H, a);
         } else {
             const unsigned blocks = (unsigned)a.slots;
             const size_t lds = sizeof(uint32_t) * wave_lds_words(H.L);
             if (a.tau > 0.f)
-                hipLaunchKernelGGL((k_eval_plain<MODE, true>), dim3(blocks), dim3(64), lds, s, H, a);
+                hipLaunchKernelGGL((k_eval_plain<MODE, true, KER>), dim3(blocks), dim3(64), lds, s, H, a);
             else
-                hipLaunchKernelGGL((k_eval_plain<MODE, false>), dim3(blocks), dim3(64), lds, s, H, a);
+                hipLaunchKernelGGL((k_eval_plain<MODE, false, KER>), dim3(blocks), dim3(64), lds, s, H, a);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int MODE>
+hipError_t launch_kernel(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s)
+{
+    if (a.kernel == PNDF_KERNEL_BOX) return launch_mode<MODE, PNDF_KERNEL_BOX>(H, a, algo, s);
+    if (a.kernel == PNDF_KERNEL_DISK) return launch_mode<MODE, PNDF_KERNEL_DISK>(H, a, algo, s);
+    return launch_mode<MODE, PNDF_KERNEL_GAUSSIAN>(H, a, algo, s);
 }
 
 // ------------------------------------------------------------ query order
@@ -1068,9 +1077,9 @@ void free_order(uint32_t* order, hipStream_t s)
 hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s)
 {
     if (a.nq <= 0) return hipSuccess;
-    if (a.offsets) return launch_mode<kModeRecord>(H, a, algo, s);
-    if (a.counts) return launch_mode<kModeCount>(H, a, algo, s);
-    return launch_mode<kModeValue>(H, a, algo, s);
+    if (a.offsets) return launch_kernel<kModeRecord>(H, a, algo, s);
+    if (a.counts) return launch_kernel<kModeCount>(H, a, algo, s);
+    return launch_kernel<kModeValue>(H, a, algo, s);
 }
 
 // ---------------------------------------------------------------- persistent
@@ -1097,6 +1106,16 @@ static void reset_params(PersistPlan& P, const pndf_query* q, long long nq, floa
     P.reset.sharedMemBytes = 0;
     P.reset.kernelParams = P.rargs;
     P.reset.extra = nullptr;
+}
+
+// The worker kernel for a plan's cut setting and footprint kernel.
+static void* persist_func(const PersistPlan& P)
+{
+    const bool cut = P.tau > 0.f;
+    if (P.kernel == PNDF_KERNEL_BOX) return cut ? (void*)k_persist<true, PNDF_KERNEL_BOX> : (void*)k_persist<false, PNDF_KERNEL_BOX>;
+    if (P.kernel == PNDF_KERNEL_DISK)
+        return cut ? (void*)k_persist<true, PNDF_KERNEL_DISK> : (void*)k_persist<false, PNDF_KERNEL_DISK>;
+    return cut ? (void*)k_persist<true, PNDF_KERNEL_GAUSSIAN> : (void*)k_persist<false, PNDF_KERNEL_GAUSSIAN>;
 }
 
 static unsigned order_grid(long long nq)
@@ -1148,6 +1167,7 @@ void persist_prepare(const HierDev& H, PersistPlan& P)
     P.pa.fexp = P.fexp;
     P.pa.tau = P.tau;
     P.pa.s2r = P.s2r;
+    P.pa.kernel = P.kernel;
     P.pa.split_level = P.split_level;
     P.pa.wait_ticks = P.wait_ticks;
     P.okey = P.ohist = nullptr;
@@ -1167,7 +1187,7 @@ hipError_t persist_graph_build(const HierDev& H, PersistPlan& P)
     P.wargs[0] = &P.H;
     P.wargs[1] = &P.pa;
     hipKernelNodeParams work{};
-    work.func = P.tau > 0.f ? (void*)k_persist<true> : (void*)k_persist<false>;
+    work.func = persist_func(P);
     work.gridDim = dim3((unsigned)P.blocks);
     work.blockDim = dim3(256);
     work.sharedMemBytes = (unsigned)(sizeof(uint32_t) * 4 * wave_lds_words(H.L));
@@ -1219,10 +1239,9 @@ hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float*
                            P.ohist, P.order);
     }
     const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(P.H.L);
-    if (P.tau > 0.f)
-        hipLaunchKernelGGL(k_persist<true>, dim3((unsigned)P.blocks), dim3(256), lds, s, P.H, P.pa);
-    else
-        hipLaunchKernelGGL(k_persist<false>, dim3((unsigned)P.blocks), dim3(256), lds, s, P.H, P.pa);
+    void* args[] = {&P.H, &P.pa};
+    const hipError_t e = hipLaunchKernel(persist_func(P), dim3((unsigned)P.blocks), dim3(256), args, lds, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_persist_finalize, P.reset.gridDim, dim3(256), 0, s, P.ctl, P.acc, P.fexp);
     return hipGetLastError();
 }

@@ -81,10 +81,8 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     if (max_nq < 1 || max_nq >= ((int64_t)1 << 32)) return plan_invalid("max_nq must be in [1, 2^32)");
     pndf_eval_opts o{PNDF_KERNEL_GAUSSIAN, 0.f, 3.f, PNDF_ALGO_PERSISTENT, 0};
     if (opts) o = *opts;
-    if (o.kernel != PNDF_KERNEL_GAUSSIAN) {
-        set_error("only the Gaussian footprint kernel is implemented");
-        return PNDF_EUNSUPPORTED;
-    }
+    if (o.kernel != PNDF_KERNEL_GAUSSIAN && o.kernel != PNDF_KERNEL_DISK && o.kernel != PNDF_KERNEL_BOX)
+        return plan_invalid("unknown footprint kernel");
     if (!(std::isfinite(o.tau) && o.tau >= 0.f)) return plan_invalid("tau must be finite and >= 0");
     if (!(std::isfinite(o.sigma_to_r) && o.sigma_to_r > 0.f)) return plan_invalid("sigma_to_r must be > 0");
     if (o.flags & ~PNDF_EVAL_INPUT_ORDER) return plan_invalid("unknown flags");
@@ -111,6 +109,7 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     P.wait_ticks = wall_ticks(30.0);
     P.tau = o.tau;
     P.s2r = o.sigma_to_r;
+    P.kernel = o.kernel;
     hipError_t e = hipMalloc(&P.ctl, sizeof(QueueCtl));
     if (e == hipSuccess) e = hipMalloc(&P.acc, sizeof(Fix192) * (size_t)max_nq);
     if (e == hipSuccess) e = hipMalloc(&P.fexp, sizeof(int) * (size_t)max_nq);

@@ -65,7 +65,8 @@ struct HierDev {
 // levels below hold sum_{k=1}^{l-1} (n / 2^k)^2 = (n^2 - (n / 2^(l-1))^2) / 3 nodes.
 __host__ __device__ __forceinline__ int64_t level_offset(int logn, int l)
 {
-    return ((int64_t)1 << (2 * logn)) / 3 - ((int64_t)1 << (2 * (logn - l + 1))) / 3;
+    // 32-bit arithmetic suffices (n <= 8192: 4^13 = 2^26 nodes at most)
+    return (int64_t)(((1u << (2 * logn)) - (1u << (2 * (logn - l + 1)))) / 3u);
 }
 
 // ---- exact accumulation: unsigned 192-bit fixed point w0 + 2^64 w1 + 2^128 w2, in
@@ -118,6 +119,7 @@ struct PersistArgs {
     Fix192* acc;     // per-query exact sums
     int* fexp;       // per-query binary point (written by the query's root task)
     float tau, s2r;
+    int kernel;           // PNDF_KERNEL_*
     int split_level;      // smallest level whose nodes may be donated (>= 1)
     long long wait_ticks; // give-up bound of a worker's waits, in wall_clock64 ticks
 };
@@ -136,6 +138,7 @@ struct PersistPlan {
     int blocks = 0, split_level = 1;
     long long wait_ticks = 0;
     float tau = 0.f, s2r = 3.f;
+    int kernel = 0;
     unsigned epoch = 0;
     HierDev H{};
     PersistArgs pa{};
@@ -219,6 +222,7 @@ struct EvalArgs {
     float* terms;
     float tau;
     float s2r;
+    int kernel;                // PNDF_KERNEL_*
 };
 hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s);
 
@@ -242,21 +246,24 @@ __device__ __forceinline__ int ceil_div_pow2(int a, int logn) { return -((-a) >>
 
 // Per-query constants, identical for every lane of the wave that owns the query.
 struct QuerySetup {
+    int kernel;                  // PNDF_KERNEL_*
+    float rx, ry;                // support half-widths (disk / box radii)
     float x, y, hx, hy;
     int cxlo, cxhi, cylo, cyhi;  // included unrolled cell range per axis
     int l0;                      // entry level
     float t;                     // cut threshold fl(fl(rx ry) tau)
-    double kx, ky;               // log2(e) / (2 sigma^2)
-    double norm;                 // 1 / (2 pi sx sy)
+    double kx, ky;               // Gaussian: log2(e) / (2 sigma^2)
+    double norm;                 // the kernel's peak: 1 / (2 pi sx sy), 1 / (pi rx ry) or 1 / (4 rx ry)
     int fexp;                    // binary point of the exact accumulator (units of 2^fexp)
     bool valid;
 };
 
 // Support box, entry level and kernel constants of one query (see pndf.h).
 __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float tau, int L,
-                                         float eps)
+                                         float eps, int kernel)
 {
     QuerySetup q;
+    q.kernel = kernel;
     q.x = qr.x; q.y = qr.y; q.hx = qr.hx; q.hy = qr.hy;
     const float lim = 16777216.0f;
     bool ok = isfinite(qr.x) && isfinite(qr.y) && isfinite(qr.sx) && isfinite(qr.sy) &&
@@ -264,6 +271,8 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     float rx = __fmul_rn(s2r, qr.sx), ry = __fmul_rn(s2r, qr.sy);
     ok = ok && fabsf(qr.x) <= lim && fabsf(qr.y) <= lim && rx <= lim && ry <= lim;
     q.valid = ok;
+    q.rx = rx;
+    q.ry = ry;
     if (!ok) {
         q.cxlo = q.cylo = 0; q.cxhi = q.cyhi = -1; q.l0 = 0; q.t = -1.f;
         q.kx = q.ky = q.norm = 0.0;
@@ -282,7 +291,10 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     const double log2e = 1.4426950408889634074;
     q.kx = log2e / (2.0 * (double)qr.sx * (double)qr.sx);
     q.ky = log2e / (2.0 * (double)qr.sy * (double)qr.sy);
-    const double norm = 1.0 / (2.0 * 3.14159265358979323846 * (double)qr.sx * (double)qr.sy);
+    const double pi = 3.14159265358979323846;
+    const double norm = kernel == PNDF_KERNEL_BOX    ? 1.0 / (4.0 * (double)rx * (double)ry)
+                        : kernel == PNDF_KERNEL_DISK ? 1.0 / (pi * (double)rx * (double)ry)
+                                                     : 1.0 / (2.0 * pi * (double)qr.sx * (double)qr.sy);
     q.norm = norm;
     // Every term is at most norm / eps per included cell image and triangle (node
     // images of a cluster reach at most one cell beyond the box per side), so
@@ -319,6 +331,8 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
 __device__ __forceinline__ QuerySetup uniform_query(const QuerySetup& q)
 {
     QuerySetup u;
+    u.kernel = __builtin_amdgcn_readfirstlane(q.kernel);
+    u.rx = uniform_f32(q.rx); u.ry = uniform_f32(q.ry);
     u.x = uniform_f32(q.x); u.y = uniform_f32(q.y); u.hx = uniform_f32(q.hx); u.hy = uniform_f32(q.hy);
     u.cxlo = __builtin_amdgcn_readfirstlane(q.cxlo); u.cxhi = __builtin_amdgcn_readfirstlane(q.cxhi);
     u.cylo = __builtin_amdgcn_readfirstlane(q.cylo); u.cyhi = __builtin_amdgcn_readfirstlane(q.cyhi);
@@ -455,24 +469,66 @@ __device__ inline bool tri_bary_f64(const double v[6], double hx, double hy, dou
     double cx = v[4] - hx, cy = v[5] - hy;
     double e0 = bx * cy - by * cx, e1 = cx * ay - cy * ax, e2 = ax * by - ay * bx;
     bool in = (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) || (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0);
-    double S = e0 + e1 + e2;
-    *l1 = e1 / S;
-    *l2 = e2 / S;
+    const double inv = 1.0 / (e0 + e1 + e2);  // one division for both coordinates
+    *l1 = e1 * inv;
+    *l2 = e2 * inv;
     return in;
 }
 
 // Contribution of a hit: the triangle's uv vertices are (a, b, c) =
 // lower: (U0, U0 + s e_x, U0 + s e_y), upper: (U3, U3 - s e_x, U3 - s e_y) of the node
 // (I, J) of side s = 2^lev (lev = 0: texel cell), so u* = corner +- s (l1, l2).
+// Box footprint along one axis: the number of included periodic images of the
+// point start + uoff within r of x.
+__device__ inline double box_axis(float x, float r, int start, int side, double uoff, int clo, int chi, int logn)
+{
+    const int p0 = ceil_div_pow2(clo - start - side + 1, logn);
+    const int p1 = floor_div_pow2(chi - start, logn);
+    const double base = (double)start + uoff - (double)x;
+    double c = 0.0;
+    for (int p = p0; p <= p1; ++p) c += fabs(base + (double)p * (double)(1 << logn)) <= (double)r ? 1.0 : 0.0;
+    return c;
+}
+
+// Disk footprint: the number of included periodic images of the point inside the
+// ellipse of half-axes (rx, ry) around x.
+__device__ inline double disk_images(const QuerySetup& q, int sx0, int sy0, int side, double ux, double uy, int logn)
+{
+    const int p0 = ceil_div_pow2(q.cxlo - sx0 - side + 1, logn), p1 = floor_div_pow2(q.cxhi - sx0, logn);
+    const int r0 = ceil_div_pow2(q.cylo - sy0 - side + 1, logn), r1 = floor_div_pow2(q.cyhi - sy0, logn);
+    const double bx = (double)sx0 + ux - (double)q.x, by = (double)sy0 + uy - (double)q.y;
+    const double period = (double)(1 << logn);
+    double c = 0.0;
+    for (int p = p0; p <= p1; ++p) {
+        const double dx = (bx + (double)p * period) / (double)q.rx;
+        for (int r = r0; r <= r1; ++r) {
+            const double dy = (by + (double)r * period) / (double)q.ry;
+            c += dx * dx + dy * dy <= 1.0 ? 1.0 : 0.0;
+        }
+    }
+    return c;
+}
+
+// (the footprint kernel KER is a template parameter: each kernel's evaluation code
+// is compiled separately, so the Gaussian path carries none of the others' registers)
+template <int KER>
 __device__ inline double hit_term(const QuerySetup& q, int I, int J, int lev, int half, double l1,
                                   double l2, float det_used, int logn)
 {
     const int s = 1 << lev;
     double ux = half ? (double)s * (1.0 - l1) : (double)s * l1;
     double uy = half ? (double)s * (1.0 - l2) : (double)s * l2;
-    const double gx = gauss_axis(q.x, q.kx, I * s, s, ux, q.cxlo, q.cxhi, logn);
-    const double gy = gauss_axis(q.y, q.ky, J * s, s, uy, q.cylo, q.cyhi, logn);
-    return q.norm * gx * gy / (double)det_used;
+    double w;
+    if constexpr (KER == PNDF_KERNEL_BOX) {
+        w = box_axis(q.x, q.rx, I * s, s, ux, q.cxlo, q.cxhi, logn) *
+            box_axis(q.y, q.ry, J * s, s, uy, q.cylo, q.cyhi, logn);
+    } else if constexpr (KER == PNDF_KERNEL_DISK) {
+        w = disk_images(q, I * s, J * s, s, ux, uy, logn);
+    } else {
+        w = gauss_axis(q.x, q.kx, I * s, s, ux, q.cxlo, q.cxhi, logn) *
+            gauss_axis(q.y, q.ky, J * s, s, uy, q.cylo, q.cyhi, logn);
+    }
+    return q.norm * w / (double)det_used;
 }
 
 __device__ __forceinline__ uint64_t tri_id(int lev, int I, int J, int half)

@@ -192,7 +192,7 @@ hipError_t launch_slot(pndf_server* s, Slot& sl)
         if (s->opts.algo == PNDF_ALGO_PERSISTENT) {
             st = pndf_plan_eval(sl.plans[map], sl.d_q, off, sl.d_out, sl.stream);
         } else {
-            const pndf_eval_opts eo{PNDF_KERNEL_GAUSSIAN, s->opts.tau, s->opts.sigma_to_r, PNDF_ALGO_PLAIN, 0};
+            const pndf_eval_opts eo{s->opts.kernel, s->opts.tau, s->opts.sigma_to_r, PNDF_ALGO_PLAIN, 0};
             st = pndf_eval_batch(s->maps[map], sl.d_q, off, &eo, sl.d_out, sl.stream);
         }
         if (st != PNDF_OK) e = hipErrorLaunchFailure;
@@ -347,6 +347,7 @@ pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, cons
     if (o.memory_budget < (int64_t)(28 * o.max_batch_queries + 512)) return fail("memory budget below one batch");
     if (o.algo != PNDF_ALGO_AUTO && o.algo != PNDF_ALGO_PLAIN && o.algo != PNDF_ALGO_PERSISTENT)
         return fail("algo must be AUTO, PLAIN or PERSISTENT");
+    if (o.kernel < PNDF_KERNEL_GAUSSIAN || o.kernel > PNDF_KERNEL_BOX) return fail("unknown kernel");
     if (o.tau > 0.f)
         for (int k = 0; k < nmaps; ++k)
             if (!maps[k]->cluster) return fail("tau > 0 needs hierarchies built with clusters");
@@ -359,7 +360,7 @@ pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, cons
         delete s;
         return fail("pinned staging allocation failed", PNDF_ENOMEM);
     }
-    pndf_eval_opts eo{PNDF_KERNEL_GAUSSIAN, o.tau, o.sigma_to_r > 0.f ? o.sigma_to_r : 3.f,
+    pndf_eval_opts eo{o.kernel, o.tau, o.sigma_to_r > 0.f ? o.sigma_to_r : 3.f,
                       PNDF_ALGO_PERSISTENT, 0};
     s->slots.resize((size_t)o.slots);
     pndf_status st = PNDF_OK;

@@ -41,9 +41,9 @@ def gpu_build(P, nrm, cluster=True):
     return mesh, hier
 
 
-def gpu_hits(P, hier, q, tau=0.0, algo="auto"):
+def gpu_hits(P, hier, q, tau=0.0, algo="auto", kernel="gaussian", sigma_to_r=3.0):
     import torch
-    d, off, ids, terms = P.eval_hits(hier, to_dev(q), tau=tau, algo=algo)
+    d, off, ids, terms = P.eval_hits(hier, to_dev(q), tau=tau, algo=algo, kernel=kernel, sigma_to_r=sigma_to_r)
     torch.cuda.synchronize()
     return d.cpu().numpy(), off.cpu().numpy(), ids.cpu().numpy().view(np.uint64), terms.cpu().numpy()
 
@@ -295,7 +295,7 @@ def test_options_and_errors(P):
     with pytest.raises(P.PndfError):
         P.eval_batch(hier, q, sigma_to_r=0.0)
     with pytest.raises(P.PndfError):
-        P.eval_batch(hier, q, kernel=1)
+        P.eval_batch(hier, q, kernel=3)
     _, hier2 = gpu_build(P, nrm, cluster=True)
     with pytest.raises(P.PndfError):
         P.eval_batch(hier2, q, tau=1e-3, algo="brute")
@@ -431,3 +431,55 @@ def test_full_size_cut_configs_sampled(P, oracle_mod, name):
         assert plan.stats()["error"] == 0
         assert torch.equal(got.view(torch.int32), torch.from_numpy(d[: 1 << 18]).cuda().view(torch.int32))
         plan.close()
+
+
+# ------------------------------------------------------- footprint kernels
+@pytest.mark.parametrize("tau", [0.0, 1e-3])
+@pytest.mark.parametrize("kernel", ["disk", "box"])
+@pytest.mark.parametrize("name", ["bumps64", "powerlaw128", "scratched128"])
+def test_footprint_kernels(P, oracle_mod, name, kernel, tau):
+    """Disk and box footprints (support half-axes 1.5 sigma, normalised over
+    the support, truncated where the triangle is hit): plain against the
+    oracle, and brute (tau = 0) and the persistent kernel bit-identical to
+    plain."""
+    import torch
+    announce("eval %s kernel tau=%g %s" % (kernel, tau, name))
+    nrm = MAPS[name]()
+    n = nrm.shape[0]
+    clusters = oracle_mod.cluster_all(nrm) if tau > 0 else None
+    q = mixed_queries(n, 1201, 31, 0.05, 0.5 * n, normal_radius(nrm))
+    _, hier = gpu_build(P, nrm, cluster=tau > 0)
+    d, off, ids, terms = gpu_hits(P, hier, q, tau=tau, algo="plain", kernel=kernel, sigma_to_r=1.5)
+    ref = oracle_mod.evaluate(nrm, q, tau=tau, clusters=clusters, records=True, kernel=kernel,
+                              sigma_to_r=1.5)
+    st = compare(ref, d, off, ids)
+    print(st)
+    assert st["nonzero"] > 50
+    assert st["cut_ambiguous"] <= 20
+    qd = to_dev(q)
+    plain = P.eval_batch(hier, qd, tau=tau, algo="plain", kernel=kernel, sigma_to_r=1.5).cpu().numpy()
+    np.testing.assert_array_equal(plain.view(np.uint32), d.view(np.uint32))
+    if tau == 0:
+        brute = P.eval_batch(hier, qd, algo="brute", kernel=kernel, sigma_to_r=1.5).cpu().numpy()
+        np.testing.assert_array_equal(brute.view(np.uint32), d.view(np.uint32))
+    plan = P.Plan(hier, len(q), tau=tau, sigma_to_r=1.5, kernel=kernel)
+    pers = plan.eval(qd).cpu().numpy()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pers.view(np.uint32), d.view(np.uint32))
+
+
+def test_footprint_kernels_differ_from_gaussian(P, oracle_mod):
+    """The three kernels weight the same hits differently: on a flat region the
+    box and disk values are their constant densities."""
+    announce("eval kernel comparison on a flat map")
+    nrm = np.zeros((16, 16, 2), dtype=np.float32)
+    nrm[..., 0] = 0.125
+    nrm[..., 1] = -0.0625
+    _, hier = gpu_build(P, nrm, cluster=False)
+    q = np.array([[8.0, 8.0, 2.0, 3.0, 0.125, -0.0625]], dtype=np.float32)
+    out = {}
+    for k in ("gaussian", "disk", "box"):
+        out[k] = float(P.eval_batch(hier, to_dev(q), kernel=k, sigma_to_r=1.5).cpu().numpy()[0])
+        ref = oracle_mod.evaluate(nrm, q, kernel=k, sigma_to_r=1.5)["D"][0]
+        assert abs(out[k] - ref) <= 1e-4 * ref, (k, out[k], ref)
+    assert len({round(v, 3) for v in out.values()}) == 3

@@ -114,3 +114,20 @@ def test_submit_validation(maps):
     srv.close()
     with pytest.raises(P.PndfError):
         P.Server([h for _, h in maps], slots=1, max_batch_queries=256, algo="brute")
+    with pytest.raises(P.PndfError):
+        P.Server([h for _, h in maps], slots=1, max_batch_queries=256, kernel=7)
+
+
+@pytest.mark.parametrize("algo", ["plain", "persistent"])
+def test_served_box_kernel_equals_alone(maps, algo):
+    import torch
+    import paper_2505_08985_amd as P
+    announce("serving: box footprints, %s batches" % algo)
+    mids, qs = tiles(maps, 16, 17, tile=8)
+    srv = P.Server([h for _, h in maps], slots=2, max_batch_queries=2048, max_pending=64, algo=algo,
+                   kernel="box", sigma_to_r=1.5)
+    outs, lat = srv.replay(mids, np.zeros(len(qs)), qs)
+    for m, q, o in zip(mids, qs, outs):
+        alone = P.eval_batch(maps[m][1], torch.from_numpy(q).cuda(), kernel="box", sigma_to_r=1.5).cpu().numpy()
+        np.testing.assert_array_equal(o.view(np.uint32), alone.view(np.uint32))
+    srv.close()
