@@ -220,6 +220,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-octaves", action="store_true")
     ap.add_argument("--input-order", action="store_true", help="keep the query order (no spatial ordering)")
+    ap.add_argument("--tuning", default=None, metavar="BPC,SPLIT",
+                    help="persistent tuning (blocks per CU, split level) instead of autotuning")
+    ap.add_argument("--autotune-queries", type=int, default=1 << 14,
+                    help="size of the autotuning sample (a prefix of the batch)")
     ap.add_argument("--kernel", default="gaussian", choices=["gaussian", "disk", "box"],
                     help="footprint kernel")
     ap.add_argument("--sigma-to-r", type=float, default=None,
@@ -286,12 +290,17 @@ def main():
 
     tuning = None
     if args.algo == "persistent":
-        sample = tq[:min(count, 1 << 14)]
-        print("[bench] autotuning on %d queries ..." % sample.shape[0], file=sys.stderr, flush=True)
-        tuning, tms = P.autotune(hier, sample, tau=tau, **kw)
-        print("[bench] autotuned %s (%.3f ms on %d queries)" % (tuning, tms, sample.shape[0]),
-              file=sys.stderr, flush=True)
+        if args.tuning:
+            bpc, split = (int(v) for v in args.tuning.split(","))
+            tuning = dict(blocks_per_cu=bpc, split_level=split, queue_factor=16, use_graph=1)
+        else:
+            sample = tq[:min(count, args.autotune_queries)]
+            print("[bench] autotuning on %d queries ..." % sample.shape[0], file=sys.stderr, flush=True)
+            tuning, tms = P.autotune(hier, sample, tau=tau, **kw)
+            print("[bench] autotuned %s (%.3f ms on %d queries)" % (tuning, tms, sample.shape[0]),
+                  file=sys.stderr, flush=True)
         plan = P.Plan(hier, count, tau=tau, tuning=tuning, **kw)
+        print("[bench] plan tuning %s" % plan.tuning(), file=sys.stderr, flush=True)
 
         def step():
             plan.eval(tq, out=out)

@@ -205,7 +205,8 @@ const char* pndf_last_error(void);
 typedef struct pndf_plan pndf_plan;
 
 typedef struct pndf_tuning {
-    int32_t blocks_per_cu; /* worker blocks per compute unit (>= 1) */
+    int32_t blocks_per_cu; /* worker blocks per compute unit (>= 1; more than fit on a compute
+                            * unit at once, given the kernel's registers and LDS, run as that many) */
     int32_t split_level;   /* smallest level whose nodes may be donated, 1..log2 N */
     int32_t queue_factor;  /* task-queue slots per query of max_nq (>= 1); a donation that does not
                             * fit stays with its wave, so capacity only affects balance */
@@ -240,6 +241,9 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
 pndf_status pndf_plan_eval(pndf_plan* plan, const pndf_query* d_q, int64_t nq, float* d_out,
                            void* stream);
 
+/* The tuning the plan runs with (blocks_per_cu after the resident limit). */
+pndf_status pndf_plan_get_tuning(const pndf_plan* plan, pndf_tuning* out);
+
 /* Statistics of the plan's last run (synchronises `stream`). */
 pndf_status pndf_plan_get_stats(pndf_plan* plan, pndf_plan_stats* out, void* stream);
 
@@ -248,9 +252,11 @@ void pndf_plan_destroy(pndf_plan* plan);
 /*
  * Autotuner: time the persistent traversal on the given queries (a representative
  * sample of the workload) for every candidate tuning (blocks per compute unit in
- * {1, 2, 4, 6, 8}, split level 2..8 within the map's levels, graph replay; best of two
- * timed runs after a warm-up) and return the fastest in *best, with its time per
- * batch in *best_ms (may be NULL).  Synchronises `stream`.
+ * {1, 2, 4, 6, 8} up to the resident limit, split level 2..8 within the map's levels,
+ * graph replay; best of two timed runs after a warm-up) and return the fastest in
+ * *best, with its time per batch in *best_ms (may be NULL).  The sample should load
+ * the GPU like the batches the plan will run: on a much smaller batch the slowest
+ * queries dominate and favour fewer workers.  Synchronises `stream`.
  */
 pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
                           const pndf_eval_opts* opts, pndf_tuning* best, double* best_ms,

@@ -54,9 +54,12 @@ def load():
                               _dp, _i64p, _i64p, _i32p,
                               _i64p, _u64p, _dp, _i64p, _u64p, _dp, _u8p]
     lib.or_sample_normals.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, ctypes.c_int64, _dp]
+    lib.or_sample_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, _fp, _fp, _dp, ctypes.c_int64,
+                                ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_int,
+                                _dp, _dp, _u64p, _i32p]
     lib.or_num_threads.argtypes = []
     for f in (lib.or_mesh, lib.or_cluster_nodes, lib.or_fine_contrib, lib.or_eval, lib.or_eval_k,
-              lib.or_sample_normals, lib.or_num_threads):
+              lib.or_sample_normals, lib.or_sample_k, lib.or_num_threads):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -202,6 +205,36 @@ def sample_normals(nrm, u, eps=1e-6):
     if rc:
         raise ValueError("or_sample_normals failed")
     return out
+
+
+def sample(nrm, queries, xi, tau=0.0, eps=1e-6, sigma_to_r=3.0, kernel="gaussian", clusters=None,
+           band=1e-8):
+    """Draw one sample of the P-NDF per query (Q, 6) float32 (x, y, sx, sy used)
+    from the uniforms xi (Q, 2 * attempts) float64 in [0, 1).  Returns dict u (Q, 2)
+    unrolled texture coordinates, m (Q, 2) sampled normals, tri (Q,) triangle ids,
+    flags (Q,): bit0 a cut decision within 1e-5 of the threshold, bit1 u within
+    `band` of a unit edge / diagonal, bit2 every attempt rejected."""
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    nrm = _map(nrm)
+    q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, 6)
+    nq = q.shape[0]
+    xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(nq, -1)
+    attempts = xi.shape[1] // 2
+    assert xi.shape[1] == 2 * attempts and attempts >= 1
+    if tau > 0 and clusters is None:
+        clusters = cluster_all(nrm, eps)
+    cn = clusters["clu_n"] if clusters is not None else None
+    ce = clusters["clu_e"] if clusters is not None else None
+    u = np.empty((nq, 2))
+    m = np.empty((nq, 2))
+    tri = np.empty(nq, dtype=np.uint64)
+    flags = np.empty(nq, dtype=np.int32)
+    rc = load().or_sample_k(nrm.shape[0], _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp),
+                            _p(xi, _dp), nq, attempts, tau, sigma_to_r, band, kid,
+                            _p(u, _dp), _p(m, _dp), _p(tri, _u64p), _p(flags, _i32p))
+    if rc:
+        raise ValueError("or_sample_k failed (%d)" % rc)
+    return dict(u=u, m=m, tri=tri, flags=flags)
 
 
 def triangle_id(level, I, J, half):

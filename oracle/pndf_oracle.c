@@ -32,11 +32,18 @@
  *   - cut: starting at the entry level ceil(log2 max(r)) (supplement, "Entry
  *     level"), descend until a node satisfies e^l <= r_x r_y tau (section
  *     "Acceleration by mesh clustering").
+ *   - sampling: u from the footprint kernel over the support the evaluation
+ *     integrates, m the normal of the triangle (or, with the cut, the cluster
+ *     triangle) containing u, warped onto the replacement triangle when clamped
+ *     (section "Sampling and evaluation", Eq. debias, and the remark on sampling
+ *     n^l in "Acceleration by mesh clustering").
  *
  * Status of the pins: every function here is pinned by the CPU tests (flat map,
  * tilted triangle pair, linear field, mass invariant, Monte Carlo normal
  * histogram, the supplement's printed coefficient matrices, transpose
- * invariance) except the orientation of the equilateral replacement triangle,
+ * invariance; for sampling: scipy's normal quantile, the interpolated field,
+ * uniformity of disk and box draws, the linear field through clusters, the
+ * support kept by rejection, and histograms of samples against D) except the orientation of the equilateral replacement triangle,
  * which the paper leaves free ("any other shape"): parity unpinned, fixed by
  * convention (vertices at 90, 210, 330 degrees in (a, b, c) order).
  */
@@ -751,6 +758,210 @@ int or_sample_normals(int n, const float* nrm, float eps, const double* u, int64
         }
         mout[2 * k] = w[0] * nv[0][0] + w[1] * nv[1][0] + w[2] * nv[2][0];
         mout[2 * k + 1] = w[0] * nv[0][1] + w[1] * nv[1][1] + w[2] * nv[2][1];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- sampling -- */
+/*
+ * Sampling of the P-NDF (section "Sampling and evaluation", Eq. debias; with the
+ * cut, section "Acceleration by mesh clustering": sampling uses the same normal
+ * field n^l as the evaluation).  u is drawn from the footprint kernel over the
+ * same support the evaluation integrates, then m is the normal of the triangle
+ * containing u: n(u) by barycentric interpolation, or the same barycentric point
+ * of the equilateral replacement for a clamped triangle.  The density of m is
+ * then D(m) divided by D's total mass.
+ *
+ * Support (the evaluation's, R2 and R10): at tau = 0, the included cells
+ * [cxlo, cxhi + 1] per axis; with the cut, the units of the cut (cells or
+ * cluster nodes) whose unrolled image meets the included cells.  The Gaussian is
+ * drawn by inverse CDF on a per-axis range S (the included cells at tau = 0; the
+ * entry-level nodes over them with the cut) and, with the cut, rejected when its
+ * unit does not meet the included cells (the next uniform pair is then used).
+ * Disk and box supports lie inside the included cells, so their draws are
+ * direct: uniform on the ellipse (radius sqrt(xi0), angle 2 pi xi1) or rectangle.
+ */
+
+/* standard normal CDF */
+static double std_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+/* its inverse, by bisection on the monotone CDF (slow, plain) */
+static double std_cdf_inv(double p)
+{
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 400; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 1e-15 * (fabs(mid) > 1.0 ? fabs(mid) : 1.0)) break;
+        if (std_cdf(mid) < p) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* u on [a, b) from the Gaussian N(x, sig^2) truncated to [a, b), by inverse CDF */
+static double trunc_gauss(double x, double sig, double a, double b, double xi)
+{
+    double pa = std_cdf((a - x) / sig), pb = std_cdf((b - x) / sig);
+    double u = x + sig * std_cdf_inv(pa + xi * (pb - pa));
+    if (u < a) u = a;
+    if (u >= b) u = nextafter(b, a);
+    return u;
+}
+
+/* the unit of the cut that contains u: level (0 = a cell) and its torus node;
+ * flag bit0 when a decision on the way is within 1e-5 relative of t */
+static int cut_unit(const map_t* m, const query_t* q, const double u[2], long* I, long* J, int* flag)
+{
+    if (q->use_cut)
+        for (int l = q->l0; l >= 1; l--) {
+            long s = 1L << l, mm = m->n >> l;
+            long Il = wrap((long)floor(u[0] / (double)s), mm), Jl = wrap((long)floor(u[1] / (double)s), mm);
+            float e = m->clu_e[level_offset(m->n, l) + Jl * mm + Il];
+            if (fabs((double)e - (double)q->t) <= 1e-5 * fabs((double)q->t)) *flag |= 1;
+            if (e <= q->t) { *I = Il; *J = Jl; return l; }
+        }
+    *I = wrap((long)floor(u[0]), m->n);
+    *J = wrap((long)floor(u[1]), m->n);
+    return 0;
+}
+
+/* does the unrolled image of the level-l unit holding coordinate c meet [clo, chi]
+ * (cells) */
+static int unit_meets(double c, int l, long clo, long chi)
+{
+    long s = 1L << l;
+    long start = (long)floor(c / (double)s) * s;
+    return start <= chi && start + s - 1 >= clo;
+}
+
+/* m at u inside unit (level, I, J): the two triangles of the cell (level 0, the
+ * map's normals, Eq. interpolation) or of the cluster node (normals N0..N3);
+ * clamped triangles are replaced as in the evaluation.  Returns the half; flag
+ * bit1 when u lies within `band` (unit-local) of the unit's edges or diagonal. */
+static int unit_normal(const map_t* m, int level, long I, long J, const double u[2], double band, double mo[2],
+                       int* flag)
+{
+    const double s = (double)(1L << level);
+    double U = (u[0] - floor(u[0] / s) * s) / s, V = (u[1] - floor(u[1] / s) * s) / s;
+    double dmin = U;
+    if (1.0 - U < dmin) dmin = 1.0 - U;
+    if (V < dmin) dmin = V;
+    if (1.0 - V < dmin) dmin = 1.0 - V;
+    if (fabs(U + V - 1.0) < dmin) dmin = fabs(U + V - 1.0);
+    if (dmin < band) *flag |= 2;
+    double N[4][2];
+    if (level == 0) {
+        texel(m->nrm, m->n, I, J, N[0]);
+        texel(m->nrm, m->n, I + 1, J, N[1]);
+        texel(m->nrm, m->n, I, J + 1, N[2]);
+        texel(m->nrm, m->n, I + 1, J + 1, N[3]);
+    } else {
+        const float* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * (m->n >> level) + I);
+        for (int k = 0; k < 4; k++) { N[k][0] = cn[2 * k]; N[k][1] = cn[2 * k + 1]; }
+    }
+    int half = U + V < 1.0 ? 0 : 1;
+    double nv[3][2], w[3];
+    if (half == 0) {
+        memcpy(nv[0], N[0], sizeof nv[0]); memcpy(nv[1], N[1], sizeof nv[0]); memcpy(nv[2], N[2], sizeof nv[0]);
+        w[0] = 1.0 - U - V; w[1] = U; w[2] = V;
+    } else {
+        memcpy(nv[0], N[3], sizeof nv[0]); memcpy(nv[1], N[2], sizeof nv[0]); memcpy(nv[2], N[1], sizeof nv[0]);
+        w[0] = U + V - 1.0; w[1] = 1.0 - U; w[2] = 1.0 - V;
+    }
+    /* the clamp of the evaluation (test_cell / test_cluster): Jacobian per unit uv area */
+    if (jac(nv[0], nv[1], nv[2]) / (s * s) < m->eps) {
+        double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
+        eqtri(centre, eq_rho(0.5 * m->eps * s * s), nv);
+    }
+    mo[0] = w[0] * nv[0][0] + w[1] * nv[1][0] + w[2] * nv[2][0];
+    mo[1] = w[0] * nv[0][1] + w[1] * nv[1][1] + w[2] * nv[2][1];
+    return half;
+}
+
+/*
+ * Draw nq samples (queries as for or_sample_k's evaluation: x, y, sx, sy used).
+ * xi: attempts pairs of uniforms in [0, 1) per query, row-major (nq x 2 attempts).
+ * Outputs: u (2 per query, unrolled texture coordinates), m (2 per query), tri
+ * (triangle id as in the evaluation's hit lists), flags: bit0 a cut decision on
+ * the way within 1e-5 relative of t; bit1 u within `band` of a unit edge or
+ * diagonal (the triangle may differ under rounding) or of the rejection
+ * boundary; bit2 every attempt was rejected (m = NaN).  Invalid queries or
+ * uniforms give NaN with tri = ~0.
+ */
+int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+                const float* queries, const double* xi, int64_t nq, int attempts, float tau, float s2r,
+                double band, int kernel, double* uout, double* mout, uint64_t* tri, int32_t* flags)
+{
+    if (kernel < 0 || kernel > 2) return 3;
+    if (attempts < 1) return 4;
+    map_t m;
+    m.n = n;
+    m.L = ilog2_exact(n);
+    if (m.L < 1) return 1;
+    m.nrm = nrm;
+    m.eps = (double)eps;
+    m.clu_n = clu_n;
+    m.clu_e = clu_e;
+    if (tau > 0.0f && (!clu_n || !clu_e)) return 2;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < nq; k++) {
+        query_t q;
+        int fl = 0;
+        double u[2] = {NAN, NAN}, mo[2] = {NAN, NAN};
+        uint64_t id = ~(uint64_t)0;
+        int bad = setup_query(&m, queries + 6 * k, tau, s2r, 0.0, kernel, &q);
+        for (int a = 0; !bad && a < attempts; a++) {
+            double x0 = xi[(2 * k) * attempts + 2 * a], x1 = xi[(2 * k) * attempts + 2 * a + 1];
+            if (!(x0 >= 0.0 && x0 < 1.0 && x1 >= 0.0 && x1 < 1.0)) { bad = 1; break; }
+        }
+        if (bad) {
+            uout[2 * k] = uout[2 * k + 1] = NAN;
+            mout[2 * k] = mout[2 * k + 1] = NAN;
+            tri[k] = ~(uint64_t)0;
+            flags[k] = 0;
+            continue;
+        }
+        int done = 0;
+        for (int a = 0; a < attempts && !done; a++) {
+            double x0 = xi[(2 * k) * attempts + 2 * a], x1 = xi[(2 * k) * attempts + 2 * a + 1];
+            if (kernel == 1) {
+                double rad = sqrt(x0), ang = 2.0 * OR_PI * x1;
+                u[0] = q.x + q.rx * rad * cos(ang);
+                u[1] = q.y + q.ry * rad * sin(ang);
+            } else if (kernel == 2) {
+                u[0] = q.x + q.rx * (2.0 * x0 - 1.0);
+                u[1] = q.y + q.ry * (2.0 * x1 - 1.0);
+            } else {
+                /* the per-axis range S: included cells, or the entry-level nodes over them */
+                int l = q.use_cut ? q.l0 : 0;
+                long sl = 1L << l;
+                double ax = (double)(floor_div(q.cxlo, sl) * sl), bx = (double)((floor_div(q.cxhi, sl) + 1) * sl);
+                double ay = (double)(floor_div(q.cylo, sl) * sl), by = (double)((floor_div(q.cyhi, sl) + 1) * sl);
+                u[0] = trunc_gauss(q.x, q.sx, ax, bx, x0);
+                u[1] = trunc_gauss(q.y, q.sy, ay, by, x1);
+            }
+            long I, J;
+            int ufl = 0;
+            int lev = cut_unit(&m, &q, u, &I, &J, &ufl);
+            /* (flags u near the unit's edges, which also decide the rejection) */
+            int half = unit_normal(&m, lev, I, J, u, band, mo, &ufl);
+            fl |= ufl;
+            if (kernel == 0 && q.use_cut &&
+                !(unit_meets(u[0], lev, q.cxlo, q.cxhi) && unit_meets(u[1], lev, q.cylo, q.cyhi)))
+                continue; /* rejected: the unit lies outside the support */
+            id = OR_ID(lev, I, J, half);
+            done = 1;
+        }
+        if (!done) {
+            fl |= 4;
+            mo[0] = mo[1] = NAN;
+            id = ~(uint64_t)0;
+        }
+        uout[2 * k] = u[0];
+        uout[2 * k + 1] = u[1];
+        mout[2 * k] = mo[0];
+        mout[2 * k + 1] = mo[1];
+        tri[k] = id;
+        flags[k] = fl;
     }
     return 0;
 }

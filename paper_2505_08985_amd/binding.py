@@ -73,6 +73,7 @@ _plan_create = _sig("pndf_plan_create", _i32, [_vp, _i64, ctypes.POINTER(EvalOpt
                                                ctypes.POINTER(_vp)])
 _plan_eval = _sig("pndf_plan_eval", _i32, [_vp, _vp, _i64, _vp, _vp])
 _plan_get_stats = _sig("pndf_plan_get_stats", _i32, [_vp, ctypes.POINTER(PlanStats), _vp])
+_plan_get_tuning = _sig("pndf_plan_get_tuning", _i32, [_vp, ctypes.POINTER(Tuning)])
 _plan_destroy = _sig("pndf_plan_destroy", None, [_vp])
 _autotune = _sig("pndf_autotune", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), ctypes.POINTER(Tuning),
                                          ctypes.POINTER(ctypes.c_double), _vp])
@@ -81,7 +82,7 @@ EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_
             "pndf_eval_hits", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
             "pndf_last_error", "pndf_mesh_info", "pndf_mesh_export", "pndf_hier_info",
             "pndf_hier_export_level", "pndf_default_tuning", "pndf_plan_create", "pndf_plan_eval",
-            "pndf_plan_get_stats", "pndf_plan_destroy", "pndf_autotune"]
+            "pndf_plan_get_stats", "pndf_plan_get_tuning", "pndf_plan_destroy", "pndf_autotune"]
 
 
 class PndfError(RuntimeError):
@@ -302,6 +303,11 @@ class Plan:
         _check(_plan_eval(self._h, qp, nq, _dev_ptr(out, torch.float32, "out"), _stream(stream)),
                "pndf_plan_eval")
         return out
+
+    def tuning(self):
+        t = Tuning()
+        _check(_plan_get_tuning(self._h, ctypes.byref(t)), "pndf_plan_get_tuning")
+        return t.as_dict()
 
     def stats(self, stream=None):
         st = PlanStats()

@@ -700,11 +700,12 @@ __device__ __forceinline__ bool all_taken(QueueCtl* ctl, long long nq)
     return true;
 }
 
-// A unit of work (a query chunk, a task, or a failed attempt at a chunk) is over.
-// The decrement that leaves nothing outstanding after every query was taken ends
-// the run: it raises the done flags the waiting workers poll.  (Units only start
-// while queries remain or from inside a running unit, so the count cannot leave
-// zero for real work once every query is taken.)
+// A unit of work is over: a worker's whole query phase (counted when the worker
+// starts, ended when it finds no query left), or a donated task (counted by its
+// donor before it is published).  The decrement that leaves nothing outstanding
+// after every query was taken ends the run: it raises the done flags the waiting
+// workers poll.  (A worker that starts late counts itself before looking for
+// queries and finds none, so the count cannot leave zero while work remains.)
 __device__ __forceinline__ void unit_done(QueueCtl* ctl, long long nq)
 {
     const unsigned long long old = __hip_atomic_fetch_add(&ctl->outstanding, (unsigned long long)-1ll,
@@ -744,30 +745,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     long long qb = 0, qe = 0;  // the wave's current chunk of query slots
     long long ticket = -1;     // the wave's place in the task queue while it waits for a task
     int polls = 0;
+    bool querying = true;      // in the query phase (counted as one outstanding unit)
+    if (lane == 0) add_relaxed(&ctl->outstanding, 1);
     while (true) {
         long long task_slot = -1;
         if (qb >= qe) {
             long long nb = -1, ne = -1;
             if (lane == 0) {
                 if (ticket < 0) {
-                    // a chunk of queries, counted as outstanding before it is taken: from
-                    // this XCD's share of the processing order first (neighbouring queries,
-                    // so the XCD's L2 holds their nodes), then from the other shares
-                    for (int k = 0; nb < 0 && k < kXcds; ++k) {
+                    // a chunk of queries: from this XCD's share of the processing order
+                    // first (neighbouring queries, so the XCD's L2 holds their nodes), then
+                    // from the other shares (one atomic per chunk, on the share's own line)
+                    for (int k = 0; querying && nb < 0 && k < kXcds; ++k) {
                         const int x = (home + k) & (kXcds - 1);
                         const long long lo = nq * x / kXcds, len = nq * (x + 1) / kXcds - lo;
                         const long long qh = (long long)ld_relaxed(&ctl->qhead[x].v);
                         if (qh >= len) continue;
                         const long long c = max(1ll, min((long long)kMaxChunk, (len - qh) / (64 * xworkers)));
-                        add_relaxed(&ctl->outstanding, 1);
                         const long long qn = (long long)__hip_atomic_fetch_add(
                             &ctl->qhead[x].v, (unsigned long long)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (qn < len) {
                             nb = lo + qn;
                             ne = lo + min(qn + c, len);
-                        } else {
-                            unit_done(ctl, nq);
                         }
+                    }
+                    if (nb < 0 && querying) {
+                        // every query is taken: the query phase is over
+                        querying = false;
+                        unit_done(ctl, nq);
                     }
                     if (nb < 0) {
                         // no query left: take a ticket (the next task slot in order) and tell
@@ -891,9 +896,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                     pa.acc[qi] = d;                  // the only contribution
             }
         }
-        if (task_slot >= 0 || qb >= qe) {
-            // the task, or the last query of the chunk, is finished.  No fence: the count
-            // only decides when workers stop; the sums are read after the kernel ends.
+        if (task_slot >= 0) {
+            // the task is finished.  No fence: the count only decides when workers stop;
+            // the sums are read after the kernel ends.
             if (lane == 0) unit_done(ctl, nq);
         }
     }
@@ -1116,6 +1121,16 @@ static void* persist_func(const PersistPlan& P)
     if (P.kernel == PNDF_KERNEL_DISK)
         return cut ? (void*)k_persist<true, PNDF_KERNEL_DISK> : (void*)k_persist<false, PNDF_KERNEL_DISK>;
     return cut ? (void*)k_persist<true, PNDF_KERNEL_GAUSSIAN> : (void*)k_persist<false, PNDF_KERNEL_GAUSSIAN>;
+}
+
+// Worker blocks of the plan's kernel that fit on one compute unit at once
+// (registers and LDS), 0 if the runtime cannot tell.
+int persist_resident_blocks(const HierDev& H, const PersistPlan& P)
+{
+    int nb = 0;
+    const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(H.L);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_func(P), 256, lds) != hipSuccess) return 0;
+    return nb;
 }
 
 static unsigned order_grid(long long nq)

@@ -102,7 +102,6 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     PersistPlan& P = p->P;
     P.max_nq = max_nq;
     P.capacity = (unsigned long long)max_nq * (unsigned long long)t.queue_factor;
-    P.blocks = compute_units() * t.blocks_per_cu;
     P.split_level = t.split_level;
     // no single piece of undonatable work takes this long; a worker that waits
     // longer reports an error instead of hanging
@@ -110,6 +109,11 @@ pndf_status pndf_plan_create(const pndf_hier* h, int64_t max_nq, const pndf_eval
     P.tau = o.tau;
     P.s2r = o.sigma_to_r;
     P.kernel = o.kernel;
+    // blocks beyond what one compute unit holds at once would only start when
+    // resident workers exit, i.e. at the end of the run: use the resident count
+    const int resident = persist_resident_blocks(h->dev, P);
+    if (resident > 0 && t.blocks_per_cu > resident) p->tuning.blocks_per_cu = resident;
+    P.blocks = compute_units() * p->tuning.blocks_per_cu;
     hipError_t e = hipMalloc(&P.ctl, sizeof(QueueCtl));
     if (e == hipSuccess) e = hipMalloc(&P.acc, sizeof(Fix192) * (size_t)max_nq);
     if (e == hipSuccess) e = hipMalloc(&P.fexp, sizeof(int) * (size_t)max_nq);
@@ -150,6 +154,13 @@ pndf_status pndf_plan_eval(pndf_plan* plan, const pndf_query* d_q, int64_t nq, f
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_plan_eval");
 }
 
+pndf_status pndf_plan_get_tuning(const pndf_plan* plan, pndf_tuning* out)
+{
+    if (!plan || !out) return plan_invalid("NULL argument");
+    *out = plan->tuning;
+    return PNDF_OK;
+}
+
 pndf_status pndf_plan_get_stats(pndf_plan* plan, pndf_plan_stats* out, void* stream)
 {
     if (!plan || !out) return plan_invalid("NULL argument");
@@ -185,6 +196,7 @@ pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
     pndf_status st = PNDF_OK;
     const int lo = std::min(2, h->L), hi = std::min(8, h->L);
     static const int kBpc[] = {1, 2, 4, 6, 8};
+    int tried_bpc = 0;  // largest effective blocks per compute unit timed so far
     for (int bpc : kBpc) {
         if (st != PNDF_OK) break;
         for (int sl = lo; sl <= hi && st == PNDF_OK; ++sl) {
@@ -192,6 +204,13 @@ pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
             pndf_plan* p = nullptr;
             st = pndf_plan_create(h, nq, opts, &t, stream, &p);
             if (st != PNDF_OK) break;
+            // a count beyond what is resident runs as the resident count: timed already
+            t = p->tuning;
+            if (sl == lo && t.blocks_per_cu <= tried_bpc) {
+                pndf_plan_destroy(p);
+                break;
+            }
+            tried_bpc = std::max(tried_bpc, t.blocks_per_cu);
             st = pndf_plan_eval(p, d_q, nq, d_out, stream);  // warm-up
             float ms_best = 1e30f;
             for (int r = 0; r < 2 && st == PNDF_OK; ++r) {

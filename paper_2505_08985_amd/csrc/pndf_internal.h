@@ -163,6 +163,9 @@ struct PersistPlan {
 
 // Fill the device arguments of a plan whose buffers are allocated.
 void persist_prepare(const HierDev& H, PersistPlan& P);
+// Worker blocks of the plan's kernel (cut setting and footprint kernel) resident per
+// compute unit at once; 0 if unknown.
+int persist_resident_blocks(const HierDev& H, const PersistPlan& P);
 // persist_prepare, then build and instantiate the launch graph.
 hipError_t persist_graph_build(const HierDev& H, PersistPlan& P);
 hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float* out, bool use_graph,

@@ -662,3 +662,196 @@ def test_disk_box_mass_is_one(oracle_mod, kernel, n, x, y, s):
     qs[:, 4], qs[:, 5] = mx.ravel(), my.ravel()
     D = oracle_mod.evaluate(nrm, qs, sigma_to_r=1.5, kernel=kernel)["D"]
     assert D.sum() * (1.2 / k) ** 2 == pytest.approx(1.0, rel=1e-2)
+
+
+# ------------------------------------------------------ sampling of the P-NDF
+def uniforms(nq, attempts, seed):
+    return np.random.default_rng(seed).uniform(size=(nq, 2 * attempts))
+
+
+def test_sample_gaussian_inverse_cdf(oracle_mod):
+    """Sampling and evaluation: u ~ k restricted to the cells the evaluation
+    includes, per axis u = x + s Phi^-1(Phi(a) + xi (Phi(b) - Phi(a))) on the
+    included range [a, b), checked against scipy's normal CDF and quantile."""
+    from scipy.special import ndtr, ndtri
+    nrm = random_disk_map(16, 4)
+    rng = np.random.default_rng(5)
+    nq = 3000
+    q = np.zeros((nq, 6), np.float32)
+    q[:, 0:2] = rng.uniform(-20, 40, (nq, 2))
+    q[:, 2:4] = np.exp(rng.uniform(np.log(0.2), np.log(30), (nq, 2)))
+    xi = uniforms(nq, 1, 6)
+    r = oracle_mod.sample(nrm, q, xi)
+    assert not np.isnan(r["m"]).any() and (r["flags"] & 4 == 0).all()
+    for ax in (0, 1):
+        rng_ = [cell_range(q[k, ax], q[k, 2 + ax]) for k in range(nq)]
+        a = np.array([c[0] for c in rng_], float)
+        b = np.array([c[1] + 1 for c in rng_], float)
+        x = q[:, ax].astype(float)
+        s = q[:, 2 + ax].astype(float)
+        pa, pb = ndtr((a - x) / s), ndtr((b - x) / s)
+        want = x + s * ndtri(pa + xi[:, ax] * (pb - pa))
+        np.testing.assert_allclose(r["u"][:, ax], want, rtol=0, atol=1e-9 * max(1.0, float(np.abs(want).max())))
+        assert ((r["u"][:, ax] >= a) & (r["u"][:, ax] < b)).all()
+
+
+def test_sample_normal_is_the_field(oracle_mod):
+    """Without the cut, m = n(u) of Eq. (interpolation) (written out independently
+    here), and the triangle is the one containing u: cell floor(u) on the torus,
+    upper half when the in-cell coordinates sum to 1 or more."""
+    n = 16
+    nrm = random_disk_map(n, 9)
+    det, deg = oracle_mod.mesh(nrm)
+    assert not deg.any()
+    rng = np.random.default_rng(10)
+    nq = 4000
+    q = np.zeros((nq, 6), np.float32)
+    q[:, 0:2] = rng.uniform(-30, 50, (nq, 2))
+    q[:, 2:4] = np.exp(rng.uniform(np.log(0.1), np.log(12), (nq, 2)))
+    r = oracle_mod.sample(nrm, q, uniforms(nq, 1, 11))
+    np.testing.assert_allclose(r["m"], interp_normals(nrm, r["u"]), rtol=0, atol=1e-12)
+    lev, I, J, half = oracle_mod.decode_id(r["tri"])
+    fl = np.floor(r["u"])
+    assert (lev == 0).all()
+    assert (I == np.mod(fl[:, 0], n)).all() and (J == np.mod(fl[:, 1], n)).all()
+    frac = (r["u"] - fl).sum(axis=1)
+    ok = np.abs(frac - 1) > 1e-9
+    assert (half[ok] == (frac[ok] >= 1)).all()
+
+
+@pytest.mark.parametrize("kernel", ["disk", "box"])
+def test_sample_disk_box_uniform_on_support(oracle_mod, kernel):
+    """Disk and box footprints are uniform densities on their support (the ellipse
+    or rectangle of half-axes r = 1.5 sigma): samples stay inside it and their
+    coordinates follow the uniform law (Kolmogorov-Smirnov)."""
+    from scipy.stats import kstest
+    nrm = random_disk_map(16, 4)
+    nq = 20000
+    x, y, sx, sy = 5.3, 7.1, 2.0, 3.0
+    q = np.tile(np.array([[x, y, sx, sy, 0, 0]], np.float32), (nq, 1))
+    r = oracle_mod.sample(nrm, q, uniforms(nq, 1, 12), sigma_to_r=1.5, kernel=kernel)
+    rx, ry = float(np.float32(1.5) * np.float32(sx)), float(np.float32(1.5) * np.float32(sy))
+    dx = (r["u"][:, 0] - np.float32(x)) / rx
+    dy = (r["u"][:, 1] - np.float32(y)) / ry
+    if kernel == "box":
+        assert (np.abs(dx) <= 1 + 1e-12).all() and (np.abs(dy) <= 1 + 1e-12).all()
+        assert kstest((dx + 1) / 2, "uniform").pvalue > 1e-3
+        assert kstest((dy + 1) / 2, "uniform").pvalue > 1e-3
+    else:
+        rho2 = dx * dx + dy * dy
+        assert (rho2 <= 1 + 1e-12).all()
+        assert kstest(rho2, "uniform").pvalue > 1e-3          # area fraction inside radius
+        assert kstest((np.arctan2(dy, dx) / (2 * np.pi)) % 1.0, "uniform").pvalue > 1e-3
+
+
+def test_sample_linear_field_with_clusters(oracle_mod):
+    """With the cut, sampling reads the cluster field n^l (section "Acceleration by
+    mesh clustering").  For a linear field every cluster is exact, so the sample
+    is still n(u) = n_c + G (u - u_c), now taken from cluster triangles."""
+    nrm, G, nc, uc = linear_map()
+    rng = np.random.default_rng(13)
+    nq = 3000
+    q = np.zeros((nq, 6), np.float32)
+    q[:, 0:2] = rng.uniform(28, 36, (nq, 2))
+    q[:, 2:4] = rng.uniform(1.0, 3.0, (nq, 2))
+    r = oracle_mod.sample(nrm, q, uniforms(nq, 4, 14), tau=1e-3)
+    ok = r["flags"] == 0
+    assert ok.mean() > 0.95
+    lev, I, J, half = oracle_mod.decode_id(r["tri"][ok])
+    assert (lev >= 1).mean() > 0.9
+    want = nc + (r["u"] - uc) @ G.T
+    np.testing.assert_allclose(r["m"][ok], want[ok], rtol=0, atol=1e-9)
+
+
+def clamped_disk_map(n, seed):
+    """Random normals with a 3 x 3 block of equal texels: its 2 x 2 cells have
+    zero-area normal triangles and take the equilateral replacement."""
+    nrm = random_disk_map(n, seed, radius=0.45)
+    nrm[2:5, 2:5] = np.float32([0.1, -0.05])
+    return nrm
+
+
+@pytest.mark.parametrize("kernel,tau", [("gaussian", 0.0), ("gaussian", 1e-2), ("disk", 0.0),
+                                        ("box", 1e-2)])
+def test_sample_histogram_matches_ndf(oracle_mod, kernel, tau):
+    """Sampling is consistent with evaluation (Eq. debias; with the cut, sampling
+    reads n^l): the histogram of sampled normals matches the integral of D over
+    each bin divided by D's total, including clamped triangles (eps = 1e-2 here,
+    so that their replacement triangles span several grid steps) and cluster
+    triangles of the cut.  Disk and box densities jump at the support's edge, so
+    their bin integrals take a finer grid and only bins holding 0.5 % of the mass
+    or more are compared (the midpoint rule's error at a jump is first order)."""
+    n = 8
+    eps = float(np.float32(1e-2))
+    nrm = clamped_disk_map(n, 5)
+    det, deg = oracle_mod.mesh(nrm, eps=eps)
+    assert deg.any()
+    s2r = 3.0 if kernel == "gaussian" else 1.5
+    x, y, s = np.float32(4.1), np.float32(3.7), np.float32(0.9 if kernel == "gaussian" else 1.8)
+    clusters = oracle_mod.cluster_all(nrm, eps) if tau > 0 else None
+    ns = 1_000_000
+    q = np.tile(np.array([[x, y, s, s, 0, 0]], np.float32), (ns, 1))
+    r = oracle_mod.sample(nrm, q, uniforms(ns, 4, 15), tau=tau, eps=eps, sigma_to_r=s2r, kernel=kernel,
+                          clusters=clusters)
+    good = ~np.isnan(r["m"][:, 0])
+    assert good.mean() > 0.999
+    if tau > 0:
+        lev, _, _, _ = oracle_mod.decode_id(r["tri"][good])
+        assert (lev >= 1).mean() > 0.1
+    nb = 12
+    edges = np.linspace(-0.54, 0.54, nb + 1)
+    hist, _, _ = np.histogram2d(r["m"][good, 0], r["m"][good, 1], bins=[edges, edges])
+    freq = hist / good.sum()
+    sub = 24 if kernel == "gaussian" else 48
+    w = edges[1] - edges[0]
+    cx = (edges[:-1, None] + (np.arange(sub)[None, :] + 0.5) * w / sub).ravel()
+    mx, my = np.meshgrid(cx, cx, indexing="ij")
+    qs = np.zeros((mx.size, 6), dtype=np.float32)
+    qs[:, 0], qs[:, 1], qs[:, 2], qs[:, 3] = x, y, s, s
+    qs[:, 4], qs[:, 5] = mx.ravel(), my.ravel()
+    D = oracle_mod.evaluate(nrm, qs, tau=tau, eps=eps, sigma_to_r=s2r, kernel=kernel, clusters=clusters)["D"]
+    binint = D.reshape(nb, sub, nb, sub).sum(axis=(1, 3))
+    p = binint / binint.sum()
+    assert freq.sum() == pytest.approx(1.0, abs=2e-3)   # the grid covers the samples
+    big = p > (2e-3 if kernel == "gaussian" else 5e-3)
+    assert big.sum() >= 20
+    rel = np.abs(freq[big] - p[big]) / p[big]
+    assert np.median(rel) < 0.03
+    assert rel.max() < 0.15
+
+
+def test_sample_rejection_keeps_the_evaluated_support(oracle_mod):
+    """With the cut the evaluation integrates whole cut units (cells or cluster
+    nodes) that meet the included cells.  The Gaussian draw covers the entry-level
+    nodes around them and rejects units that do not meet the included cells: every
+    accepted sample's unit meets them (checked here from the triangle id), some
+    first draws are rejected, and a sample whose first draw is accepted does not
+    depend on the spare uniforms."""
+    n = 32
+    nrm = random_disk_map(n, 21)
+    rng = np.random.default_rng(22)
+    nq = 20000
+    q = np.zeros((nq, 6), np.float32)
+    q[:, 0:2] = rng.uniform(0, n, (nq, 2))
+    q[:, 2:4] = np.exp(rng.uniform(np.log(0.4), np.log(4.0), (nq, 2)))
+    clusters = oracle_mod.cluster_all(nrm)
+    xi = uniforms(nq, 4, 23)
+    r4 = oracle_mod.sample(nrm, q, xi, tau=3e-2, clusters=clusters)
+    r1 = oracle_mod.sample(nrm, q, xi[:, :2].copy(), tau=3e-2, clusters=clusters)
+    acc = ~np.isnan(r4["m"][:, 0])
+    assert acc.mean() > 0.999
+    lev, I, J, half = oracle_mod.decode_id(r4["tri"][acc])
+    assert (lev >= 1).mean() > 0.1
+    for ax, (Iax, xcol, scol) in enumerate(((I, 0, 2), (J, 1, 3))):
+        rngs = [cell_range(q[k, xcol], q[k, scol]) for k in np.where(acc)[0]]
+        clo = np.array([c[0] for c in rngs])
+        chi = np.array([c[1] for c in rngs])
+        side = 1 << lev
+        start = np.floor(r4["u"][acc, ax] / side).astype(np.int64) * side
+        assert ((start <= chi) & (start + side - 1 >= clo)).all()
+        assert (np.mod(start // side, n >> lev) == Iax).all()
+    rej = np.isnan(r1["m"][:, 0])
+    assert 0.001 < rej.mean() < 0.2 and (r1["flags"][rej] & 4).all()
+    same = ~rej
+    np.testing.assert_array_equal(r1["tri"][same], r4["tri"][same])
+    np.testing.assert_array_equal(r1["m"][same], r4["m"][same])
