@@ -209,6 +209,77 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def sample_bench(args):
+    """Sampling throughput: one P-NDF sample per query of the workload's query
+    stream (pndf_sample_batch), uniforms drawn on the device beforehand."""
+    import torch
+    import paper_2505_08985_amd as P
+    import workloads
+    cfg = workloads.CONFIGS[args.workload]
+    mc, qc = cfg["map"], cfg["queries"]
+    tau = args.sample_tau
+    n = mc["n"]
+    kern = args.kernel
+    s2r = args.sigma_to_r if args.sigma_to_r is not None else (3.0 if kern == "gaussian" else 1.5)
+    count = args.queries or (1 << 24)
+    nrm = workloads.make_map(**mc)
+    q = workloads.uniform_queries(n, count, qc["seed"], qc["sigma"], qc["radius"])
+    print("[bench] sampling on %s: map %d^2, %d samples, tau %g, %s" % (args.workload, n, count, tau, kern),
+          file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    mesh = P.build_mesh(torch.from_numpy(nrm).cuda())
+    hier = P.build_hierarchy(mesh, cluster=tau > 0)
+    tq = torch.from_numpy(q).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    attempts = 2 if tau > 0 else 1
+    xi = torch.rand((attempts, count, 2), dtype=torch.float64, device="cuda", generator=g)
+    m = torch.empty((count, 2), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        P.sample_batch(hier, tq, xi, tau=tau, sigma_to_r=s2r, kernel=kern, tri=False, m=m)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    mm = m.cpu().numpy()
+    assert np.isfinite(mm).mean() > 0.999
+    # algorithmic bytes per sample: query 24, one uniform pair 16, the sample 8, the
+    # unit's four corner normals 32 and clamp byte 1; with the cut, 4 per residual read
+    # (entry level down to the unit) and 1 for the cluster clamp byte instead
+    _, tri, _ = P.sample_batch(hier, tq, xi, tau=tau, sigma_to_r=s2r, kernel=kern)
+    lev = (tri.cpu().numpy().view(np.uint64) >> np.uint64(58)).astype(np.int64)
+    per = 81.0
+    if tau > 0:
+        rmax = np.maximum(q[:, 2], q[:, 3]).astype(np.float64) * s2r
+        l0 = np.minimum(np.ceil(np.log2(np.maximum(rmax, 1.0))), int(np.log2(n)))
+        valid = lev >= 0
+        per += float(4.0 * np.mean(np.where(lev > 0, l0 - lev + 1, l0)[valid]))
+    abytes = per * count
+    achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    line = {"metric": "P-NDF samples/sec at 1 MI355X", "value": count * args.steps / wall, "unit": "samples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": args.workload + " sampling", "map": "%s %dx%d" % (mc["kind"], n, n),
+                       "samples": count, "tau": tau, "kernel": kern, "sigma_to_r": s2r, "attempts": attempts},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "kernel_ms": kernel_ms, "algorithmic_bytes_per_sample": per,
+            "cluster_share": float((lev > 0).mean())}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +300,8 @@ def main():
     ap.add_argument("--sigma-to-r", type=float, default=None,
                     help="support half-width in sigma (default 3 for gaussian, 1.5 for disk and box)")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (continuous batching)")
+    ap.add_argument("--sample", action="store_true", help="sampling benchmark (pndf_sample_batch)")
+    ap.add_argument("--sample-tau", type=float, default=0.0)
     ap.add_argument("--serve-tau", type=float, default=1e-3)
     ap.add_argument("--serve-tiles", type=int, default=200)
     ap.add_argument("--serve-sigma-max", type=float, default=4096.0)
@@ -258,6 +331,9 @@ def main():
         return
     if args.serve:
         serve_bench(args)
+        return
+    if args.sample:
+        sample_bench(args)
         return
     import paper_2505_08985_amd as P
     import workloads

@@ -179,6 +179,41 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
                            uint64_t* d_ids, float* d_terms, uint64_t capacity,
                            uint64_t* required, void* stream);
 
+/*
+ * Sampling of the P-NDF (section "Sampling and evaluation", Eq. debias; with
+ * tau > 0 the cluster field of the cut, section "Acceleration by mesh
+ * clustering"), consistent with pndf_eval_batch: for query k (x, y, sx, sy used,
+ * hx, hy ignored) it draws u from the footprint kernel over the support the
+ * evaluation integrates and returns the normal m of the triangle (or, with the
+ * cut, the cluster triangle) containing u, warped onto the replacement
+ * triangle when that triangle is clamped.  The density of m is D(m) over D's
+ * total mass, for each kernel and tau.
+ *
+ *  d_xi       device, attempts x nq pairs of uniforms in [0, 1), attempt-major:
+ *             pair t of query k at d_xi[2 (t nq + k)], d_xi[2 (t nq + k) + 1].
+ *             The caller draws them (any generator).  The Gaussian footprint is
+ *             drawn by inverse CDF per axis; with tau > 0 a draw whose cut unit
+ *             lies outside the included cells is rejected and the next pair is
+ *             used (a first draw is rejected with probability of order 1e-2);
+ *             disk and box draws (uniform on the ellipse / rectangle) and tau = 0
+ *             use the first pair only.
+ *  attempts   >= 1 pairs per query.
+ *  opts       kernel, tau, sigma_to_r as for pndf_eval_batch (algo ignored,
+ *             flags must be 0); tau > 0 needs clusters.
+ *  d_m        device, nq float2: the sampled normal; NaN when the query is
+ *             invalid (as for the evaluation), a used pair lies outside [0, 1),
+ *             or every attempt was rejected.
+ *  d_tri      device, nq triangle ids (same encoding as pndf_eval_hits), ~0 when
+ *             m is NaN; may be NULL.
+ *  d_u        device, nq double2: the drawn texture coordinates (unrolled, not
+ *             wrapped onto the torus; the last draw when all were rejected); may
+ *             be NULL.
+ * Asynchronous on `stream`; deterministic.
+ */
+pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t nq, const double* d_xi,
+                              int32_t attempts, const pndf_eval_opts* opts, float* d_m, uint64_t* d_tri,
+                              double* d_u, void* stream);
+
 /* Release handles (no work may be in flight on them).  NULL is ignored. */
 void pndf_destroy_mesh(pndf_mesh* mesh);
 void pndf_destroy_hierarchy(pndf_hier* h);

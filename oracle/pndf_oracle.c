@@ -884,8 +884,8 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
  * (triangle id as in the evaluation's hit lists), flags: bit0 a cut decision on
  * the way within 1e-5 relative of t; bit1 u within `band` of a unit edge or
  * diagonal (the triangle may differ under rounding) or of the rejection
- * boundary; bit2 every attempt was rejected (m = NaN).  Invalid queries or
- * uniforms give NaN with tri = ~0.
+ * boundary; bit2 every attempt was rejected (m = NaN).  Invalid queries, or a
+ * pair of uniforms outside [0, 1) among those used, give NaN with tri = ~0.
  */
 int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
                 const float* queries, const double* xi, int64_t nq, int attempts, float tau, float s2r,
@@ -909,20 +909,11 @@ int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const fl
         double u[2] = {NAN, NAN}, mo[2] = {NAN, NAN};
         uint64_t id = ~(uint64_t)0;
         int bad = setup_query(&m, queries + 6 * k, tau, s2r, 0.0, kernel, &q);
-        for (int a = 0; !bad && a < attempts; a++) {
-            double x0 = xi[(2 * k) * attempts + 2 * a], x1 = xi[(2 * k) * attempts + 2 * a + 1];
-            if (!(x0 >= 0.0 && x0 < 1.0 && x1 >= 0.0 && x1 < 1.0)) { bad = 1; break; }
-        }
-        if (bad) {
-            uout[2 * k] = uout[2 * k + 1] = NAN;
-            mout[2 * k] = mout[2 * k + 1] = NAN;
-            tri[k] = ~(uint64_t)0;
-            flags[k] = 0;
-            continue;
-        }
         int done = 0;
-        for (int a = 0; a < attempts && !done; a++) {
+        for (int a = 0; !bad && a < attempts && !done; a++) {
             double x0 = xi[(2 * k) * attempts + 2 * a], x1 = xi[(2 * k) * attempts + 2 * a + 1];
+            /* a pair that is used must be uniforms in [0, 1) */
+            if (!(x0 >= 0.0 && x0 < 1.0 && x1 >= 0.0 && x1 < 1.0)) { bad = 1; break; }
             if (kernel == 1) {
                 double rad = sqrt(x0), ang = 2.0 * OR_PI * x1;
                 u[0] = q.x + q.rx * rad * cos(ang);
@@ -951,7 +942,12 @@ int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const fl
             id = OR_ID(lev, I, J, half);
             done = 1;
         }
-        if (!done) {
+        if (bad) {
+            u[0] = u[1] = NAN;
+            mo[0] = mo[1] = NAN;
+            id = ~(uint64_t)0;
+            fl = 0;
+        } else if (!done) {
             fl |= 4;
             mo[0] = mo[1] = NAN;
             id = ~(uint64_t)0;

@@ -59,6 +59,8 @@ _eval_batch = _sig("pndf_eval_batch", _i32, [_vp, _vp, _i64, ctypes.POINTER(Eval
 _eval_counts = _sig("pndf_eval_counts", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp])
 _eval_hits = _sig("pndf_eval_hits", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp, _vp,
                                            _u64, ctypes.POINTER(_u64), _vp])
+_sample_batch = _sig("pndf_sample_batch", _i32, [_vp, _vp, _i64, _vp, _i32, ctypes.POINTER(EvalOpts), _vp, _vp,
+                                                 _vp, _vp])
 _destroy_mesh = _sig("pndf_destroy_mesh", None, [_vp])
 _destroy_hier = _sig("pndf_destroy_hierarchy", None, [_vp])
 _status_string = _sig("pndf_status_string", ctypes.c_char_p, [_i32])
@@ -79,7 +81,7 @@ _autotune = _sig("pndf_autotune", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts
                                          ctypes.POINTER(ctypes.c_double), _vp])
 
 EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_eval_counts",
-            "pndf_eval_hits", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
+            "pndf_eval_hits", "pndf_sample_batch", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
             "pndf_last_error", "pndf_mesh_info", "pndf_mesh_export", "pndf_hier_info",
             "pndf_hier_export_level", "pndf_default_tuning", "pndf_plan_create", "pndf_plan_eval",
             "pndf_plan_get_stats", "pndf_plan_get_tuning", "pndf_plan_destroy", "pndf_autotune"]
@@ -203,6 +205,25 @@ def eval_batch(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, st
     _check(_eval_batch(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
                        _stream(stream)), "pndf_eval_batch")
     return out
+
+
+def sample_batch(hier, queries, xi, tau=0.0, sigma_to_r=3.0, kernel=0, tri=True, u=False, m=None, stream=None):
+    """One P-NDF sample per query.  xi: (attempts, Q, 2) float64 device tensor of
+    uniforms in [0, 1).  Returns (m (Q, 2) float32, tri (Q,) int64 or None,
+    u (Q, 2) float64 or None)."""
+    qp, nq = _queries(queries)
+    if xi.dim() != 3 or xi.shape[1] != nq or xi.shape[2] != 2:
+        raise ValueError("xi must have shape (attempts, Q, 2)")
+    dev = queries.device
+    if m is None:
+        m = torch.empty((nq, 2), dtype=torch.float32, device=dev)
+    t = torch.empty(nq, dtype=torch.int64, device=dev) if tri else None
+    uu = torch.empty((nq, 2), dtype=torch.float64, device=dev) if u else None
+    o = _opts(tau, sigma_to_r, "auto", kernel)
+    _check(_sample_batch(hier.handle, qp, nq, _dev_ptr(xi, torch.float64, "xi"), int(xi.shape[0]), ctypes.byref(o),
+                         _dev_ptr(m, torch.float32, "m"), _vp(t.data_ptr()) if tri else None,
+                         _vp(uu.data_ptr()) if u else None, _stream(stream)), "pndf_sample_batch")
+    return m, t, uu
 
 
 def eval_counts(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", stream=None, kernel=0):

@@ -301,6 +301,32 @@ static pndf_status eval_common(const pndf_hier* h, const pndf_query* d_q, int64_
     return check_sticky();
 }
 
+pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t nq, const double* d_xi,
+                              int32_t attempts, const pndf_eval_opts* opts, float* d_m, uint64_t* d_tri,
+                              double* d_u, void* stream)
+{
+    if (!h) return invalid("hierarchy is NULL");
+    if (nq < 0) return invalid("nq < 0");
+    if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
+    if (attempts < 1 || attempts > 64) return invalid("attempts must be in [1, 64]");
+    if (nq > 0 && (!d_q || !d_xi || !d_m)) return invalid("query, uniform or output pointer is NULL");
+    pndf_eval_opts o{PNDF_KERNEL_GAUSSIAN, 0.f, 3.f, PNDF_ALGO_AUTO, 0};
+    if (opts) {
+        o = *opts;
+        o.algo = PNDF_ALGO_AUTO;  // ignored
+    }
+    if (o.flags != 0) return invalid("sampling takes no flags");
+    pndf_eval_opts r;
+    pndf_status st = resolve_opts(h, &o, &r);
+    if (st != PNDF_OK) return st;
+    st = check_sticky();
+    if (st != PNDF_OK) return st;
+    SampleArgs a{d_q, d_xi, nq, attempts, r.tau, r.sigma_to_r, r.kernel, reinterpret_cast<float2*>(d_m), d_tri,
+                 reinterpret_cast<double2*>(d_u)};
+    const hipError_t e = launch_sample(h->dev, a, (hipStream_t)stream);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_sample_batch");
+}
+
 pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
                             const pndf_eval_opts* opts, float* d_out, void* stream)
 {

@@ -229,6 +229,21 @@ struct EvalArgs {
 };
 hipError_t launch_eval(const HierDev& H, const EvalArgs& a, int algo, hipStream_t s);
 
+// One sample of the P-NDF per query (sample.hip).
+struct SampleArgs {
+    const pndf_query* q;
+    const double* xi;          // attempts x nq pairs of uniforms, attempt-major
+    int64_t nq;
+    int attempts;
+    float tau;
+    float s2r;
+    int kernel;                // PNDF_KERNEL_*
+    float2* m;                 // sampled normal per query
+    uint64_t* tri;             // optional: triangle id
+    double2* u;                // optional: unrolled texture coordinates
+};
+hipError_t launch_sample(const HierDev& H, const SampleArgs& a, hipStream_t s);
+
 // Spatial processing order of a batch: queries bucketed by the Morton code of their
 // centre cell (64 x 64 buckets over the torus), stream-ordered workspace.
 hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s);
