@@ -57,9 +57,13 @@ def load():
     lib.or_sample_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, _fp, _fp, _dp, ctypes.c_int64,
                                 ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_int,
                                 _dp, _dp, _u64p, _i32p]
+    lib.or_projected_area.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, ctypes.c_int64, ctypes.c_float,
+                                      ctypes.c_int, _dp]
+    lib.or_tri_projected.argtypes = [_dp, _dp]
+    lib.or_tri_projected.restype = ctypes.c_double
     lib.or_num_threads.argtypes = []
     for f in (lib.or_mesh, lib.or_cluster_nodes, lib.or_fine_contrib, lib.or_eval, lib.or_eval_k,
-              lib.or_sample_normals, lib.or_sample_k, lib.or_num_threads):
+              lib.or_sample_normals, lib.or_sample_k, lib.or_projected_area, lib.or_num_threads):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -235,6 +239,29 @@ def sample(nrm, queries, xi, tau=0.0, eps=1e-6, sigma_to_r=3.0, kernel="gaussian
     if rc:
         raise ValueError("or_sample_k failed (%d)" % rc)
     return dict(u=u, m=m, tri=tri, flags=flags)
+
+
+def projected_area(nrm, queries, eps=1e-6, sigma_to_r=3.0, kernel="gaussian"):
+    """P(w) per query (Q, 6) float32: x, y, sx, sy, w_x, w_y (w_z = sqrt(1 - w_x^2 - w_y^2)),
+    with the footprint kernel constant over each triangle (its value at the uv
+    centroid).  Brute force, FP64."""
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    nrm = _map(nrm)
+    q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, 6)
+    out = np.empty(len(q))
+    rc = load().or_projected_area(nrm.shape[0], _p(nrm, _fp), eps, _p(q, _fp), len(q), sigma_to_r, kid,
+                                  _p(out, _dp))
+    if rc:
+        raise ValueError("or_projected_area failed (%d)" % rc)
+    return out
+
+
+def tri_projected(tri, w):
+    """Integral of (w . m~) / m~_z over the part of the normal triangle tri (3, 2)
+    where m~ . w >= 0 and |m| <= 1, for the unit direction w (3,), w_z >= 0."""
+    tri = np.ascontiguousarray(tri, dtype=np.float64).reshape(3, 2)
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(3)
+    return float(load().or_tri_projected(_p(tri, _dp), _p(w, _dp)))
 
 
 def triangle_id(level, I, J, half):

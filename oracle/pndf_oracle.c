@@ -32,6 +32,10 @@
  *   - cut: starting at the entry level ceil(log2 max(r)) (supplement, "Entry
  *     level"), descend until a node satisfies e^l <= r_x r_y tau (section
  *     "Acceleration by mesh clustering").
+ *   - projected area (shadow-masking): Eq. lambda with the kernel constant over
+ *     each triangle, the rotation to w_y = 0, clipping to the visible region, and
+ *     the boundary integrals of Eq. area-integral / Eq. line-integral (section
+ *     "Shadow-masking" and its supplement).
  *   - sampling: u from the footprint kernel over the support the evaluation
  *     integrates, m the normal of the triangle (or, with the cut, the cluster
  *     triangle) containing u, warped onto the replacement triangle when clamped
@@ -43,7 +47,10 @@
  * histogram, the supplement's printed coefficient matrices, transpose
  * invariance; for sampling: scipy's normal quantile, the interpolated field,
  * uniformity of disk and box draws, the linear field through clusters, the
- * support kept by rejection, and histograms of samples against D) except the orientation of the equilateral replacement triangle,
+ * support kept by rejection, and histograms of samples against D; for the
+ * projected area: the hemisphere's clipped-cosine closed form, the triangle
+ * area at normal incidence, quadrature of the area integral, the footprint mass
+ * at normal incidence, rotation invariance, Monte Carlo and the flat map) except the orientation of the equilateral replacement triangle,
  * which the paper leaves free ("any other shape"): parity unpinned, fixed by
  * convention (vertices at 90, 210, 330 degrees in (a, b, c) order).
  */
@@ -958,6 +965,300 @@ int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const fl
         mout[2 * k + 1] = mo[1];
         tri[k] = id;
         flags[k] = fl;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------- projected area -- */
+/*
+ * Projected area of the P-NDF (section "Shadow-masking", Eq. lambda):
+ *   P(w) = integral of D(m) max(m~ . w, 0) over the solid angle of m~, m~ the unit
+ * normal (m_x, m_y, sqrt(1 - |m|^2)) over the projected normal m.  With the
+ * footprint kernel taken constant over each triangle (its value at the
+ * triangle's uv centroid), Eq. area-integral gives
+ *   P(w) = sum over triangles k(tri) / J(tri) * integral over n+(tri) of
+ *          (w_x m_x / m~_z + w_z) dm
+ * in the frame rotated about z so that w_y = 0 and w_x >= 0; J is the (clamped)
+ * Jacobian and n+(tri) the part of the normal triangle where m~ . w >= 0 and
+ * |m| <= 1.  That region V is bounded on the right by the unit circle and on the
+ * left by the semi-ellipse m_x = -w_z sqrt(1 - m_y^2), and is convex.
+ *
+ * The integral over n+(tri) is a boundary integral by Stokes' theorem, the curl of
+ * (0, w_z m_x - w_x m~_z, 0) being the integrand (supplement, "Correctness of the
+ * area-line integral conversion"): the counter-clockwise boundary integral of
+ * F dm_y, F = w_z m_x - w_x m~_z, over the clipped edges of the triangle and the
+ * pieces of the boundary of V between them.  Closed forms, with
+ * S(y) = (asin y + y sqrt(1 - y^2)) / 2 (the integral of sqrt(1 - t^2) from 0):
+ *   segment P -> Q: w_z (Q_y - P_y)(Q_x + P_x) / 2 - w_x d_y r^2 [S(p/r)] from
+ *     p = d.P to d.Q, d the unit direction, r = sqrt(1 - s^2), s the line's
+ *     distance to the origin (on the line, m~_z = sqrt(r^2 - p^2));
+ *   unit-circle arc (m~_z = 0, m_x = sqrt(1 - y^2)): w_z [S(y)] between its ends;
+ *   ellipse arc (F = -sqrt(1 - y^2) there): -[S(y)] between its ends.
+ * (The supplement's printed sign of the segment's arcsine term and its "d_x"
+ * disagree with its own derivation; these follow the mathematics.)
+ */
+
+static double S_half(double y)
+{
+    if (y > 1.0) y = 1.0;
+    if (y < -1.0) y = -1.0;
+    return 0.5 * (asin(y) + y * sqrt(1.0 - y * y));
+}
+
+/* in the region V (closed), for the canonical w = (wx, 0, wz) */
+static int in_vis(double x, double y, double wz)
+{
+    if (x * x + y * y > 1.0) return 0;
+    if (x >= 0.0) return 1;
+    return x * x + wz * wz * y * y <= wz * wz;
+}
+
+/* the boundary integral of F dm_y along the segment P -> Q (inside V) */
+static double seg_term(const double P[2], const double Q[2], double wx, double wz)
+{
+    double dx = Q[0] - P[0], dy = Q[1] - P[1];
+    double len = sqrt(dx * dx + dy * dy);
+    if (len == 0.0) return 0.0;
+    double t = 0.5 * wz * dy * (Q[0] + P[0]);
+    dx /= len;
+    dy /= len;
+    double s = dy * P[0] - dx * P[1];
+    double r2 = 1.0 - s * s;
+    if (r2 <= 0.0) return t; /* tangent to the unit circle: m~_z = 0 on it */
+    double r = sqrt(r2);
+    double p0 = dx * P[0] + dy * P[1], p1 = dx * Q[0] + dy * Q[1];
+    return t - wx * dy * r2 * (S_half(p1 / r) - S_half(p0 / r));
+}
+
+/* position of a boundary point of V along its counter-clockwise traversal,
+ * starting at (0, -1): the right semicircle (y from -1 to 1) maps to y + 1 in
+ * [0, 2], the left semi-ellipse (y from 1 to -1) to 3 - y in [2, 4] */
+static double vis_pos(double x, double y)
+{
+    if (y > 1.0) y = 1.0;
+    if (y < -1.0) y = -1.0;
+    return x >= 0.0 ? y + 1.0 : 3.0 - y;
+}
+
+/* the boundary integral of F dm_y along the boundary of V counter-clockwise
+ * from position a to position b (a <= b < a + 4, positions modulo 4) */
+static double arc_term(double a, double b, double wz)
+{
+    double sum = 0.0;
+    while (b - a > 1e-300) {
+        double base = floor(a / 2.0) * 2.0; /* start of the current half */
+        double end = base + 2.0 < b ? base + 2.0 : b;
+        double la = a - base, lb = end - base; /* in [0, 2] */
+        if (fmod(base, 4.0) == 0.0) {
+            /* right semicircle: y = pos - 1, F = w_z sqrt(1 - y^2) */
+            sum += wz * (S_half(lb - 1.0) - S_half(la - 1.0));
+        } else {
+            /* left semi-ellipse: y = 1 - pos, F = -sqrt(1 - y^2), y decreasing */
+            sum += -(S_half(1.0 - lb) - S_half(1.0 - la));
+        }
+        a = end;
+    }
+    return sum;
+}
+
+/* roots t in [0, 1] of the segment P + t D meeting the boundary of V */
+static int vis_crossings(const double P[2], const double D[2], double wz, double t[4])
+{
+    int n = 0;
+    /* unit circle, right half */
+    double a = D[0] * D[0] + D[1] * D[1], b = 2.0 * (P[0] * D[0] + P[1] * D[1]), c = P[0] * P[0] + P[1] * P[1] - 1.0;
+    for (int pass = 0; pass < 2; pass++) {
+        double disc = b * b - 4.0 * a * c;
+        if (a > 0.0 && disc >= 0.0) {
+            double sq = sqrt(disc);
+            double r[2] = {(-b - sq) / (2.0 * a), (-b + sq) / (2.0 * a)};
+            for (int k = 0; k < 2; k++) {
+                if (r[k] < 0.0 || r[k] > 1.0) continue;
+                double x = P[0] + r[k] * D[0];
+                if ((pass == 0 && x >= 0.0) || (pass == 1 && x <= 0.0)) t[n++] = r[k];
+            }
+        }
+        /* then the ellipse x^2 + wz^2 y^2 = wz^2, left half */
+        a = D[0] * D[0] + wz * wz * D[1] * D[1];
+        b = 2.0 * (P[0] * D[0] + wz * wz * P[1] * D[1]);
+        c = P[0] * P[0] + wz * wz * P[1] * P[1] - wz * wz;
+    }
+    return n;
+}
+
+/* integral of (w_x m_x / m~_z + w_z) over (triangle v) intersected with V, the
+ * triangle given in the canonical frame */
+static double tri_projected(const double v0[3][2], double wx, double wz)
+{
+    double v[3][2];
+    memcpy(v, v0, sizeof v);
+    double area2 = sarea2(v[0], v[1], v[2]);
+    if (area2 < 0.0) { /* counter-clockwise */
+        double tmp[2];
+        memcpy(tmp, v[1], sizeof tmp); memcpy(v[1], v[2], sizeof tmp); memcpy(v[2], tmp, sizeof tmp);
+    }
+    /* per edge: the part inside V (V convex: one interval) */
+    double ent[3][2], ext[3][2];
+    int has[3];
+    int any = 0;
+    for (int e = 0; e < 3; e++) {
+        const double* P = v[e];
+        const double* Q = v[(e + 1) % 3];
+        double D[2] = {Q[0] - P[0], Q[1] - P[1]};
+        double ts[8];
+        int nt = 0;
+        ts[nt++] = 0.0;
+        ts[nt++] = 1.0;
+        nt += vis_crossings(P, D, wz, ts + nt);
+        /* sort */
+        for (int i = 1; i < nt; i++)
+            for (int j = i; j > 0 && ts[j] < ts[j - 1]; j--) { double x = ts[j]; ts[j] = ts[j - 1]; ts[j - 1] = x; }
+        double t0 = 2.0, t1 = -1.0;
+        for (int i = 0; i + 1 < nt; i++) {
+            double tm = 0.5 * (ts[i] + ts[i + 1]);
+            if (ts[i + 1] - ts[i] <= 0.0) continue;
+            if (in_vis(P[0] + tm * D[0], P[1] + tm * D[1], wz)) {
+                if (ts[i] < t0) t0 = ts[i];
+                if (ts[i + 1] > t1) t1 = ts[i + 1];
+            }
+        }
+        has[e] = t1 > t0;
+        if (has[e]) {
+            /* (the vertices themselves at t = 0 and 1, so that consecutive edges meet
+             * exactly at a vertex inside V) */
+            if (t0 == 0.0) { ent[e][0] = P[0]; ent[e][1] = P[1]; }
+            else { ent[e][0] = P[0] + t0 * D[0]; ent[e][1] = P[1] + t0 * D[1]; }
+            if (t1 == 1.0) { ext[e][0] = Q[0]; ext[e][1] = Q[1]; }
+            else { ext[e][0] = P[0] + t1 * D[0]; ext[e][1] = P[1] + t1 * D[1]; }
+            any = 1;
+        }
+    }
+    if (!any) {
+        /* no edge inside V: V lies inside the triangle, or they are disjoint
+         * (the origin, a point of V, decides) */
+        double o[2] = {0.0, 0.0};
+        double a0 = sarea2(o, v[1], v[2]), a1 = sarea2(v[0], o, v[2]), a2 = sarea2(v[0], v[1], o);
+        if (a0 >= 0.0 && a1 >= 0.0 && a2 >= 0.0) return arc_term(0.0, 4.0, wz);
+        return 0.0;
+    }
+    double sum = 0.0;
+    for (int e = 0; e < 3; e++) {
+        if (!has[e]) continue;
+        sum += seg_term(ent[e], ext[e], wx, wz);
+        /* from this edge's exit along the boundary of V to the next edge's entry,
+         * unless the exit is the next edge's start (a vertex inside V) */
+        int f = (e + 1) % 3;
+        while (!has[f]) f = (f + 1) % 3;
+        if (ext[e][0] == ent[f][0] && ext[e][1] == ent[f][1]) continue;
+        double a = vis_pos(ext[e][0], ext[e][1]), b = vis_pos(ent[f][0], ent[f][1]);
+        if (b < a) b += 4.0;
+        sum += arc_term(a, b, wz);
+    }
+    return sum;
+}
+
+/* exposed for the pins: the integral for one triangle (3 x 2 normals) and a
+ * direction w (x, y, z), w_z >= 0 */
+double or_tri_projected(const double* tri, const double* w)
+{
+    double len = sqrt(w[0] * w[0] + w[1] * w[1]);
+    double c = len > 0.0 ? w[0] / len : 1.0, sn = len > 0.0 ? w[1] / len : 0.0;
+    double v[3][2];
+    for (int k = 0; k < 3; k++) {
+        v[k][0] = c * tri[2 * k] + sn * tri[2 * k + 1];
+        v[k][1] = -sn * tri[2 * k] + c * tri[2 * k + 1];
+    }
+    return tri_projected((const double(*)[2])v, len, w[2]);
+}
+
+/* the footprint kernel at uv point (ux, uy) of the cell (i, j) (torus indices),
+ * summed over the cell's included periodic images */
+static double kernel_at(const map_t* m, const query_t* q, double ux, double uy, long i, long j)
+{
+    int amb = 0;
+    if (q->kernel == 2)
+        return box_count(ux, i, 1, q->cxlo, q->cxhi, m->n, q->x, q->rx, &amb) *
+               box_count(uy, j, 1, q->cylo, q->cyhi, m->n, q->y, q->ry, &amb) / (4.0 * q->rx * q->ry);
+    if (q->kernel == 1) return disk_count(ux, uy, i, j, 1, q, m->n, &amb) / (OR_PI * q->rx * q->ry);
+    return gauss_sum(ux, i, 1, q->cxlo, q->cxhi, m->n, q->x, q->sx) *
+           gauss_sum(uy, j, 1, q->cylo, q->cyhi, m->n, q->y, q->sy) / (2.0 * OR_PI * q->sx * q->sy);
+}
+
+/*
+ * Projected area P(w) (see above) for nq queries: x, y, sx, sy as for the
+ * evaluation; the last two floats are w_x, w_y of the unit direction w, with
+ * w_z = sqrt(1 - w_x^2 - w_y^2) >= 0.  Brute force over every triangle of every
+ * included cell (the paper's own implementation is brute force too).  P[k] is NaN
+ * for an invalid query or |(w_x, w_y)| > 1.
+ */
+int or_projected_area(int n, const float* nrm, float eps, const float* queries, int64_t nq, float s2r,
+                      int kernel, double* Pout)
+{
+    if (kernel < 0 || kernel > 2) return 3;
+    map_t m;
+    m.n = n;
+    m.L = ilog2_exact(n);
+    if (m.L < 1) return 1;
+    m.nrm = nrm;
+    m.eps = (double)eps;
+    m.clu_n = NULL;
+    m.clu_e = NULL;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nq; k++) {
+        query_t q;
+        const float* qr = queries + 6 * k;
+        double wx = qr[4], wy = qr[5];
+        double wl2 = wx * wx + wy * wy;
+        if (setup_query(&m, qr, 0.0f, s2r, 0.0, kernel, &q) || !(wl2 <= 1.0)) {
+            Pout[k] = NAN;
+            continue;
+        }
+        double wz = sqrt(1.0 - wl2), wl = sqrt(wl2);
+        /* rotation about z taking w to (wl, 0, wz) */
+        double c = wl > 0.0 ? wx / wl : 1.0, sn = wl > 0.0 ? wy / wl : 0.0;
+        long* xi = (long*)malloc(sizeof(long) * (size_t)n);
+        long* yj = (long*)malloc(sizeof(long) * (size_t)n);
+        long nx = axis_cells(q.cxlo, q.cxhi, n, xi);
+        long ny = axis_cells(q.cylo, q.cyhi, n, yj);
+        double P = 0.0;
+        for (long b = 0; b < ny; b++)
+            for (long a = 0; a < nx; a++) {
+                long i = xi[a], j = yj[b];
+                double nv4[4][2];
+                texel(m.nrm, n, i, j, nv4[0]);
+                texel(m.nrm, n, i + 1, j, nv4[1]);
+                texel(m.nrm, n, i, j + 1, nv4[2]);
+                texel(m.nrm, n, i + 1, j + 1, nv4[3]);
+                double centre[2] = {0.5 * (nv4[1][0] + nv4[2][0]), 0.5 * (nv4[1][1] + nv4[2][1])};
+                for (int half = 0; half < 2; half++) {
+                    double nv[3][2];
+                    if (half == 0) {
+                        memcpy(nv[0], nv4[0], sizeof nv[0]); memcpy(nv[1], nv4[1], sizeof nv[0]);
+                        memcpy(nv[2], nv4[2], sizeof nv[0]);
+                    } else {
+                        memcpy(nv[0], nv4[3], sizeof nv[0]); memcpy(nv[1], nv4[2], sizeof nv[0]);
+                        memcpy(nv[2], nv4[1], sizeof nv[0]);
+                    }
+                    double J = jac(nv[0], nv[1], nv[2]);
+                    if (J < m.eps) {
+                        eqtri(centre, eq_rho(0.5 * m.eps), nv);
+                        J = m.eps;
+                    }
+                    /* the kernel, constant over the triangle: its value at the uv centroid */
+                    double third = half == 0 ? 1.0 / 3.0 : 2.0 / 3.0;
+                    double kv = kernel_at(&m, &q, (double)i + third, (double)j + third, i, j);
+                    if (kv == 0.0) continue;
+                    double rv[3][2];
+                    for (int v = 0; v < 3; v++) {
+                        rv[v][0] = c * nv[v][0] + sn * nv[v][1];
+                        rv[v][1] = -sn * nv[v][0] + c * nv[v][1];
+                    }
+                    P += kv / J * tri_projected((const double(*)[2])rv, wl, wz);
+                }
+            }
+        free(xi);
+        free(yj);
+        Pout[k] = P;
     }
     return 0;
 }
