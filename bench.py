@@ -36,14 +36,15 @@ METRIC = "P-NDF queries/sec at 1 MI355X vs footprint size; p99 tile latency (ser
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane operations per second, in T
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_plain_powerlaw2048.json")
-KERNEL_SRC = [os.path.join(ROOT, "paper_2505_08985_amd", "csrc", f)
-              for f in ("eval.hip", "pndf_internal.h")]
+EVAL_SRC = ("eval.hip", "pndf_internal.h")
+SAMPLE_SRC = ("sample.hip", "pndf_internal.h")
+SAMPLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_powerlaw2048.json")
 
 
-def kernel_hash():
+def kernel_hash(files=EVAL_SRC):
     h = hashlib.sha256()
-    for p in KERNEL_SRC:
-        h.update(open(p, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2505_08985_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -268,15 +269,111 @@ def sample_bench(args):
         per += float(4.0 * np.mean(np.where(lev > 0, l0 - lev + 1, l0)[valid]))
     abytes = per * count
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        t = json.load(open(SAMPLE_TRAFFIC_FILE))
+        if (t.get("kernel_hash") == kernel_hash(SAMPLE_SRC) and t.get("samples") == count and tau == 0
+                and kern == "gaussian" and args.workload == "powerlaw2048"):
+            traffic = float(t["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        pass
     line = {"metric": "P-NDF samples/sec at 1 MI355X", "value": count * args.steps / wall, "unit": "samples/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": args.workload + " sampling", "map": "%s %dx%d" % (mc["kind"], n, n),
                        "samples": count, "tau": tau, "kernel": kern, "sigma_to_r": s2r, "attempts": attempts},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
             "kernel_ms": kernel_ms, "algorithmic_bytes_per_sample": per,
             "cluster_share": float((lev > 0).mean())}
+    print(json.dumps(line), flush=True)
+
+
+FP64_PEAK_TFLOPS = 78.6
+# FP64 operations per triangle of the projected area's fast path (triangle inside
+# the visible region): rotation 12, visibility tests 24, three boundary segments of
+# ~40 each (asin and sqrt counted as one operation), kernel weight 20, sum 4
+PROJ_OPS_PER_TRIANGLE = 180.0
+
+
+def projarea_bench(args):
+    """Projected area P(w) (pndf_projected_area, brute force): footprints
+    log-uniform in [1, 8] texels on the workload's map, directions uniform on the
+    hemisphere."""
+    import torch
+    import paper_2505_08985_amd as P
+    import workloads
+    cfg = workloads.CONFIGS[args.workload]
+    mc, qc = cfg["map"], cfg["queries"]
+    n = mc["n"]
+    kern = args.kernel
+    s2r = args.sigma_to_r if args.sigma_to_r is not None else (3.0 if kern == "gaussian" else 1.5)
+    count = args.queries or (1 << 16)
+    nrm = workloads.make_map(**mc)
+    q = workloads.uniform_queries(n, count, qc["seed"], (1.0, 8.0), qc["radius"])
+    rng = np.random.default_rng(7)
+    z = rng.uniform(0, 1, count)
+    ph = rng.uniform(0, 2 * np.pi, count)
+    r = np.sqrt(1 - z * z)
+    q[:, 4] = (r * np.cos(ph)).astype(np.float32)
+    q[:, 5] = (r * np.sin(ph)).astype(np.float32)
+    # keep |w_xy| <= 1 after rounding to float32 (|w_xy| > 1 is an invalid direction)
+    over = (q[:, 4].astype(np.float64) ** 2 + q[:, 5].astype(np.float64) ** 2) > 1.0
+    q[over, 4:6] *= np.float32(1.0 - 2.0 ** -22)
+    print("[bench] projected area on %s: map %d^2, %d queries, sigma 1-8, %s" % (args.workload, n, count, kern),
+          file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    mesh = P.build_mesh(torch.from_numpy(nrm).cuda())
+    hier = P.build_hierarchy(mesh, cluster=False)
+    tq = torch.from_numpy(q).cuda()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return P.projected_area(hier, tq, sigma_to_r=s2r, kernel=kern)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        out = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    assert np.isfinite(out.cpu().numpy()).all()
+    # triangles per query: two per included cell
+    rx = np.float32(s2r) * q[:, 2]
+    ry = np.float32(s2r) * q[:, 3]
+    nx = np.floor(q[:, 0] + rx) - (np.ceil(q[:, 0] - rx) - 1) + 1
+    ny = np.floor(q[:, 1] + ry) - (np.ceil(q[:, 1] - ry) - 1) + 1
+    tris = float((2.0 * nx * ny).sum())
+    achieved = tris * PROJ_OPS_PER_TRIANGLE / (kernel_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 256
+        t1 = time.perf_counter()
+        oracle.projected_area(nrm, q[:k], sigma_to_r=s2r, kernel=kern)
+        dt = time.perf_counter() - t1
+        k2 = int(min(count, max(k, 10.0 / max(dt, 1e-6) * k)))
+        t1 = time.perf_counter()
+        oracle.projected_area(nrm, q[:k2], sigma_to_r=s2r, kernel=kern)
+        dt2 = time.perf_counter() - t1
+        cpu = {"value": k2 / dt2, "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "first %d queries (%.1f s, FP64 brute force)" % (k2, dt2)}
+    line = {"metric": "P-NDF projected areas/sec at 1 MI355X", "value": count * args.steps / wall,
+            "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": args.workload + " projected area", "map": "%s %dx%d" % (mc["kind"], n, n),
+                       "queries": count, "sigma": [1.0, 8.0], "kernel": kern, "sigma_to_r": s2r},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None},
+            "cpu_baseline": cpu, "kernel_ms": kernel_ms, "triangles_per_query": tris / count}
     print(json.dumps(line), flush=True)
 
 
@@ -302,6 +399,7 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving benchmark (continuous batching)")
     ap.add_argument("--sample", action="store_true", help="sampling benchmark (pndf_sample_batch)")
     ap.add_argument("--sample-tau", type=float, default=0.0)
+    ap.add_argument("--projarea", action="store_true", help="projected-area benchmark (pndf_projected_area)")
     ap.add_argument("--serve-tau", type=float, default=1e-3)
     ap.add_argument("--serve-tiles", type=int, default=200)
     ap.add_argument("--serve-sigma-max", type=float, default=4096.0)
@@ -334,6 +432,9 @@ def main():
         return
     if args.sample:
         sample_bench(args)
+        return
+    if args.projarea:
+        projarea_bench(args)
         return
     import paper_2505_08985_amd as P
     import workloads

@@ -214,6 +214,32 @@ pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t
                               int32_t attempts, const pndf_eval_opts* opts, float* d_m, uint64_t* d_tri,
                               double* d_u, void* stream);
 
+/*
+ * Projected area of the P-NDF for shadow-masking (section "Shadow-masking",
+ * Eq. lambda, Eq. area-integral, Eq. line-integral):
+ *   P(w) = integral of D(m, x) max(m~ . w, 0) over the solid angle of the unit
+ *          normal m~ = (m, sqrt(1 - |m|^2)),
+ * with the footprint kernel taken constant over each triangle (its value at the
+ * triangle's uv centroid, summed over the included periodic images; exact for a
+ * box whose support contains the triangles).  Computed by brute force over every
+ * triangle of every included cell, each by rotation to w_y = 0, clipping to the
+ * visible region and closed-form boundary integrals (Stokes).  Then
+ *   Lambda(w) = P(w) / w_z - 1,
+ *   G(w_i, w_o, m) = H(m~ . w_i) H(m~ . w_o) / ((1 + Lambda(w_i)) (1 + Lambda(w_o))),
+ *   aggregated diffuse BRDF f_d = P(w_i) / (pi w_iz).
+ *
+ *  d_q       device, nq queries: x, y, sx, sy as for pndf_eval_batch; the last two
+ *            floats (hx, hy) carry w_x, w_y of the unit direction w, whose w_z is
+ *            sqrt(1 - w_x^2 - w_y^2) (the upper hemisphere).
+ *  opts      kernel and sigma_to_r; tau must be 0; algo ignored; flags must be 0.
+ *  d_P       device, nq floats: P(w); NaN for an invalid query (as for the
+ *            evaluation) or w_x^2 + w_y^2 > 1.
+ *  d_lambda  device, nq floats: Lambda(w) (+inf at w_z = 0); may be NULL.
+ * Asynchronous on `stream`.
+ */
+pndf_status pndf_projected_area(const pndf_hier* h, const pndf_query* d_q, int64_t nq, const pndf_eval_opts* opts,
+                                float* d_P, float* d_lambda, void* stream);
+
 /* Release handles (no work may be in flight on them).  NULL is ignored. */
 void pndf_destroy_mesh(pndf_mesh* mesh);
 void pndf_destroy_hierarchy(pndf_hier* h);

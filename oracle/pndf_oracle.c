@@ -1032,12 +1032,14 @@ static double seg_term(const double P[2], const double Q[2], double wx, double w
 
 /* position of a boundary point of V along its counter-clockwise traversal,
  * starting at (0, -1): the right semicircle (y from -1 to 1) maps to y + 1 in
- * [0, 2], the left semi-ellipse (y from 1 to -1) to 3 - y in [2, 4] */
+ * [0, 2], the left semi-ellipse (y from 1 to -1) to 3 - y in [2, 4].  A point is
+ * on the semicircle when x >= 0 and it lies on the unit circle (at w_z = 0 the
+ * semi-ellipse is the segment x = 0 inside the disk) */
 static double vis_pos(double x, double y)
 {
     if (y > 1.0) y = 1.0;
     if (y < -1.0) y = -1.0;
-    return x >= 0.0 ? y + 1.0 : 3.0 - y;
+    return (x >= 0.0 && x * x + y * y >= 1.0 - 1e-9) ? y + 1.0 : 3.0 - y;
 }
 
 /* the boundary integral of F dm_y along the boundary of V counter-clockwise
@@ -1061,27 +1063,32 @@ static double arc_term(double a, double b, double wz)
     return sum;
 }
 
-/* roots t in [0, 1] of the segment P + t D meeting the boundary of V */
+/* parameters t in [0, 1] where the segment P + t D meets the unit circle or the
+ * full ellipse; the boundary of V is made of parts of these two curves, so its
+ * crossings are among them (the others only split the segment further) */
 static int vis_crossings(const double P[2], const double D[2], double wz, double t[4])
 {
     int n = 0;
-    /* unit circle, right half */
+    /* unit circle */
     double a = D[0] * D[0] + D[1] * D[1], b = 2.0 * (P[0] * D[0] + P[1] * D[1]), c = P[0] * P[0] + P[1] * P[1] - 1.0;
     for (int pass = 0; pass < 2; pass++) {
         double disc = b * b - 4.0 * a * c;
         if (a > 0.0 && disc >= 0.0) {
             double sq = sqrt(disc);
             double r[2] = {(-b - sq) / (2.0 * a), (-b + sq) / (2.0 * a)};
-            for (int k = 0; k < 2; k++) {
-                if (r[k] < 0.0 || r[k] > 1.0) continue;
-                double x = P[0] + r[k] * D[0];
-                if ((pass == 0 && x >= 0.0) || (pass == 1 && x <= 0.0)) t[n++] = r[k];
-            }
+            for (int k = 0; k < 2; k++)
+                if (r[k] >= 0.0 && r[k] <= 1.0) t[n++] = r[k];
         }
-        /* then the ellipse x^2 + wz^2 y^2 = wz^2, left half */
+        /* then the ellipse x^2 + wz^2 y^2 = wz^2 */
         a = D[0] * D[0] + wz * wz * D[1] * D[1];
         b = 2.0 * (P[0] * D[0] + wz * wz * P[1] * D[1]);
         c = P[0] * P[0] + wz * wz * P[1] * P[1] - wz * wz;
+    }
+    /* and the line x = 0, which the ellipse becomes as wz -> 0 (where its
+     * discriminant is a difference of equal products and can round below 0) */
+    if (D[0] != 0.0) {
+        double r = -P[0] / D[0];
+        if (r >= 0.0 && r <= 1.0) t[n++] = r;
     }
     return n;
 }
@@ -1105,7 +1112,7 @@ static double tri_projected(const double v0[3][2], double wx, double wz)
         const double* P = v[e];
         const double* Q = v[(e + 1) % 3];
         double D[2] = {Q[0] - P[0], Q[1] - P[1]};
-        double ts[8];
+        double ts[9];
         int nt = 0;
         ts[nt++] = 0.0;
         ts[nt++] = 1.0;

@@ -61,6 +61,7 @@ _eval_hits = _sig("pndf_eval_hits", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOp
                                            _u64, ctypes.POINTER(_u64), _vp])
 _sample_batch = _sig("pndf_sample_batch", _i32, [_vp, _vp, _i64, _vp, _i32, ctypes.POINTER(EvalOpts), _vp, _vp,
                                                  _vp, _vp])
+_projected_area = _sig("pndf_projected_area", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp])
 _destroy_mesh = _sig("pndf_destroy_mesh", None, [_vp])
 _destroy_hier = _sig("pndf_destroy_hierarchy", None, [_vp])
 _status_string = _sig("pndf_status_string", ctypes.c_char_p, [_i32])
@@ -81,7 +82,7 @@ _autotune = _sig("pndf_autotune", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts
                                          ctypes.POINTER(ctypes.c_double), _vp])
 
 EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_eval_counts",
-            "pndf_eval_hits", "pndf_sample_batch", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
+            "pndf_eval_hits", "pndf_sample_batch", "pndf_projected_area", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
             "pndf_last_error", "pndf_mesh_info", "pndf_mesh_export", "pndf_hier_info",
             "pndf_hier_export_level", "pndf_default_tuning", "pndf_plan_create", "pndf_plan_eval",
             "pndf_plan_get_stats", "pndf_plan_get_tuning", "pndf_plan_destroy", "pndf_autotune"]
@@ -224,6 +225,18 @@ def sample_batch(hier, queries, xi, tau=0.0, sigma_to_r=3.0, kernel=0, tri=True,
                          _dev_ptr(m, torch.float32, "m"), _vp(t.data_ptr()) if tri else None,
                          _vp(uu.data_ptr()) if u else None, _stream(stream)), "pndf_sample_batch")
     return m, t, uu
+
+
+def projected_area(hier, queries, sigma_to_r=3.0, kernel=0, lam=False, stream=None):
+    """P(w) per query (Q, 6): x, y, sx, sy, w_x, w_y.  Returns P (Q,) float32, and
+    Lambda(w) = P / w_z - 1 too if lam."""
+    qp, nq = _queries(queries)
+    P = torch.empty(nq, dtype=torch.float32, device=queries.device)
+    L = torch.empty(nq, dtype=torch.float32, device=queries.device) if lam else None
+    o = _opts(0.0, sigma_to_r, "auto", kernel)
+    _check(_projected_area(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(P, torch.float32, "P"),
+                           _vp(L.data_ptr()) if lam else None, _stream(stream)), "pndf_projected_area")
+    return (P, L) if lam else P
 
 
 def eval_counts(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", stream=None, kernel=0):

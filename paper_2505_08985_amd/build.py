@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libpndf.so")
 
-SOURCES = ["api.cpp", "plan.cpp", "serve.cpp", "mesh.hip", "hier.hip", "eval.hip", "sample.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "serve.cpp", "mesh.hip", "hier.hip", "eval.hip", "sample.hip", "projarea.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

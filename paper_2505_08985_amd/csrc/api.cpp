@@ -327,6 +327,30 @@ pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_sample_batch");
 }
 
+pndf_status pndf_projected_area(const pndf_hier* h, const pndf_query* d_q, int64_t nq, const pndf_eval_opts* opts,
+                                float* d_P, float* d_lambda, void* stream)
+{
+    if (!h) return invalid("hierarchy is NULL");
+    if (nq < 0) return invalid("nq < 0");
+    if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
+    if (nq > 0 && (!d_q || !d_P)) return invalid("query or output pointer is NULL");
+    pndf_eval_opts o{PNDF_KERNEL_GAUSSIAN, 0.f, 3.f, PNDF_ALGO_AUTO, 0};
+    if (opts) {
+        o = *opts;
+        o.algo = PNDF_ALGO_AUTO;  // ignored
+    }
+    if (o.flags != 0) return invalid("the projected area takes no flags");
+    if (o.tau != 0.f) return invalid("the projected area is brute force: tau must be 0");
+    pndf_eval_opts r;
+    pndf_status st = resolve_opts(h, &o, &r);
+    if (st != PNDF_OK) return st;
+    st = check_sticky();
+    if (st != PNDF_OK) return st;
+    ProjArgs a{d_q, nq, r.sigma_to_r, r.kernel, d_P, d_lambda};
+    const hipError_t e = launch_projected_area(h->dev, a, (hipStream_t)stream);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_projected_area");
+}
+
 pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
                             const pndf_eval_opts* opts, float* d_out, void* stream)
 {

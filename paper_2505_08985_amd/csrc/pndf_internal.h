@@ -244,6 +244,17 @@ struct SampleArgs {
 };
 hipError_t launch_sample(const HierDev& H, const SampleArgs& a, hipStream_t s);
 
+// Projected area P(w) per query (projarea.hip).
+struct ProjArgs {
+    const pndf_query* q;       // x, y, sx, sy, and w_x, w_y in place of the query normal
+    int64_t nq;
+    float s2r;
+    int kernel;                // PNDF_KERNEL_*
+    float* P;
+    float* lambda;             // optional: P / w_z - 1
+};
+hipError_t launch_projected_area(const HierDev& H, const ProjArgs& a, hipStream_t s);
+
 // Spatial processing order of a batch: queries bucketed by the Morton code of their
 // centre cell (64 x 64 buckets over the torus), stream-ordered workspace.
 hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s);

@@ -1,0 +1,157 @@
+"""GPU projected area P(w) (pndf_projected_area, through the C ABI) against the
+FP64 oracle: both evaluate the same piecewise-constant-kernel definition in FP64
+(brute force over the included cells), so the float32 output agrees to 1e-5
+relative (plus 1e-9 absolute for values near 0, e.g. surfaces facing away)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
+
+RTOL = 1e-5
+ATOL = 1e-9
+
+
+def announce(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2505_08985_amd as P
+    return P
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def random_disk_map(n, seed, radius=0.5):
+    rng = np.random.default_rng(seed)
+    r = radius * np.sqrt(rng.uniform(size=(n, n)))
+    t = rng.uniform(0, 2 * np.pi, size=(n, n))
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=-1).astype(np.float32)
+
+
+def flat_patch_map(n, seed):
+    nrm = random_disk_map(n, seed, 0.6)
+    for k in range(0, n - 4, 9):
+        nrm[k:k + 4, k:k + 4] = nrm[k, k]
+    return nrm
+
+
+MAPS = {
+    "bumps64": lambda: __import__("workloads").make_map("bumps", 64, 101, count=32),
+    "powerlaw128": lambda: __import__("workloads").make_map("powerlaw", 128, 7),
+    "scratched128": lambda: __import__("workloads").make_map(
+        "scratched", 128, 9, scratches=120, flakes=300),
+    "flatpatch32": lambda: flat_patch_map(32, 4),
+    "steep16": lambda: random_disk_map(16, 8, 0.97),
+}
+
+
+def directions(count, seed):
+    """Uniform on the hemisphere, plus normal incidence and near-grazing ones."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(0, 1, count)
+    z[:8] = 1.0
+    z[8:16] = 1e-3
+    phi = rng.uniform(0, 2 * np.pi, count)
+    r = np.sqrt(1 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi)], axis=1)
+
+
+def queries(n, count, seed, smin, smax):
+    rng = np.random.default_rng(seed)
+    q = np.zeros((count, 6), dtype=np.float32)
+    q[:, 0:2] = rng.uniform(-n, 2 * n, (count, 2))
+    q[:, 2] = np.exp(rng.uniform(np.log(smin), np.log(smax), count))
+    q[:, 3] = q[:, 2] * np.exp(rng.uniform(-0.5, 0.5, count))
+    q[:, 4:6] = directions(count, seed + 1)
+    return q
+
+
+def build(P, nrm):
+    import torch
+    mesh = P.build_mesh(to_dev(nrm))
+    hier = P.build_hierarchy(mesh, cluster=False)
+    torch.cuda.synchronize()
+    return mesh, hier
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "disk", "box"])
+@pytest.mark.parametrize("name", sorted(MAPS))
+def test_projected_area_parity(P, oracle_mod, name, kernel):
+    """Footprints 0.2 to 6 texels (and wider than small maps: periodic images),
+    directions over the hemisphere including normal incidence and grazing."""
+    import torch
+    announce("projected area %s %s" % (name, kernel))
+    nrm = MAPS[name]()
+    n = nrm.shape[0]
+    s2r = 3.0 if kernel == "gaussian" else 1.5
+    q = queries(n, 1001, 51, 0.2, 6.0)
+    _, hier = build(P, nrm)
+    got, lam = P.projected_area(hier, to_dev(q), sigma_to_r=s2r, kernel=kernel, lam=True)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.float64)
+    lam = lam.cpu().numpy().astype(np.float64)
+    ref = oracle_mod.projected_area(nrm, q, sigma_to_r=s2r, kernel=kernel)
+    assert not np.isnan(ref).any() and not np.isnan(got).any()
+    err = np.abs(got - ref)
+    bad = err > RTOL * np.abs(ref) + ATOL
+    assert not bad.any(), "%d queries differ, worst %s" % (bad.sum(), np.argmax(err / (np.abs(ref) + ATOL)))
+    wz = np.sqrt(np.maximum(0.0, 1.0 - (q[:, 4:6].astype(np.float64) ** 2).sum(1)))
+    ok = wz > 1e-2
+    np.testing.assert_allclose(lam[ok], got[ok] / wz[ok] - 1.0, rtol=1e-5, atol=1e-5)
+    assert (ref > 0).sum() > 500
+
+
+def test_projected_area_edge_cases(P, oracle_mod):
+    import torch
+    announce("projected area edge cases")
+    nrm = random_disk_map(16, 5, 0.6)
+    _, hier = build(P, nrm)
+    q = np.array([
+        [3.5, 4.5, 0.01, 0.01, 0.3, 0.2],     # tiny footprint
+        [7.0, 7.0, 30.0, 30.0, 0.1, -0.5],     # several periods wide
+        [-100.25, 700.5, 2.0, 2.0, 0.0, 0.0],  # far outside the base period, w = z
+        [5.0, 5.0, 1.0, 1.0, 1.0, 0.0],        # grazing: w_z = 0
+        [5.0, 5.0, 1.0, 1.0, 0.8, 0.7],        # |w_xy| > 1: invalid
+        [np.nan, 1, 1, 1, 0, 0],               # invalid query
+        [1, 1, 0.0, 1, 0, 0],
+    ], dtype=np.float32)
+    got, lam = P.projected_area(hier, to_dev(q), lam=True)
+    got, lam = got.cpu().numpy(), lam.cpu().numpy()
+    ref = oracle_mod.projected_area(nrm, q)
+    ok = ~np.isnan(ref)
+    assert np.array_equal(np.isnan(got), ~ok)
+    np.testing.assert_allclose(got[ok], ref[ok], rtol=RTOL, atol=ATOL)
+    assert np.isnan(got[4:]).all() and not np.isnan(got[:4]).any()
+    assert math.isinf(lam[3]) and lam[3] > 0
+    # continuity at grazing directions: w_z = 0 against the smallest w_z that
+    # float32 inputs reach (|w_xy| = 1 - 2^-24: w_z = 3.5e-4) and 1 - 2^-20 (1.4e-3)
+    g = []
+    for wl in (1.0, 1.0 - 2.0 ** -24, 1.0 - 2.0 ** -20):
+        qq = np.array([[5.0, 5.0, 1.0, 1.2, 0.0, wl], [9.0, 3.0, 2.0, 0.7, -wl, 0.0]], np.float32)
+        g.append(P.projected_area(hier, to_dev(qq)).cpu().numpy().astype(np.float64))
+        np.testing.assert_allclose(g[-1], oracle_mod.projected_area(nrm, qq), rtol=RTOL, atol=ATOL)
+    assert (g[0] > 0).all()
+    # smooth in w_z: difference quotients from 0 and between the two small values agree
+    wz = [0.0] + [math.sqrt(1.0 - float(np.float32(w)) ** 2) for w in (1.0 - 2.0 ** -24, 1.0 - 2.0 ** -20)]
+    s1 = (g[1] - g[0]) / wz[1]
+    s2 = (g[2] - g[1]) / (wz[2] - wz[1])
+    assert (np.abs(s1 - s2) <= 0.1 * np.abs(s2) + 0.05).all(), (s1, s2)
+    e = torch.zeros((0, 6), device="cuda")
+    assert P.projected_area(hier, e).numel() == 0
+    qd = to_dev(q)
+    with pytest.raises(P.PndfError):
+        P.projected_area(hier, qd, kernel=9)
+    with pytest.raises(P.PndfError):
+        P.projected_area(hier, qd, sigma_to_r=0.0)

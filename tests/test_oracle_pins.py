@@ -878,7 +878,7 @@ def test_projected_triangle_closed_forms(oracle_mod):
     rng = np.random.default_rng(31)
     for _ in range(20):
         tri = rng.uniform(-0.6, 0.6, (3, 2))
-        area = 0.5 * abs(np.cross(tri[1] - tri[0], tri[2] - tri[0]))
+        area = 0.5 * abs((tri[1, 0] - tri[0, 0]) * (tri[2, 1] - tri[0, 1]) - (tri[1, 1] - tri[0, 1]) * (tri[2, 0] - tri[0, 0]))
         assert oracle_mod.tri_projected(tri, np.array([0.0, 0.0, 1.0])) == pytest.approx(area, rel=1e-12)
     back = np.array([[-0.95, -0.1], [-0.85, 0.1], [-0.9, 0.15]])
     assert oracle_mod.tri_projected(back, unit_dir(1.45, 0.0)) == 0.0
@@ -920,7 +920,7 @@ def test_projected_triangle_quadrature(oracle_mod):
         # the midpoint rule converges to first order here (the triangle's edges and
         # the kink of max(., 0) cut grid cells): Richardson-extrapolate two grids
         ref = 2.0 * grid_projected(tri, w, 2400) - grid_projected(tri, w, 1200)
-        area = 0.5 * abs(np.cross(tri[1] - tri[0], tri[2] - tri[0]))
+        area = 0.5 * abs((tri[1, 0] - tri[0, 0]) * (tri[2, 1] - tri[0, 1]) - (tri[1, 1] - tri[0, 1]) * (tri[2, 0] - tri[0, 0]))
         assert abs(got - ref) <= 1.5e-3 * max(ref, 0.05 * area), (k, got, ref)
         mt = np.sqrt(1 - (tri ** 2).sum(1))
         dots = tri @ w[:2] + w[2] * mt
@@ -1035,3 +1035,23 @@ def test_projected_area_flat_map(oracle_mod):
         qq[0, 4:6] = w[:2]
         want = mass * max(float(n0 @ w[:2] + w[2] * nz), 0.0) / nz
         assert oracle_mod.projected_area(nrm, qq)[0] == pytest.approx(want, rel=5e-3, abs=1e-4 * mass)
+
+
+def test_projected_area_continuous_at_grazing(oracle_mod):
+    """At w_z = 0 the semi-ellipse bounding the visible normals degenerates to the
+    segment m_x = 0 (its half-axis along x is w_z); P is continuous there."""
+    nrm = random_disk_map(16, 5, 0.6)
+    for ax, sgn in ((0, 1.0), (1, 1.0), (0, -1.0)):
+        vals = []
+        # |w_xy| = 1, 1 - 2^-24 and 1 - 2^-20 in float32: w_z = 0, 3.5e-4, 1.4e-3
+        for wl in (1.0, 1.0 - 2.0 ** -24, 1.0 - 2.0 ** -20):
+            q = np.array([[5.0, 5.0, 1.0, 1.2, 0.0, 0.0]], np.float32)
+            q[0, 4 + ax] = sgn * wl
+            vals.append(oracle_mod.projected_area(nrm, q)[0])
+        assert vals[0] > 0
+        # P is smooth in w_z: the difference quotients from 0 and between the two
+        # small values agree (a jump at w_z = 0 would break this)
+        wz = [0.0] + [math.sqrt(1.0 - float(np.float32(w)) ** 2) for w in (1.0 - 2.0 ** -24, 1.0 - 2.0 ** -20)]
+        s1 = (vals[1] - vals[0]) / wz[1]
+        s2 = (vals[2] - vals[1]) / (wz[2] - wz[1])
+        assert abs(s1 - s2) <= 0.1 * abs(s2) + 0.05 and abs(s2) < 5.0, (s1, s2)
