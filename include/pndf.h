@@ -283,7 +283,8 @@ typedef struct pndf_plan_stats {
                             * task (bit2); the results of that run are invalid */
 } pndf_plan_stats;
 
-/* Default tuning for a hierarchy (used when pndf_plan_create gets tuning == NULL). */
+/* Default tuning for a hierarchy (used when pndf_plan_create gets tuning == NULL):
+ * as many blocks per compute unit as are resident, split level log2 N - 3. */
 pndf_status pndf_default_tuning(const pndf_hier* h, pndf_tuning* out);
 
 /*

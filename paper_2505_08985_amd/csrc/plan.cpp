@@ -65,8 +65,11 @@ extern "C" {
 pndf_status pndf_default_tuning(const pndf_hier* h, pndf_tuning* out)
 {
     if (!h || !out) return plan_invalid("NULL argument");
-    out->blocks_per_cu = 4;
-    out->split_level = std::min(h->L, 7);
+    // as many worker blocks as fit on a compute unit (reduced to the resident count
+    // when the plan is made), nodes three levels below the root donatable: the best
+    // measured setting on the scratched and power-law maps
+    out->blocks_per_cu = 8;
+    out->split_level = std::max(1, h->L - 3);
     out->queue_factor = 16;
     out->use_graph = 1;
     return PNDF_OK;

@@ -21,7 +21,11 @@
 //
 // Brute force like the paper's implementation: one wavefront per query, lanes over
 // the included cells (two triangles each), FP64 throughout; the lanes' partial
-// sums are reduced in the wave.
+// sums are reduced in the wave.  V lies right of the line m_x = -w_z (the
+// ellipse's leftmost point), so a triangle left of it adds nothing; a triangle
+// with its three vertices in V takes three segment terms at once; only the others
+// need clipping, and they wait in a per-wave LDS queue until 64 of them fill a
+// round with one per lane (a lane's clipping would otherwise stall its wave).
 #include "pndf_internal.h"
 
 namespace pndf {
@@ -38,6 +42,18 @@ __device__ __forceinline__ bool visible(double x, double y, double wz)
     return x * x + y * y <= 1.0 && (x >= 0.0 || x * x + wz * wz * y * y <= wz * wz);
 }
 
+// A(b) - A(a) with one arcsine: asin b - asin a = asin(b sqrt(1 - a^2) - a sqrt(1 - b^2))
+// while the difference of the angles is within [-pi/2, pi/2], i.e. while
+// sqrt(1 - a^2) sqrt(1 - b^2) + a b >= 0; else two
+__device__ __forceinline__ double arc_prim_diff(double a, double b)
+{
+    a = fmin(1.0, fmax(-1.0, a));
+    b = fmin(1.0, fmax(-1.0, b));
+    const double ca = sqrt(fmax(0.0, 1.0 - a * a)), cb = sqrt(fmax(0.0, 1.0 - b * b));
+    const double d = ca * cb + a * b >= 0.0 ? asin(fmin(1.0, fmax(-1.0, b * ca - a * cb))) : asin(b) - asin(a);
+    return 0.5 * (d + b * cb - a * ca);
+}
+
 // F dm_y along the segment P -> Q
 __device__ inline double segment_int(double px, double py, double qx, double qy, double wl, double wz)
 {
@@ -51,7 +67,7 @@ __device__ inline double segment_int(double px, double py, double qx, double qy,
     const double rho2 = 1.0 - s * s;
     if (rho2 <= 0.0) return lin;
     const double rho = sqrt(rho2);
-    return lin - wl * dy * rho2 * (arc_prim((dx * qx + dy * qy) / rho) - arc_prim((dx * px + dy * py) / rho));
+    return lin - wl * dy * rho2 * arc_prim_diff((dx * px + dy * py) / rho, (dx * qx + dy * qy) / rho);
 }
 
 // place of a point of V's boundary on its counter-clockwise loop from (0, -1):
@@ -81,16 +97,24 @@ __device__ inline double boundary_int(double a, double b, double wz)
     return sum;
 }
 
+__device__ __forceinline__ void cswap(double& a, double& b)
+{
+    const double lo = fmin(a, b), hi = fmax(a, b);
+    a = lo;
+    b = hi;
+}
+
 // parameter interval [t0, t1] of the segment P + t D (t in [0, 1]) inside V;
-// false if empty
+// false if empty.  The candidates: the ends, every meeting with the unit circle or
+// the whole ellipse x^2 + wz^2 y^2 = wz^2 (V's boundary crossings are among them,
+// the others only split the segment), and the line x = 0, the ellipse's limit as
+// wz -> 0 (its discriminant is then a difference of equal products and may round
+// below 0).  Unused slots repeat t = 1.  Sorted by a fixed network (registers
+// only); V convex: the visible pieces between consecutive candidates form one
+// interval.
 __device__ inline bool clip_edge(double px, double py, double dx, double dy, double wz, double* t0, double* t1)
 {
-    double ts[7];
-    int nt = 0;
-    ts[nt++] = 0.0;
-    ts[nt++] = 1.0;
-    // every meeting with the unit circle or the whole ellipse x^2 + wz^2 y^2 = wz^2:
-    // V's boundary crossings are among them, the others only split the segment
+    double ts[7] = {0.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
 #pragma unroll
     for (int curve = 0; curve < 2; ++curve) {
         const double ey = curve == 0 ? 1.0 : wz * wz, rhs = curve == 0 ? 1.0 : wz * wz;
@@ -100,28 +124,25 @@ __device__ inline bool clip_edge(double px, double py, double dx, double dy, dou
         const double disc = qb * qb - 4.0 * qa * qc;
         if (qa > 0.0 && disc >= 0.0) {
             const double sq = sqrt(disc);
-#pragma unroll
-            for (int sgn = -1; sgn <= 1; sgn += 2) {
-                const double t = (-qb + sgn * sq) / (2.0 * qa);
-                if (t > 0.0 && t < 1.0) ts[nt++] = t;
-            }
+            const double ra = (-qb - sq) / (2.0 * qa), rb = (-qb + sq) / (2.0 * qa);
+            ts[2 + 2 * curve] = (ra > 0.0 && ra < 1.0) ? ra : 1.0;
+            ts[3 + 2 * curve] = (rb > 0.0 && rb < 1.0) ? rb : 1.0;
         }
     }
-    // the line x = 0, the ellipse's limit as wz -> 0 (its discriminant is then a
-    // difference of equal products and may round below 0)
     if (dx != 0.0) {
         const double t = -px / dx;
-        if (t > 0.0 && t < 1.0) ts[nt++] = t;
+        ts[6] = (t > 0.0 && t < 1.0) ? t : 1.0;
     }
-    // sort (at most 7 values)
-    for (int i = 1; i < nt; ++i)
-        for (int j = i; j > 0 && ts[j] < ts[j - 1]; --j) {
-            const double tmp = ts[j];
-            ts[j] = ts[j - 1];
-            ts[j - 1] = tmp;
-        }
+    // sorting network for 7 values
+    cswap(ts[0], ts[6]); cswap(ts[2], ts[3]); cswap(ts[4], ts[5]);
+    cswap(ts[0], ts[2]); cswap(ts[1], ts[4]); cswap(ts[3], ts[6]);
+    cswap(ts[0], ts[1]); cswap(ts[2], ts[5]); cswap(ts[3], ts[4]);
+    cswap(ts[1], ts[2]); cswap(ts[4], ts[6]);
+    cswap(ts[2], ts[3]); cswap(ts[4], ts[5]);
+    cswap(ts[1], ts[2]); cswap(ts[3], ts[4]); cswap(ts[5], ts[6]);
     double lo = 2.0, hi = -1.0;
-    for (int i = 0; i + 1 < nt; ++i) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
         if (!(ts[i + 1] > ts[i])) continue;
         const double tm = 0.5 * (ts[i] + ts[i + 1]);
         if (visible(px + tm * dx, py + tm * dy, wz)) {
@@ -134,18 +155,20 @@ __device__ inline bool clip_edge(double px, double py, double dx, double dy, dou
     return hi > lo;
 }
 
-// integral of (w_l m_x / m~_z + w_z) over (triangle v, canonical frame) within V
-__device__ inline double triangle_int(double v[6], double wl, double wz)
+// counter-clockwise vertex order
+__device__ __forceinline__ void orient_ccw(double v[6])
 {
-    // counter-clockwise
     const double a2 = (v[2] - v[0]) * (v[5] - v[1]) - (v[3] - v[1]) * (v[4] - v[0]);
     if (a2 < 0.0) {
         double t = v[2]; v[2] = v[4]; v[4] = t;
         t = v[3]; v[3] = v[5]; v[5] = t;
     }
-    if (visible(v[0], v[1], wz) && visible(v[2], v[3], wz) && visible(v[4], v[5], wz))
-        return segment_int(v[0], v[1], v[2], v[3], wl, wz) + segment_int(v[2], v[3], v[4], v[5], wl, wz) +
-               segment_int(v[4], v[5], v[0], v[1], wl, wz);
+}
+
+// integral of (w_l m_x / m~_z + w_z) over (triangle v, canonical frame,
+// counter-clockwise) within V, by clipping
+__device__ inline double triangle_int_clipped(const double v[6], double wl, double wz)
+{
     double ex[3], ey[3], xx[3], xy[3];  // entry and exit point of each edge
     bool in[3];
     bool any = false;
@@ -187,19 +210,42 @@ __device__ inline double triangle_int(double v[6], double wl, double wz)
     return sum;
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v)
+// A triangle of cell (i, j) and its weight k / J: normals in the canonical frame.
+__device__ __forceinline__ void cell_triangle(const HierDev& H, int i, int j, int half, double c, double sn,
+                                              double r[6])
 {
+    const int wdt = H.n + 1;
+    const float2* p = H.nrm + (int64_t)j * wdt + i;
+    const float2 n1 = p[1], n2 = p[wdt];
+    const float2 nc = half ? p[wdt + 1] : p[0];
+    double v[6];
+    if ((H.deg[(int64_t)j * H.n + i] >> half) & 1u) {
+        eqtri_f64(0.5 * ((double)n1.x + (double)n2.x), 0.5 * ((double)n1.y + (double)n2.y), (double)H.rho, v);
+    } else if (half == 0) {
+        v[0] = nc.x; v[1] = nc.y; v[2] = n1.x; v[3] = n1.y; v[4] = n2.x; v[5] = n2.y;
+    } else {
+        v[0] = nc.x; v[1] = nc.y; v[2] = n2.x; v[3] = n2.y; v[4] = n1.x; v[5] = n1.y;
+    }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int k = 0; k < 3; ++k) {
+        r[2 * k] = c * v[2 * k] + sn * v[2 * k + 1];
+        r[2 * k + 1] = -sn * v[2 * k] + c * v[2 * k + 1];
+    }
+    orient_ccw(r);
 }
 
+constexpr int kClipCap = 256;  // queued triangles per wave (a step adds at most 128)
+
 template <int KER>
-__global__ __launch_bounds__(256) void k_projected_area(HierDev H, ProjArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_projected_area(HierDev H, ProjArgs a)
 {
+    __shared__ uint32_t clip_cell_all[4 * kClipCap];
+    __shared__ double clip_w_all[4 * kClipCap];
     const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (qi >= a.nq) return;
     const int lane = threadIdx.x & 63;
+    uint32_t* clip_cell = clip_cell_all + (threadIdx.x >> 6) * kClipCap;
+    double* clip_w = clip_w_all + (threadIdx.x >> 6) * kClipCap;
     const pndf_query qr = a.q[qi];
     const QuerySetup q = uniform_query(setup_query(qr, a.s2r, 0.f, H.L, H.eps, KER));
     const double wx = qr.hx, wy = qr.hy;
@@ -218,37 +264,60 @@ __global__ __launch_bounds__(256) void k_projected_area(HierDev H, ProjArgs a)
     const int nx = spanx >= n ? n : spanx, ny = spany >= n ? n : spany;
     const int total = nx * ny;
     double acc = 0.0;
-    for (int idx = lane; idx < total; idx += 64) {
-        const int ca = idx % nx, cb = idx / nx;
-        const int i = spanx >= n ? ca : ((q.cxlo + ca) & msk);
-        const int j = spany >= n ? cb : ((q.cylo + cb) & msk);
-        const int wdt = n + 1;
-        const float2* p = H.nrm + (int64_t)j * wdt + i;
-        const float2 n0 = p[0], n1 = p[1], n2 = p[wdt], n3 = p[wdt + 1];
-        const uint8_t dg = H.deg[(int64_t)j * n + i];
-        const float2 dd = H.det[(int64_t)j * n + i];
+    int qn = 0;  // queued triangles (wave-uniform)
+    for (int base = 0; base < total || qn > 0; base += 64) {
+        uint32_t clip = 0;          // bit h: this lane's triangle h needs clipping
+        double kw[2] = {0.0, 0.0};
+        uint32_t cell = 0;
+        const int idx = base + lane;
+        if (idx < total) {
+            const int ca = idx % nx, cb = idx / nx;
+            const int i = spanx >= n ? ca : ((q.cxlo + ca) & msk);
+            const int j = spany >= n ? cb : ((q.cylo + cb) & msk);
+            cell = (uint32_t)i | ((uint32_t)j << 13);
+            const float2 dd = H.det[(int64_t)j * n + i];
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            const double J = (double)(half ? dd.y : dd.x);
-            // kernel at the uv centroid over the included images, divided by J
-            const double kj = hit_term<KER>(q, i, j, 0, half, 1.0 / 3.0, 1.0 / 3.0, (float)J, H.logn);
-            if (kj == 0.0) continue;
-            double v[6];
-            if ((dg >> half) & 1u) {
-                eqtri_f64(0.5 * ((double)n1.x + (double)n2.x), 0.5 * ((double)n1.y + (double)n2.y),
-                          (double)H.rho, v);
-            } else if (half == 0) {
-                v[0] = n0.x; v[1] = n0.y; v[2] = n1.x; v[3] = n1.y; v[4] = n2.x; v[5] = n2.y;
-            } else {
-                v[0] = n3.x; v[1] = n3.y; v[2] = n2.x; v[3] = n2.y; v[4] = n1.x; v[5] = n1.y;
+            for (int half = 0; half < 2; ++half) {
+                // kernel at the uv centroid over the included images, divided by J
+                const double kj = hit_term<KER>(q, i, j, 0, half, 1.0 / 3.0, 1.0 / 3.0, half ? dd.y : dd.x, H.logn);
+                if (kj == 0.0) continue;
+                double r[6];
+                cell_triangle(H, i, j, half, c, sn, r);
+                if (r[0] < -wz && r[2] < -wz && r[4] < -wz) continue;  // left of V
+                if (visible(r[0], r[1], wz) && visible(r[2], r[3], wz) && visible(r[4], r[5], wz)) {
+                    acc += kj * (segment_int(r[0], r[1], r[2], r[3], wl, wz) +
+                                 segment_int(r[2], r[3], r[4], r[5], wl, wz) +
+                                 segment_int(r[4], r[5], r[0], r[1], wl, wz));
+                } else {
+                    clip |= 1u << half;
+                    kw[half] = kj;
+                }
             }
-            double r[6];
+        }
+        // queue the triangles that need clipping (lane order)
+        int tot;
+        const int pos = wave_prefix_small(__popc(clip), &tot);
+        int at = qn + pos;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                r[2 * k] = c * v[2 * k] + sn * v[2 * k + 1];
-                r[2 * k + 1] = -sn * v[2 * k] + c * v[2 * k + 1];
+        for (int half = 0; half < 2; ++half)
+            if (clip & (1u << half)) {
+                clip_cell[at] = cell | ((uint32_t)half << 26);
+                clip_w[at] = kw[half];
+                ++at;
             }
-            acc += kj * triangle_int(r, wl, wz);
+        qn += tot;
+        wave_sync();
+        // full rounds, and at the end whatever is left
+        while (qn >= 64 || (qn > 0 && base + 64 >= total)) {
+            const int cnt = min(qn, 64);
+            qn -= cnt;
+            if (lane < cnt) {
+                const uint32_t e = clip_cell[qn + lane];
+                double r[6];
+                cell_triangle(H, (int)(e & 0x1fffu), (int)((e >> 13) & 0x1fffu), (int)(e >> 26), c, sn, r);
+                acc += clip_w[qn + lane] * triangle_int_clipped(r, wl, wz);
+            }
+            wave_sync();
         }
     }
     const double P = wave_sum_f64(acc);
