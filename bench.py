@@ -390,8 +390,11 @@ def main():
     ap.add_argument("--input-order", action="store_true", help="keep the query order (no spatial ordering)")
     ap.add_argument("--tuning", default=None, metavar="BPC,SPLIT",
                     help="persistent tuning (blocks per CU, split level) instead of autotuning")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the persistent plan (default: the plan's default tuning)")
     ap.add_argument("--autotune-queries", type=int, default=1 << 14,
-                    help="size of the autotuning sample (a prefix of the batch)")
+                    help="size of the autotuning sample (a prefix of the batch); a sample much smaller "
+                         "than the batch is dominated by its slowest queries and favours fewer workers")
     ap.add_argument("--kernel", default="gaussian", choices=["gaussian", "disk", "box"],
                     help="footprint kernel")
     ap.add_argument("--sigma-to-r", type=float, default=None,
@@ -470,14 +473,15 @@ def main():
         if args.tuning:
             bpc, split = (int(v) for v in args.tuning.split(","))
             tuning = dict(blocks_per_cu=bpc, split_level=split, queue_factor=16, use_graph=1)
-        else:
+        elif args.autotune:
             sample = tq[:min(count, args.autotune_queries)]
             print("[bench] autotuning on %d queries ..." % sample.shape[0], file=sys.stderr, flush=True)
             tuning, tms = P.autotune(hier, sample, tau=tau, **kw)
             print("[bench] autotuned %s (%.3f ms on %d queries)" % (tuning, tms, sample.shape[0]),
                   file=sys.stderr, flush=True)
         plan = P.Plan(hier, count, tau=tau, tuning=tuning, **kw)
-        print("[bench] plan tuning %s" % plan.tuning(), file=sys.stderr, flush=True)
+        tuning = plan.tuning()
+        print("[bench] plan tuning %s" % tuning, file=sys.stderr, flush=True)
 
         def step():
             plan.eval(tq, out=out)

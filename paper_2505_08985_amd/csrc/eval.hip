@@ -678,10 +678,16 @@ __global__ void k_persist_reset(QueueCtl* ctl, Fix192* acc, int* fexp, const pnd
     }
 }
 
-// Queries taken by one worker at a time: a few while the batch is long (fewer
-// counter updates), one at a time for its last part, so no wave ends up holding
-// several large footprints in a row.
-constexpr int kMaxChunk = 4;
+// Queries taken by one worker per claim: an eighth of the share's remaining queries
+// per worker of the XCD, at most kMaxChunk, down to single queries for the share's
+// last part (so that no wave ends up holding several large footprints at the end).
+// Every claim is an atomic on the share's counter, which all the XCD's workers
+// hit: at one claim per few cheap queries its line serialised them (powerlaw2048
+// took 18.2 ms with at most 4 queries per claim, 13.6 ms with up to 32; claims
+// sized by the time of the previous chunk, or without reading the counter first,
+// were slower on the scratched map's heavy tail).
+constexpr int kMaxChunk = 32;
+constexpr int kChunkDiv = 8;
 
 __device__ __forceinline__ unsigned long long ld_relaxed(const unsigned long long* p)
 {
@@ -761,7 +767,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                         const long long lo = nq * x / kXcds, len = nq * (x + 1) / kXcds - lo;
                         const long long qh = (long long)ld_relaxed(&ctl->qhead[x].v);
                         if (qh >= len) continue;
-                        const long long c = max(1ll, min((long long)kMaxChunk, (len - qh) / (64 * xworkers)));
+                        const long long c =
+                            max(1ll, min((long long)kMaxChunk, (len - qh) / (kChunkDiv * xworkers)));
                         const long long qn = (long long)__hip_atomic_fetch_add(
                             &ctl->qhead[x].v, (unsigned long long)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (qn < len) {
