@@ -189,7 +189,7 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
  * triangle when that triangle is clamped.  The density of m is D(m) over D's
  * total mass, for each kernel and tau.
  *
- *  d_xi       device, attempts x nq pairs of uniforms in [0, 1), attempt-major:
+ *  d_xi       device, 16-byte aligned, attempts x nq pairs of uniforms in [0, 1), attempt-major:
  *             pair t of query k at d_xi[2 (t nq + k)], d_xi[2 (t nq + k) + 1].
  *             The caller draws them (any generator).  The Gaussian footprint is
  *             drawn by inverse CDF per axis; with tau > 0 a draw whose cut unit
@@ -200,12 +200,12 @@ pndf_status pndf_eval_hits(const pndf_hier* h, const pndf_query* d_q, int64_t nq
  *  attempts   >= 1 pairs per query.
  *  opts       kernel, tau, sigma_to_r as for pndf_eval_batch (algo ignored,
  *             flags must be 0); tau > 0 needs clusters.
- *  d_m        device, nq float2: the sampled normal; NaN when the query is
+ *  d_m        device, 8-byte aligned, nq float2: the sampled normal; NaN when the query is
  *             invalid (as for the evaluation), a used pair lies outside [0, 1),
  *             or every attempt was rejected.
  *  d_tri      device, nq triangle ids (same encoding as pndf_eval_hits), ~0 when
  *             m is NaN; may be NULL.
- *  d_u        device, nq double2: the drawn texture coordinates (unrolled, not
+ *  d_u        device, 16-byte aligned, nq double2: the drawn texture coordinates (unrolled, not
  *             wrapped onto the torus; the last draw when all were rejected); may
  *             be NULL.
  * Asynchronous on `stream`; deterministic.

@@ -310,6 +310,10 @@ pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t
     if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
     if (attempts < 1 || attempts > 64) return invalid("attempts must be in [1, 64]");
     if (nq > 0 && (!d_q || !d_xi || !d_m)) return invalid("query, uniform or output pointer is NULL");
+    // (the kernel reads the uniforms as pairs of doubles and writes m, u as pairs)
+    if (((uintptr_t)d_xi & 15u) || ((uintptr_t)d_m & 7u) || ((uintptr_t)d_u & 15u) || ((uintptr_t)d_tri & 7u) ||
+        ((uintptr_t)d_q & 3u))
+        return invalid("misaligned pointer (uniforms and u: 16 B, m and tri: 8 B, queries: 4 B)");
     pndf_eval_opts o{PNDF_KERNEL_GAUSSIAN, 0.f, 3.f, PNDF_ALGO_AUTO, 0};
     if (opts) {
         o = *opts;

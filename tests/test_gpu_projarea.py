@@ -155,3 +155,29 @@ def test_projected_area_edge_cases(P, oracle_mod):
         P.projected_area(hier, qd, kernel=9)
     with pytest.raises(P.PndfError):
         P.projected_area(hier, qd, sigma_to_r=0.0)
+
+
+def test_projected_area_full_size_sampled(P, oracle_mod):
+    """The bench launch: 2^16 queries on the 2048^2 power-law map (sigma in [1, 8],
+    directions uniform on the hemisphere), checked against the oracle on 512 of
+    them."""
+    import torch
+    import workloads
+    announce("projected area full size powerlaw2048 2^16")
+    cfg = workloads.CONFIGS["powerlaw2048"]
+    mc, qc = cfg["map"], cfg["queries"]
+    n = mc["n"]
+    count = 1 << 16
+    nrm = workloads.make_map(**mc)
+    q = workloads.uniform_queries(n, count, qc["seed"], (1.0, 8.0), qc["radius"])
+    q[:, 4:6] = directions(count, 77).astype(np.float32)
+    over = (q[:, 4].astype(np.float64) ** 2 + q[:, 5].astype(np.float64) ** 2) > 1.0
+    q[over, 4:6] *= np.float32(1.0 - 2.0 ** -22)
+    _, hier = build(P, nrm)
+    for kernel in ("gaussian", "box"):
+        s2r = 3.0 if kernel == "gaussian" else 1.5
+        got = P.projected_area(hier, to_dev(q), sigma_to_r=s2r, kernel=kernel).cpu().numpy().astype(np.float64)
+        pick = np.sort(np.random.default_rng(10).choice(count, 512, replace=False))
+        ref = oracle_mod.projected_area(nrm, q[pick], sigma_to_r=s2r, kernel=kernel)
+        np.testing.assert_allclose(got[pick], ref, rtol=RTOL, atol=ATOL)
+        assert np.isfinite(got).all() and (got >= 0).all()

@@ -179,6 +179,10 @@ def test_sample_edge_cases(P, oracle_mod):
     _, hier0 = build(P, nrm, cluster=False)
     with pytest.raises(P.PndfError):
         P.sample_batch(hier0, qd, xd, tau=1e-3)
+    # uniforms not 16-byte aligned (one double into an allocation)
+    base = torch.zeros(2 * len(q) + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PndfError):
+        P.sample_batch(hier, qd, base[1:].view(1, len(q), 2))
 
 
 @pytest.mark.parametrize("kernel,tau", [("gaussian", 0.0), ("gaussian", 1e-2), ("disk", 1e-2), ("box", 0.0)])
@@ -223,3 +227,37 @@ def test_sample_histogram_matches_gpu_evaluation(P, kernel, tau):
     print("bins %d, median rel %.4f, max rel %.4f" % (big.sum(), np.median(rel), rel.max()))
     assert np.median(rel) < 0.02
     assert rel.max() < 0.08
+
+
+def test_sample_full_size_sampled(P, oracle_mod):
+    """The bench launch: 2^24 samples on the 2048^2 power-law map (sigma in [1, 64],
+    tau = 0 and 1e-3), checked against the oracle on 4096 samples drawn from the
+    launch's output."""
+    import torch
+    import workloads
+    announce("sample full size powerlaw2048 2^24")
+    cfg = workloads.CONFIGS["powerlaw2048"]
+    mc, qc = cfg["map"], cfg["queries"]
+    n = mc["n"]
+    count = 1 << 24
+    nrm = workloads.make_map(**mc)
+    q = workloads.uniform_queries(n, count, qc["seed"], qc["sigma"], qc["radius"])
+    _, hier = build(P, nrm, cluster=True)
+    tq = to_dev(q)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    xi = torch.rand((2, count, 2), dtype=torch.float64, device="cuda", generator=g)
+    pick = np.sort(np.random.default_rng(9).choice(count, 4096, replace=False))
+    for tau in (0.0, 1e-3):
+        m, tri, u = P.sample_batch(hier, tq, xi, tau=tau, u=True)
+        torch.cuda.synchronize()
+        sel = torch.from_numpy(pick).cuda()
+        ms, ts, us = m[sel].cpu().numpy(), tri[sel].cpu().numpy(), u[sel].cpu().numpy()
+        xs = xi[:, sel, :].cpu().numpy()
+        clusters = oracle_mod.cluster_all(nrm) if tau > 0 else None
+        ref = oracle_mod.sample(nrm, q[pick], oracle_xi(xs), tau=tau, clusters=clusters)
+        st = compare(ref, ms, ts, us)
+        print(tau, st)
+        assert st["flagged"] <= 0.02 * len(pick)
+        if tau > 0:
+            assert st["clusters"] > 500
