@@ -171,17 +171,21 @@ __device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const Query
         y0 = axis_overlap(2 * J, 1, q.cylo, q.cyhi, logn);
         y1 = axis_overlap(2 * J + 1, 1, q.cylo, q.cyhi, logn);
     }
+    // every cell is tested (the wave runs each cell's test whenever one lane needs
+    // it anyway) and the cells outside the support are masked afterwards
+    const uint32_t ov = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) | ((uint32_t)(x0 && y1) << 2) |
+                        ((uint32_t)(x1 && y1) << 3);
+    acc.cells += (uint32_t)__popc(ov);
     uint32_t mask = 0;
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
         const int di = c4 & 1, dj = c4 >> 1;
-        if (!((di ? x1 : x0) && (dj ? y1 : y0))) continue;
-        acc.cells += 1;
         mask |= cell_mask(q, H.rho, t[3 * dj + di], t[3 * dj + di + 1], t[3 * dj + di + 3], t[3 * dj + di + 4],
                           (dg4 >> (8 * c4)) & 0xffu)
                 << (2 * c4);
     }
-    return mask;
+    const uint32_t ov2 = (ov & 1u) * 3u | ((ov >> 1) & 1u) * 12u | ((ov >> 2) & 1u) * 48u | ((ov >> 3) & 1u) * 192u;
+    return mask & ov2;
 }
 
 // The two cluster triangles of node idx (level lev): bit half.
@@ -443,36 +447,30 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 pend = leaf_quad_mask(H, q, m, inside, acc);
                 ebase = m << 3;
             } else {
+                // the four child boxes are one 64-byte Morton segment: loaded whole (no
+                // extra traffic), children outside the support masked afterwards
                 const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
-                float4 b0, b1, b2, b3;
+                const float4 b0 = cb[0], b1 = cb[1], b2 = cb[2], b3 = cb[3];
+                uint32_t ov = 0xfu;  // children meeting the support box
                 cin = 0xfu;
-                if (inside) {
-                    // the node lies inside the box, so do all its descendants
-                    b0 = cb[0]; b1 = cb[1]; b2 = cb[2]; b3 = cb[3];
-                    tested = 4;
-                } else {
+                if (!inside) {
                     const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
                     const int side = 1 << (l - 1);
                     const int sx0 = 2 * I * side, sx1 = sx0 + side, sy0 = 2 * J * side, sy1 = sy0 + side;
-                    const bool x0 = axis_overlap(sx0, side, q.cxlo, q.cxhi, logn);
-                    const bool x1 = axis_overlap(sx1, side, q.cxlo, q.cxhi, logn);
-                    const bool y0 = axis_overlap(sy0, side, q.cylo, q.cyhi, logn);
-                    const bool y1 = axis_overlap(sy1, side, q.cylo, q.cyhi, logn);
-                    b0 = b1 = b2 = b3 = make_float4(1.f, 1.f, -1.f, -1.f);
-                    if (x0 && y0) b0 = cb[0];
-                    if (x1 && y0) b1 = cb[1];
-                    if (x0 && y1) b2 = cb[2];
-                    if (x1 && y1) b3 = cb[3];
-                    tested = (uint32_t)((x0 && y0) + (x1 && y0) + (x0 && y1) + (x1 && y1));
-                    const bool fx0 = axis_inside(sx0, side, q.cxlo, q.cxhi, logn);
-                    const bool fx1 = axis_inside(sx1, side, q.cxlo, q.cxhi, logn);
-                    const bool fy0 = axis_inside(sy0, side, q.cylo, q.cyhi, logn);
-                    const bool fy1 = axis_inside(sy1, side, q.cylo, q.cyhi, logn);
-                    cin = (uint32_t)(fx0 && fy0) | ((uint32_t)(fx1 && fy0) << 1) | ((uint32_t)(fx0 && fy1) << 2) |
-                          ((uint32_t)(fx1 && fy1) << 3);
+                    const uint32_t x0 = axis_overlap(sx0, side, q.cxlo, q.cxhi, logn);
+                    const uint32_t x1 = axis_overlap(sx1, side, q.cxlo, q.cxhi, logn);
+                    const uint32_t y0 = axis_overlap(sy0, side, q.cylo, q.cyhi, logn);
+                    const uint32_t y1 = axis_overlap(sy1, side, q.cylo, q.cyhi, logn);
+                    ov = (x0 & y0) | ((x1 & y0) << 1) | ((x0 & y1) << 2) | ((x1 & y1) << 3);
+                    const uint32_t fx0 = axis_inside(sx0, side, q.cxlo, q.cxhi, logn);
+                    const uint32_t fx1 = axis_inside(sx1, side, q.cxlo, q.cxhi, logn);
+                    const uint32_t fy0 = axis_inside(sy0, side, q.cylo, q.cyhi, logn);
+                    const uint32_t fy1 = axis_inside(sy1, side, q.cylo, q.cyhi, logn);
+                    cin = (fx0 & fy0) | ((fx1 & fy0) << 1) | ((fx0 & fy1) << 2) | ((fx1 & fy1) << 3);
                 }
-                chm = (uint32_t)in_box(q, b0) | ((uint32_t)in_box(q, b1) << 1) | ((uint32_t)in_box(q, b2) << 2) |
-                      ((uint32_t)in_box(q, b3) << 3);
+                tested = (uint32_t)__popc(ov);
+                chm = ((uint32_t)in_box(q, b0) | ((uint32_t)in_box(q, b1) << 1) | ((uint32_t)in_box(q, b2) << 2) |
+                       ((uint32_t)in_box(q, b3) << 3)) & ov;
                 m4 = 4 * m;
             }
         }
