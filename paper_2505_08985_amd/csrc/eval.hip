@@ -114,31 +114,44 @@ constexpr uint32_t kHitPlane = 1u << 30, kHitCluster = 2u << 30;
 // spatial tests.
 constexpr uint32_t kInside = 1u << 31;
 
+// Inclusive same-sign test of a triangle's three edge values: h inside or on it.
+__device__ __forceinline__ uint32_t same_sign3(float a, float b, float c)
+{
+    return (uint32_t)(fminf(fminf(a, b), c) >= 0.f) | (uint32_t)(fmaxf(fmaxf(a, b), c) <= 0.f);
+}
+
+// A clamped half is replaced by its equilateral triangle (Eq. debias), the same for
+// both halves of a cell (centred on the shared diagonal's midpoint): set the bits
+// of the clamped halves (dg) of a cell's 2-bit mask from that triangle's test.
+__device__ __forceinline__ uint32_t patch_clamped(const QuerySetup& q, float rho, float2 n1, float2 n2,
+                                                  uint32_t dg, uint32_t m2)
+{
+    float v[6];
+    eqtri_f32(0.5f * (n1.x + n2.x), 0.5f * (n1.y + n2.y), rho, v);
+    const uint32_t e = (uint32_t)tri_hit_f32(v, q.hx, q.hy);
+    if (dg & 1u) m2 = (m2 & ~1u) | e;
+    if (dg & 2u) m2 = (m2 & ~2u) | (e << 1);
+    return m2;
+}
+
 // The two triangles of a cell from its four corner normals and clamp bits: bit 0
-// lower (n0, n1, n2), bit 1 upper (n3, n2, n1).
+// lower (n0, n1, n2), bit 1 upper (n3, n2, n1).  Every edge value is computed in
+// one canonical direction (bottom and top edges left to right, left and right
+// edges upwards, the diagonal from n1 to n2) and only its sign is flipped where a
+// triangle runs along it the other way, so a cell tested alone and the same cell
+// tested within its 2 x 2 block (which shares edges between cells) decide alike.
 __device__ __forceinline__ uint32_t cell_mask(const QuerySetup& q, float rho, float2 n0, float2 n1, float2 n2,
                                               float2 n3, uint32_t dg)
 {
-    if (dg == 0) {
-        // shared offsets and edge functions of the two triangles (they share n1-n2)
-        const float q0x = n0.x - q.hx, q0y = n0.y - q.hy, q1x = n1.x - q.hx, q1y = n1.y - q.hy;
-        const float q2x = n2.x - q.hx, q2y = n2.y - q.hy, q3x = n3.x - q.hx, q3y = n3.y - q.hy;
-        const float c12 = cross2(q1x, q1y, q2x, q2y);
-        const float c20 = cross2(q2x, q2y, q0x, q0y);
-        const float c01 = cross2(q0x, q0y, q1x, q1y);
-        const float c13 = cross2(q1x, q1y, q3x, q3y);
-        const float c32 = cross2(q3x, q3y, q2x, q2y);
-        const bool hl = (c12 >= 0.f && c20 >= 0.f && c01 >= 0.f) || (c12 <= 0.f && c20 <= 0.f && c01 <= 0.f);
-        const bool hu = (c12 <= 0.f && c13 >= 0.f && c32 >= 0.f) || (c12 >= 0.f && c13 <= 0.f && c32 <= 0.f);
-        return (uint32_t)hl | ((uint32_t)hu << 1);
-    }
-    float vl[6], vu[6];
-    const float cx = 0.5f * (n1.x + n2.x), cy = 0.5f * (n1.y + n2.y);
-    if (dg & 1) eqtri_f32(cx, cy, rho, vl);
-    else { vl[0] = n0.x; vl[1] = n0.y; vl[2] = n1.x; vl[3] = n1.y; vl[4] = n2.x; vl[5] = n2.y; }
-    if (dg & 2) eqtri_f32(cx, cy, rho, vu);
-    else { vu[0] = n3.x; vu[1] = n3.y; vu[2] = n2.x; vu[3] = n2.y; vu[4] = n1.x; vu[5] = n1.y; }
-    return (uint32_t)tri_hit_f32(vl, q.hx, q.hy) | ((uint32_t)tri_hit_f32(vu, q.hx, q.hy) << 1);
+    const float q0x = n0.x - q.hx, q0y = n0.y - q.hy, q1x = n1.x - q.hx, q1y = n1.y - q.hy;
+    const float q2x = n2.x - q.hx, q2y = n2.y - q.hy, q3x = n3.x - q.hx, q3y = n3.y - q.hy;
+    const float h01 = cross2(q0x, q0y, q1x, q1y), h23 = cross2(q2x, q2y, q3x, q3y);
+    const float v02 = cross2(q0x, q0y, q2x, q2y), v13 = cross2(q1x, q1y, q3x, q3y);
+    const float d12 = cross2(q1x, q1y, q2x, q2y);
+    // lower: (d12, -v02, h01); upper: (-d12, v13, -h23), negated as a whole
+    uint32_t m = same_sign3(d12, -v02, h01) | (same_sign3(d12, -v13, h23) << 1);
+    if (dg & 3u) m = patch_clamped(q, rho, n1, n2, dg, m);
+    return m;
 }
 
 // A texel cell tested from the padded normal plane (brute force, tiny footprints).
@@ -151,38 +164,109 @@ __device__ __forceinline__ uint32_t plane_cell_mask(const HierDev& H, const Quer
     return cell_mask(q, H.rho, p[0], p[1], p[w], p[w + 1], H.deg[(int64_t)j * H.n + i]);
 }
 
+// Along one axis, the level-c node columns (side 2^c; M = N >> c of them on the
+// torus) that meet the unrolled cell range [clo, chi] form one cyclic run of n
+// columns starting at a, and those with an image wholly inside the range a run of
+// ni starting at ai (n or ni = M: every column).  Column X belongs to a run iff
+// ((X - a) mod M) < n.  The runs depend only on the query and the level
+// (wave-uniform), so each node's spatial tests are a subtraction, a mask and a
+// compare per axis and child.
+struct AxisRuns {
+    int a, n, ai, ni;
+};
+
+__device__ __forceinline__ AxisRuns axis_runs(int clo, int chi, int c, int M)
+{
+    AxisRuns r;
+    r.a = clo >> c;
+    r.n = min((chi >> c) - r.a + 1, M);
+    r.ai = -((-clo) >> c);
+    r.ni = max(0, min(((chi + 1) >> c) - r.ai, M));
+    return r;
+}
+
+// Bits 0 / 1: the columns 2X and 2X + 1 of the level below X (mask mk = M - 1
+// there) in the run (a, n).
+__device__ __forceinline__ uint32_t pair_in_run(int X, int a, int n, int mk)
+{
+    const int d = 2 * X - a;
+    return (uint32_t)((d & mk) < n) | ((uint32_t)(((d + 1) & mk) < n) << 1);
+}
+
+// Bits c = 2 dj + di of the 2 x 2 block from its column bits x and row bits y.
+__device__ __forceinline__ uint32_t quad_bits(uint32_t x, uint32_t y)
+{
+    return (x & (y & 1u ? 3u : 0u)) | ((x & (y & 2u ? 3u : 0u)) << 2);
+}
+
 // The 2 x 2 cells of level-1 node m (its leaf record), those overlapping the box
 // (all four when the node lies inside it): bit 2 c4 + half for cell c4 = 2 dj + di.
+// The block's nine corners give 16 distinct edges (6 horizontal, 6 vertical and 4
+// diagonals), each computed once in its canonical direction as in cell_mask, so
+// the bits equal cell_mask's for each cell.  rx, ry: the level-0 runs.
 __device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const QuerySetup& q, uint32_t m, bool inside,
-                                                   Acc& acc)
+                                                   const AxisRuns& rx, const AxisRuns& ry, Acc& acc)
 {
     const float4* r = reinterpret_cast<const float4*>(H.quad + m);
     const float4 a = r[0], b = r[1], c = r[2], d = r[3], e = r[4];
-    const float2 t[9] = {make_float2(a.x, a.y), make_float2(a.z, a.w), make_float2(b.x, b.y),
-                         make_float2(b.z, b.w), make_float2(c.x, c.y), make_float2(c.z, c.w),
-                         make_float2(d.x, d.y), make_float2(d.z, d.w), make_float2(e.x, e.y)};
+    const float tx[9] = {a.x, a.z, b.x, b.z, c.x, c.z, d.x, d.z, e.x};
+    const float ty[9] = {a.y, a.w, b.y, b.w, c.y, c.w, d.y, d.w, e.y};
     const uint32_t dg4 = __float_as_uint(e.z);
-    bool x0 = true, x1 = true, y0 = true, y1 = true;
+    uint32_t ov = 0xfu;
     if (!inside) {
-        const int logn = H.logn;
-        const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
-        x0 = axis_overlap(2 * I, 1, q.cxlo, q.cxhi, logn);
-        x1 = axis_overlap(2 * I + 1, 1, q.cxlo, q.cxhi, logn);
-        y0 = axis_overlap(2 * J, 1, q.cylo, q.cyhi, logn);
-        y1 = axis_overlap(2 * J + 1, 1, q.cylo, q.cyhi, logn);
+        const int mk = H.n - 1;
+        ov = quad_bits(pair_in_run((int)morton_compact(m), rx.a, rx.n, mk),
+                       pair_in_run((int)morton_compact(m >> 1), ry.a, ry.n, mk));
     }
-    // every cell is tested (the wave runs each cell's test whenever one lane needs
-    // it anyway) and the cells outside the support are masked afterwards
-    const uint32_t ov = (uint32_t)(x0 && y0) | ((uint32_t)(x1 && y0) << 1) | ((uint32_t)(x0 && y1) << 2) |
-                        ((uint32_t)(x1 && y1) << 3);
     acc.cells += (uint32_t)__popc(ov);
+    // row by row (rows of corners 0-2 bottom to top), so that only two rows of
+    // offsets and their edges are live at a time
     uint32_t mask = 0;
+    float bx[3], by[3], bh[2];  // the lower row's offsets and its horizontal edges
 #pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) {
-        const int di = c4 & 1, dj = c4 >> 1;
-        mask |= cell_mask(q, H.rho, t[3 * dj + di], t[3 * dj + di + 1], t[3 * dj + di + 3], t[3 * dj + di + 4],
-                          (dg4 >> (8 * c4)) & 0xffu)
-                << (2 * c4);
+    for (int c = 0; c < 3; ++c) {
+        bx[c] = tx[c] - q.hx;
+        by[c] = ty[c] - q.hy;
+    }
+    bh[0] = cross2(bx[0], by[0], bx[1], by[1]);
+    bh[1] = cross2(bx[1], by[1], bx[2], by[2]);
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+        float ux[3], uy[3], uh[2], vt[3];  // the upper row, its horizontal edges, the vertical edges
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ux[c] = tx[3 * dj + 3 + c] - q.hx;
+            uy[c] = ty[3 * dj + 3 + c] - q.hy;
+            vt[c] = cross2(bx[c], by[c], ux[c], uy[c]);
+        }
+        uh[0] = cross2(ux[0], uy[0], ux[1], uy[1]);
+        uh[1] = cross2(ux[1], uy[1], ux[2], uy[2]);
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const float d12 = cross2(bx[di + 1], by[di + 1], ux[di], uy[di]);
+            mask |= (same_sign3(d12, -vt[di], bh[di]) | (same_sign3(d12, -vt[di + 1], uh[di]) << 1))
+                    << (2 * (2 * dj + di));
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            bx[c] = ux[c];
+            by[c] = uy[c];
+        }
+        bh[0] = uh[0];
+        bh[1] = uh[1];
+    }
+    if (dg4 & 0x03030303u) {
+        // rare: a clamped triangle (its cell's replacement) is tested on its own; the
+        // corners are read again (cached) rather than kept live through the tests
+        const QuadRec* rec = H.quad + m;
+        for (int c4 = 0; c4 < 4; ++c4) {
+            const uint32_t dg = (dg4 >> (8 * c4)) & 3u;
+            if (dg) {
+                const int k = 3 * (c4 >> 1) + (c4 & 1);
+                const uint32_t m2 = patch_clamped(q, H.rho, rec->t[k + 1], rec->t[k + 3], dg, (mask >> (2 * c4)) & 3u);
+                mask = (mask & ~(3u << (2 * c4))) | (m2 << (2 * c4));
+            }
+        }
     }
     const uint32_t ov2 = (ov & 1u) * 3u | ((ov >> 1) & 1u) * 12u | ((ov >> 2) & 1u) * 48u | ((ov >> 3) & 1u) * 192u;
     return mask & ov2;
@@ -320,13 +404,13 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 {
     static_assert(!SPAWN || MODE == kModeValue, "donation is only used by value-mode workers");
     const int lane = threadIdx.x & 63;
-    const int logn = H.logn;
     const float4* __restrict__ boxes = CUT ? H.bbox_all : H.bbox;
     uint32_t* hq = lists + H.L * kListCap;  // hit queue
     int hn = 0;                             // queued hits (wave-uniform)
     uint32_t pend = 0, ebase = 0;           // this lane's float32 hits not yet queued
     uint32_t nonempty = 0;   // bit l: list of level l non-empty (wave-uniform)
     int cntv = 0;            // lane l holds the size of list l
+    const AxisRuns rx0 = axis_runs(q.cxlo, q.cxhi, 0, H.n), ry0 = axis_runs(q.cylo, q.cyhi, 0, H.n);
     if (root_level == 0) {
         const int i = (int)(root_item & 0xffffu), j = (int)(root_item >> 16);
         if (root_ok) {
@@ -444,7 +528,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 pend = cluster_mask(H, q, l, idx, acc);
                 ebase = kHitCluster | ((uint32_t)l << 25) | (m << 1);
             } else if (l == 1) {
-                pend = leaf_quad_mask(H, q, m, inside, acc);
+                pend = leaf_quad_mask(H, q, m, inside, rx0, ry0, acc);
                 ebase = m << 3;
             } else {
                 // the four child boxes are one 64-byte Morton segment: loaded whole (no
@@ -455,18 +539,11 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 cin = 0xfu;
                 if (!inside) {
                     const int I = (int)morton_compact(m), J = (int)morton_compact(m >> 1);
-                    const int side = 1 << (l - 1);
-                    const int sx0 = 2 * I * side, sx1 = sx0 + side, sy0 = 2 * J * side, sy1 = sy0 + side;
-                    const uint32_t x0 = axis_overlap(sx0, side, q.cxlo, q.cxhi, logn);
-                    const uint32_t x1 = axis_overlap(sx1, side, q.cxlo, q.cxhi, logn);
-                    const uint32_t y0 = axis_overlap(sy0, side, q.cylo, q.cyhi, logn);
-                    const uint32_t y1 = axis_overlap(sy1, side, q.cylo, q.cyhi, logn);
-                    ov = (x0 & y0) | ((x1 & y0) << 1) | ((x0 & y1) << 2) | ((x1 & y1) << 3);
-                    const uint32_t fx0 = axis_inside(sx0, side, q.cxlo, q.cxhi, logn);
-                    const uint32_t fx1 = axis_inside(sx1, side, q.cxlo, q.cxhi, logn);
-                    const uint32_t fy0 = axis_inside(sy0, side, q.cylo, q.cyhi, logn);
-                    const uint32_t fy1 = axis_inside(sy1, side, q.cylo, q.cyhi, logn);
-                    cin = (fx0 & fy0) | ((fx1 & fy0) << 1) | ((fx0 & fy1) << 2) | ((fx1 & fy1) << 3);
+                    const int mk = (H.n >> (l - 1)) - 1;
+                    const AxisRuns rx = axis_runs(q.cxlo, q.cxhi, l - 1, mk + 1);
+                    const AxisRuns ry = axis_runs(q.cylo, q.cyhi, l - 1, mk + 1);
+                    ov = quad_bits(pair_in_run(I, rx.a, rx.n, mk), pair_in_run(J, ry.a, ry.n, mk));
+                    cin = quad_bits(pair_in_run(I, rx.ai, rx.ni, mk), pair_in_run(J, ry.ai, ry.ni, mk));
                 }
                 tested = (uint32_t)__popc(ov);
                 chm = ((uint32_t)in_box(q, b0) | ((uint32_t)in_box(q, b1) << 1) | ((uint32_t)in_box(q, b2) << 2) |
