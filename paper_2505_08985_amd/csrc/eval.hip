@@ -42,15 +42,25 @@ struct Rec {  // hit-record cursor (record mode)
     uint64_t pos, end;
 };
 
-// FP64 confirmation of a float32 hit, barycentrics and term; < 0 if rejected.
+// FP64 confirmation of a float32 hit, barycentrics and term; < 0 if rejected.  The
+// offsets v - h of float32 values are exact in FP64 and the cyclic edge functions
+// e_k (as in the float32 test) give the barycentrics l_k = e_k / S, S = e0 + e1 + e2
+// (twice the signed area, never 0: clamped triangles are replaced).  One division,
+// R = 1 / (S det), serves both quotients: 1 / S = det R and 1 / det = S R.
 template <int KER>
 __device__ __forceinline__ double confirm_and_term(const QuerySetup& q, const double v[6], int I,
                                                    int J, int lev, int half, float det_used,
                                                    int logn)
 {
-    double l1, l2;
-    if (!tri_bary_f64(v, (double)q.hx, (double)q.hy, &l1, &l2)) return -1.0;
-    return hit_term<KER>(q, I, J, lev, half, l1, l2, det_used, logn);
+    const double hx = (double)q.hx, hy = (double)q.hy;
+    const double ax = v[0] - hx, ay = v[1] - hy, bx = v[2] - hx, by = v[3] - hy;
+    const double cx = v[4] - hx, cy = v[5] - hy;
+    const double e0 = bx * cy - by * cx, e1 = cx * ay - cy * ax, e2 = ax * by - ay * bx;
+    if (!((e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) || (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0))) return -1.0;
+    const double S = e0 + e1 + e2, dj = (double)det_used;
+    const double R = 1.0 / (S * dj);
+    const double rs = dj * R;
+    return hit_weight<KER>(q, I, J, lev, half, e1 * rs, e2 * rs, logn) * (S * R);
 }
 
 // Per-lane hit sink of one hit-processing round: value/count modes add the term to

@@ -373,8 +373,18 @@ __device__ __forceinline__ QuerySetup uniform_query(const QuerySetup& q)
     return u;
 }
 
+// Bits [64 w, 64 w + 64) of m 2^sh for s = sh - 64 w (m < 2^53): m << s for
+// 0 <= s < 64, m >> -s for -64 < s < 0, else 0 (the hardware takes shift counts
+// mod 64, hence the selects).
+__device__ __forceinline__ uint64_t fix_word(uint64_t m, int s)
+{
+    const uint64_t up = m << (s & 63), dn = m >> ((-s) & 63);
+    return s >= 0 ? (s < 64 ? up : 0ull) : (s > -64 ? dn : 0ull);
+}
+
 // FP64 term t >= 0 added exactly down to 2^fexp: t = m 2^(ex - 1075) = (m 2^sh) 2^fexp,
-// sh <= 136 since t < 2^(fexp + 189)
+// sh <= 136 since t < 2^(fexp + 189).  Branch-free: the lanes of a wave hold terms of
+// different magnitudes, and a branch per word range would run every range.
 __device__ __forceinline__ void fix_add_term(Fix192& a, double t, int fexp)
 {
     const uint64_t b = (uint64_t)__double_as_longlong(t);
@@ -382,21 +392,7 @@ __device__ __forceinline__ void fix_add_term(Fix192& a, double t, int fexp)
     uint64_t m = b & 0xfffffffffffffull;
     if (ex) m |= 0x10000000000000ull; else ex = 1;
     const int sh = ex - 1075 - fexp;
-    uint64_t v0 = 0, v1 = 0, v2 = 0;
-    if (sh <= -64) {
-        // below the accumulator's resolution
-    } else if (sh < 0) {
-        v0 = m >> (-sh);
-    } else if (sh < 64) {
-        v0 = m << sh;
-        v1 = sh ? (m >> (64 - sh)) : 0;
-    } else if (sh < 128) {
-        const int s1 = sh - 64;
-        v1 = m << s1;
-        v2 = s1 ? (m >> (64 - s1)) : 0;
-    } else {
-        v2 = m << (sh - 128);
-    }
+    const uint64_t v0 = fix_word(m, sh), v1 = fix_word(m, sh - 64), v2 = fix_word(m, sh - 128);
     const uint64_t r0 = a.w0 + v0;
     const uint64_t c0 = r0 < v0 ? 1u : 0u;
     const uint64_t t1 = a.w1 + v1;
@@ -447,6 +443,12 @@ __device__ __forceinline__ bool axis_overlap(int start, int side, int clo, int c
 // exponent a = d^2 log2(e) / (2 sigma^2) is split into floor(a) (an exact power of
 // two, ldexp) and a fraction (float32 exp2), so nothing underflows before the
 // FP64 product.
+__device__ __forceinline__ double exp2_neg_split(double a)
+{
+    const double ai = floor(a);
+    return ldexp((double)exp2f(-(float)(a - ai)), -(int)fmin(ai, 2000.0));
+}
+
 __device__ inline double gauss_axis(float x, double k, int start, int side, double uoff, int clo,
                                     int chi, int logn)
 {
@@ -456,11 +458,25 @@ __device__ inline double gauss_axis(float x, double k, int start, int side, doub
     double base = (double)start + uoff - (double)x;
     for (int p = p0; p <= p1; ++p) {
         const double d = base + (double)p * (double)(1 << logn);
-        const double a = d * d * k;
-        const double ai = floor(a);
-        g += ldexp((double)exp2f(-(float)(a - ai)), -(int)fmin(ai, 2000.0));
+        g += exp2_neg_split(d * d * k);
     }
     return g;
+}
+
+// Both axes of the Gaussian footprint.  When each axis has a single included image
+// (every footprint narrower than the map, away from none of its wraps) the product
+// of the two factors is one exponential of the summed exponents.
+__device__ inline double gauss_2d(const QuerySetup& q, int sx, int sy, int side, double ux, double uy, int logn)
+{
+    const int px = ceil_div_pow2(q.cxlo - sx - side + 1, logn), py = ceil_div_pow2(q.cylo - sy - side + 1, logn);
+    if (px == floor_div_pow2(q.cxhi - sx, logn) && py == floor_div_pow2(q.cyhi - sy, logn)) {
+        const double period = (double)(1 << logn);
+        const double dx = (double)sx + ux - (double)q.x + (double)px * period;
+        const double dy = (double)sy + uy - (double)q.y + (double)py * period;
+        return exp2_neg_split(dx * dx * q.kx + dy * dy * q.ky);
+    }
+    return gauss_axis(q.x, q.kx, sx, side, ux, q.cxlo, q.cxhi, logn) *
+           gauss_axis(q.y, q.ky, sy, side, uy, q.cylo, q.cyhi, logn);
 }
 
 // Replacement-triangle vertices (circumradius rho around c, at 90/210/330 degrees).
@@ -489,19 +505,6 @@ __device__ __forceinline__ bool tri_hit_f32(const float v[6], float hx, float hy
     float cx = v[4] - hx, cy = v[5] - hy;
     float e0 = cross2(bx, by, cx, cy), e1 = cross2(cx, cy, ax, ay), e2 = cross2(ax, ay, bx, by);
     return (e0 >= 0.f && e1 >= 0.f && e2 >= 0.f) || (e0 <= 0.f && e1 <= 0.f && e2 <= 0.f);
-}
-
-// FP64 barycentrics of h in triangle v (a, b, c); returns false if h is outside.
-__device__ inline bool tri_bary_f64(const double v[6], double hx, double hy, double* l1, double* l2)
-{
-    double ax = v[0] - hx, ay = v[1] - hy, bx = v[2] - hx, by = v[3] - hy;
-    double cx = v[4] - hx, cy = v[5] - hy;
-    double e0 = bx * cy - by * cx, e1 = cx * ay - cy * ax, e2 = ax * by - ay * bx;
-    bool in = (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) || (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0);
-    const double inv = 1.0 / (e0 + e1 + e2);  // one division for both coordinates
-    *l1 = e1 * inv;
-    *l2 = e2 * inv;
-    return in;
 }
 
 // Contribution of a hit: the triangle's uv vertices are (a, b, c) =
@@ -540,9 +543,10 @@ __device__ inline double disk_images(const QuerySetup& q, int sx0, int sy0, int 
 
 // (the footprint kernel KER is a template parameter: each kernel's evaluation code
 // is compiled separately, so the Gaussian path carries none of the others' registers)
+// The footprint weight of a hit, norm k(u*), without the division by the Jacobian.
 template <int KER>
-__device__ inline double hit_term(const QuerySetup& q, int I, int J, int lev, int half, double l1,
-                                  double l2, float det_used, int logn)
+__device__ inline double hit_weight(const QuerySetup& q, int I, int J, int lev, int half, double l1,
+                                    double l2, int logn)
 {
     const int s = 1 << lev;
     double ux = half ? (double)s * (1.0 - l1) : (double)s * l1;
@@ -554,10 +558,16 @@ __device__ inline double hit_term(const QuerySetup& q, int I, int J, int lev, in
     } else if constexpr (KER == PNDF_KERNEL_DISK) {
         w = disk_images(q, I * s, J * s, s, ux, uy, logn);
     } else {
-        w = gauss_axis(q.x, q.kx, I * s, s, ux, q.cxlo, q.cxhi, logn) *
-            gauss_axis(q.y, q.ky, J * s, s, uy, q.cylo, q.cyhi, logn);
+        w = gauss_2d(q, I * s, J * s, s, ux, uy, logn);
     }
-    return q.norm * w / (double)det_used;
+    return q.norm * w;
+}
+
+template <int KER>
+__device__ inline double hit_term(const QuerySetup& q, int I, int J, int lev, int half, double l1,
+                                  double l2, float det_used, int logn)
+{
+    return hit_weight<KER>(q, I, J, lev, half, l1, l2, logn) / (double)det_used;
 }
 
 __device__ __forceinline__ uint64_t tri_id(int lev, int I, int J, int half)
