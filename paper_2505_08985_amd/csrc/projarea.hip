@@ -23,9 +23,10 @@
 // the included cells (two triangles each), FP64 throughout; the lanes' partial
 // sums are reduced in the wave.  V lies right of the line m_x = -w_z (the
 // ellipse's leftmost point), so a triangle left of it adds nothing; a triangle
-// with its three vertices in V takes three segment terms at once; only the others
-// need clipping, and they wait in a per-wave LDS queue until 64 of them fill a
-// round with one per lane (a lane's clipping would otherwise stall its wave).
+// with its three vertices in V takes three segment terms at once (a cell whose two
+// triangles both lie in V five: the shared diagonal once); only the others need
+// clipping, and they wait in a per-wave LDS queue until 64 of them fill a round with
+// one per lane (a lane's clipping would otherwise stall its wave).
 #include "pndf_internal.h"
 
 namespace pndf {
@@ -54,20 +55,33 @@ __device__ __forceinline__ double arc_prim_diff(double a, double b)
     return 0.5 * (d + b * cb - a * ca);
 }
 
+// 1 / sqrt(x), x > 0, in FP64: the hardware estimate refined by two Newton steps
+// y <- y (3/2 - x y^2 / 2) (each step squares the relative error), so the segment
+// terms need no FP64 square root or division for their unit direction and 1/rho.
+__device__ __forceinline__ double rsqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 // F dm_y along the segment P -> Q
 __device__ inline double segment_int(double px, double py, double qx, double qy, double wl, double wz)
 {
     double dx = qx - px, dy = qy - py;
-    const double len = sqrt(dx * dx + dy * dy);
-    if (len == 0.0) return 0.0;
+    const double l2 = dx * dx + dy * dy;
+    if (l2 == 0.0) return 0.0;
     const double lin = 0.5 * wz * dy * (px + qx);
-    dx /= len;
-    dy /= len;
+    const double il = rsqrt_f64(l2);
+    dx *= il;
+    dy *= il;
     const double s = dy * px - dx * py;
     const double rho2 = 1.0 - s * s;
     if (rho2 <= 0.0) return lin;
-    const double rho = sqrt(rho2);
-    return lin - wl * dy * rho2 * arc_prim_diff((dx * px + dy * py) / rho, (dx * qx + dy * qy) / rho);
+    const double ir = rsqrt_f64(rho2);
+    return lin - wl * dy * rho2 * arc_prim_diff((dx * px + dy * py) * ir, (dx * qx + dy * qy) * ir);
 }
 
 // place of a point of V's boundary on its counter-clockwise loop from (0, -1):
@@ -276,21 +290,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             const int j = spany >= n ? cb : ((q.cylo + cb) & msk);
             cell = (uint32_t)i | ((uint32_t)j << 13);
             const float2 dd = H.det[(int64_t)j * n + i];
+            // kernel at the uv centroid over the included images, divided by J
+            double kh[2];
+            kh[0] = hit_term<KER>(q, i, j, 0, 0, 1.0 / 3.0, 1.0 / 3.0, dd.x, H.logn);
+            kh[1] = hit_term<KER>(q, i, j, 0, 1, 1.0 / 3.0, 1.0 / 3.0, dd.y, H.logn);
+            if ((H.deg[(int64_t)j * n + i] & 3u) == 0u) {
+                // both halves regular: lower (n0, n1, n2) and upper (n3, n2, n1) share the
+                // diagonal n1 -> n2, which the upper runs backwards.  The corners are rotated
+                // once; a triangle's CCW boundary integral is its orientation sign times
+                // the integral in vertex order, so with both triangles inside V the
+                // diagonal's term is computed once with weight s_l k_l - s_u k_u.
+                const int wdt = n + 1;
+                const float2* p = H.nrm + (int64_t)j * wdt + i;
+                const float2 nn[4] = {p[0], p[1], p[wdt], p[wdt + 1]};
+                double x[4], y[4];
+                bool vis[4], left[4];
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                // kernel at the uv centroid over the included images, divided by J
-                const double kj = hit_term<KER>(q, i, j, 0, half, 1.0 / 3.0, 1.0 / 3.0, half ? dd.y : dd.x, H.logn);
-                if (kj == 0.0) continue;
-                double r[6];
-                cell_triangle(H, i, j, half, c, sn, r);
-                if (r[0] < -wz && r[2] < -wz && r[4] < -wz) continue;  // left of V
-                if (visible(r[0], r[1], wz) && visible(r[2], r[3], wz) && visible(r[4], r[5], wz)) {
-                    acc += kj * (segment_int(r[0], r[1], r[2], r[3], wl, wz) +
-                                 segment_int(r[2], r[3], r[4], r[5], wl, wz) +
-                                 segment_int(r[4], r[5], r[0], r[1], wl, wz));
-                } else {
-                    clip |= 1u << half;
-                    kw[half] = kj;
+                for (int k = 0; k < 4; ++k) {
+                    x[k] = c * (double)nn[k].x + sn * (double)nn[k].y;
+                    y[k] = -sn * (double)nn[k].x + c * (double)nn[k].y;
+                    vis[k] = visible(x[k], y[k], wz);
+                    left[k] = x[k] < -wz;
+                }
+                const double sl = (x[1] - x[0]) * (y[2] - y[0]) - (y[1] - y[0]) * (x[2] - x[0]) < 0.0 ? -1.0 : 1.0;
+                const double su = (x[2] - x[3]) * (y[1] - y[3]) - (y[2] - y[3]) * (x[1] - x[3]) < 0.0 ? -1.0 : 1.0;
+                const bool lo_live = kh[0] != 0.0 && !(left[0] && left[1] && left[2]);
+                const bool up_live = kh[1] != 0.0 && !(left[3] && left[2] && left[1]);
+                const bool lo_full = lo_live && vis[0] && vis[1] && vis[2];
+                const bool up_full = up_live && vis[3] && vis[2] && vis[1];
+                double wd = 0.0;
+                if (lo_full) {
+                    acc += kh[0] * sl * (segment_int(x[0], y[0], x[1], y[1], wl, wz) +
+                                         segment_int(x[2], y[2], x[0], y[0], wl, wz));
+                    wd += kh[0] * sl;
+                }
+                if (up_full) {
+                    acc += kh[1] * su * (segment_int(x[3], y[3], x[2], y[2], wl, wz) +
+                                         segment_int(x[1], y[1], x[3], y[3], wl, wz));
+                    wd -= kh[1] * su;
+                }
+                if (wd != 0.0) acc += wd * segment_int(x[1], y[1], x[2], y[2], wl, wz);
+                if (lo_live && !lo_full) {
+                    clip |= 1u;
+                    kw[0] = kh[0];
+                }
+                if (up_live && !up_full) {
+                    clip |= 2u;
+                    kw[1] = kh[1];
+                }
+            } else {
+                // a clamped half (its replacement triangle): each triangle on its own
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const double kj = kh[half];
+                    if (kj == 0.0) continue;
+                    double r[6];
+                    cell_triangle(H, i, j, half, c, sn, r);
+                    if (r[0] < -wz && r[2] < -wz && r[4] < -wz) continue;  // left of V
+                    if (visible(r[0], r[1], wz) && visible(r[2], r[3], wz) && visible(r[4], r[5], wz)) {
+                        acc += kj * (segment_int(r[0], r[1], r[2], r[3], wl, wz) +
+                                     segment_int(r[2], r[3], r[4], r[5], wl, wz) +
+                                     segment_int(r[4], r[5], r[0], r[1], wl, wz));
+                    } else {
+                        clip |= 1u << half;
+                        kw[half] = kj;
+                    }
                 }
             }
         }
