@@ -342,6 +342,76 @@ def test_counts_are_consistent(P, oracle_mod):
     assert ct.cpu().numpy()[:, 2].sum() > 0
 
 
+def lattice_map(n, seed, step, jitter):
+    """Texel normals on the 1/128 lattice: a regular grid of the given step with a
+    jitter of up to `jitter` lattice units.  Every offset v - h with h on the 1/256
+    lattice and every edge function (products of such offsets) is exact in float32
+    and FP64, so the inclusive triangle test has one right answer for every h,
+    including h on an edge or at a vertex."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n) - n // 2
+    gx = i[None, :] * step + rng.integers(-jitter, jitter + 1, (n, n))
+    gy = i[:, None] * step + rng.integers(-jitter, jitter + 1, (n, n))
+    return (np.stack([gx, gy], axis=-1) / 128.0).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,step,jitter", [(16, 8, 1), (32, 4, 2)])
+def test_query_normals_on_edges_and_vertices(P, oracle_mod, n, step, jitter):
+    """h at texel normals (the six triangles around the vertex contain it), at the
+    midpoints of mesh edges (horizontal, vertical and cell diagonals: both triangles
+    of the edge) and at other 1/256-lattice points, with the footprint around that
+    vertex or edge.  On the 16^2 map (no clamped cell) every decision is exact, so
+    the GPU hit sets equal the oracle's exactly; on the 32^2 map some cells are
+    clamped (replacement triangles off the lattice) and the sets agree outside the
+    oracle's ambiguity band.  Brute force, plain and persistent give the same bits."""
+    import torch
+    announce("eval lattice map %d step %d: h on edges and vertices" % (n, step))
+    nrm = lattice_map(n, 21 + n, step, jitter)
+    clamped = oracle_mod.mesh(nrm)[1] != 0
+    rng = np.random.default_rng(n)
+    count = 1500
+    third = count // 3
+    ci = rng.integers(0, n, count)
+    cj = rng.integers(0, n, count)
+    q = np.zeros((count, 6), dtype=np.float32)
+    # footprint around cell (ci, cj): its neighbours' triangles are in the support
+    q[:, 0] = ci + 0.5 + n * rng.integers(-1, 2, count)
+    q[:, 1] = cj + 0.5 + n * rng.integers(-1, 2, count)
+    q[:, 2] = np.exp(rng.uniform(np.log(0.3), np.log(2.0 * n), count))
+    q[:, 3] = q[:, 2] * np.exp(rng.uniform(-0.5, 0.5, count))
+    q[:, 2:4] = np.maximum(q[:, 2:4], 0.3)
+    kind = rng.integers(0, 3, count)
+    i1, j1 = (ci + 1) % n, (cj + 1) % n
+    pa = np.where(kind[:, None] == 2, nrm[cj, i1], nrm[cj, ci])          # edge start
+    pb = np.select([kind[:, None] == 0, kind[:, None] == 1], [nrm[cj, i1], nrm[j1, ci]], nrm[j1, ci])
+    q[:third, 4:6] = nrm[cj[:third], ci[:third]]                          # vertex (ci, cj)
+    q[third:2 * third, 4:6] = (0.5 * (pa + pb))[third:2 * third]          # edge midpoints
+    q[2 * third:, 4:6] = rng.integers(-140, 141, (count - 2 * third, 2)) / 256.0
+    assert np.array_equal(q[:, 4:6] * 256.0, np.round(q[:, 4:6] * 256.0))
+    _, hier = gpu_build(P, nrm, cluster=False)
+    ref = oracle_mod.evaluate(nrm, q, records=True)
+    d, off, ids, _ = gpu_hits(P, hier, q, algo="plain")
+    st = compare(ref, d, off, ids)
+    nhit = ref["nhit"]
+    if not clamped.any():
+        hoff, hid = ref["hit_off"], ref["hit_id"]
+        for k in range(count):
+            assert set(ids[off[k]:off[k + 1]].tolist()) == set(hid[hoff[k]:hoff[k + 1]].tolist()), k
+        assert np.array_equal(nhit, np.diff(off))
+        assert (nhit[:third] >= 6).all()
+        assert (nhit[third:2 * third] >= 2).all()
+    else:
+        assert (nhit[:third] >= 6).mean() > 0.8
+    assert st["nonzero"] > count // 2
+    tq = to_dev(q)
+    bits = [P.eval_batch(hier, tq, algo=algo).view(torch.int32) for algo in ("plain", "brute")]
+    plan = P.Plan(hier, count)
+    bits.append(plan.eval(tq).view(torch.int32))
+    plan.close()
+    torch.cuda.synchronize()
+    assert torch.equal(bits[0], bits[1]) and torch.equal(bits[0], bits[2])
+
+
 def test_deterministic_alone_and_in_the_mix(P):
     import torch
     import workloads
