@@ -18,8 +18,8 @@
 //
 // Work per sample: the query (24 B), one uniform pair (16 B), the cut levels'
 // residuals (4 B each, from the entry level down to the cut), the unit's four corner
-// normals and clamp bits, and the outputs.  Nothing is shared between samples:
-// the kernel is a gather-bound stream.
+// normals and clamp bits (for a texel cell from its leaf record), and the outputs.
+// Nothing is shared between samples: the kernel is a gather-bound stream.
 #include "pndf_internal.h"
 
 namespace pndf {
@@ -123,10 +123,13 @@ __global__ __launch_bounds__(256) void k_sample(HierDev H, SampleArgs a)
         float2 n0, n1, n2, n3;
         bool clamped;
         if (lev == 0) {
-            const int wdt = H.n + 1;
-            const float2* p = H.nrm + (int64_t)J * wdt + I;
-            n0 = p[0]; n1 = p[1]; n2 = p[wdt]; n3 = p[wdt + 1];
-            clamped = (H.deg[(int64_t)J * H.n + I] >> half) & 1u;
+            // from the cell's 2 x 2 leaf record (its 3 x 3 corners and clamp bytes in
+            // 80 B), not from two rows of the normal plane and the clamp array: one
+            // scattered record instead of three scattered lines per sample
+            const QuadRec* r = H.quad + morton((uint32_t)I >> 1, (uint32_t)J >> 1);
+            const int di = I & 1, dj = J & 1, k = 3 * dj + di;
+            n0 = r->t[k]; n1 = r->t[k + 1]; n2 = r->t[k + 3]; n3 = r->t[k + 4];
+            clamped = (r->deg[2 * dj + di] >> half) & 1u;
         } else {
             const int64_t ix = level_offset(H.logn, lev) + morton((uint32_t)I, (uint32_t)J);
             const float4 ca = H.clu_n[2 * ix], cb = H.clu_n[2 * ix + 1];
