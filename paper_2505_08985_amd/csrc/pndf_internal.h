@@ -424,18 +424,12 @@ __device__ __forceinline__ float fix_to_float(const Fix192& a, int fexp)
     return (float)ldexp(d, fexp);
 }
 
-// Does a node of side 2^lev starting at torus cell `start` have a periodic image
-// with a cell inside the unrolled cell range [clo, chi]?
-// Some periodic image [start + pN, start + side - 1 + pN] lies wholly inside the cell
-// range [clo, chi]: the first image starting at or after clo ends by chi.
+// Does a node of side `side` starting at torus cell `start` have a periodic image
+// [start + pN, start + side - 1 + pN] wholly inside the unrolled cell range
+// [clo, chi]?  Yes iff the first image starting at or after clo ends by chi.
 __device__ __forceinline__ bool axis_inside(int start, int side, int clo, int chi, int logn)
 {
     return start + (ceil_div_pow2(clo - start, logn) << logn) + side - 1 <= chi;
-}
-
-__device__ __forceinline__ bool axis_overlap(int start, int side, int clo, int chi, int logn)
-{
-    return ceil_div_pow2(clo - start - side + 1, logn) <= floor_div_pow2(chi - start, logn);
 }
 
 // Sum over the included periodic images of one axis of exp(-d^2 / (2 sigma^2)),
@@ -636,16 +630,55 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// Row shift of a 64-bit value by DPP (control 0x110 + n: row_shr n; lanes shifted in
+// from outside the 16-lane row read 0).
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_row_shr(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void fix_add_row_shr(Fix192& v)
+{
+    Fix192 w;
+    w.w0 = dpp_row_shr<CTRL>(v.w0);
+    w.w1 = dpp_row_shr<CTRL>(v.w1);
+    w.w2 = dpp_row_shr<CTRL>(v.w2);
+    fix_add(v, w);
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Exact sum over the wave (every lane must be active): within each row of 16 lanes
+// by DPP row shifts 1, 2, 4, 8 (lane 15 of the row then holds the row's sum), then
+// the four row sums read from lanes 15, 31, 47 and 63.
 __device__ __forceinline__ Fix192 wave_sum_fix(Fix192 v)
 {
-    for (int o = 32; o >= 1; o >>= 1) {
-        Fix192 w;
-        w.w0 = __shfl_xor(v.w0, o, 64);
-        w.w1 = __shfl_xor(v.w1, o, 64);
-        w.w2 = __shfl_xor(v.w2, o, 64);
-        fix_add(v, w);
+    fix_add_row_shr<0x111>(v);
+    fix_add_row_shr<0x112>(v);
+    fix_add_row_shr<0x114>(v);
+    fix_add_row_shr<0x118>(v);
+    Fix192 s;
+    s.w0 = readlane_u64(v.w0, 15);
+    s.w1 = readlane_u64(v.w1, 15);
+    s.w2 = readlane_u64(v.w2, 15);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        Fix192 t;
+        t.w0 = readlane_u64(v.w0, 16 * r + 15);
+        t.w1 = readlane_u64(v.w1, 16 * r + 15);
+        t.w2 = readlane_u64(v.w2, 16 * r + 15);
+        fix_add(s, t);
     }
-    return v;
+    return s;
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)

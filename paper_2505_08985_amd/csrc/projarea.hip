@@ -43,21 +43,9 @@ __device__ __forceinline__ bool visible(double x, double y, double wz)
     return x * x + y * y <= 1.0 && (x >= 0.0 || x * x + wz * wz * y * y <= wz * wz);
 }
 
-// A(b) - A(a) with one arcsine: asin b - asin a = asin(b sqrt(1 - a^2) - a sqrt(1 - b^2))
-// while the difference of the angles is within [-pi/2, pi/2], i.e. while
-// sqrt(1 - a^2) sqrt(1 - b^2) + a b >= 0; else two
-__device__ __forceinline__ double arc_prim_diff(double a, double b)
-{
-    a = fmin(1.0, fmax(-1.0, a));
-    b = fmin(1.0, fmax(-1.0, b));
-    const double ca = sqrt(fmax(0.0, 1.0 - a * a)), cb = sqrt(fmax(0.0, 1.0 - b * b));
-    const double d = ca * cb + a * b >= 0.0 ? asin(fmin(1.0, fmax(-1.0, b * ca - a * cb))) : asin(b) - asin(a);
-    return 0.5 * (d + b * cb - a * ca);
-}
-
 // 1 / sqrt(x), x > 0, in FP64: the hardware estimate refined by two Newton steps
 // y <- y (3/2 - x y^2 / 2) (each step squares the relative error), so the segment
-// terms need no FP64 square root or division for their unit direction and 1/rho.
+// terms need no FP64 square root or division (unit direction, 1/rho, sqrt(1 - y^2)).
 __device__ __forceinline__ double rsqrt_f64(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
@@ -65,6 +53,24 @@ __device__ __forceinline__ double rsqrt_f64(double x)
     y = y * fma(-h * y, y, 1.5);
     y = y * fma(-h * y, y, 1.5);
     return y;
+}
+
+// sqrt(z) for 0 <= z <= 1 as z / sqrt(z) (exactly 0 at 0)
+__device__ __forceinline__ double sqrt_unit(double z)
+{
+    return z > 0.0 ? z * rsqrt_f64(z) : 0.0;
+}
+
+// A(b) - A(a) with one arcsine: asin b - asin a = asin(b sqrt(1 - a^2) - a sqrt(1 - b^2))
+// while the difference of the angles is within [-pi/2, pi/2], i.e. while
+// sqrt(1 - a^2) sqrt(1 - b^2) + a b >= 0; else two
+__device__ __forceinline__ double arc_prim_diff(double a, double b)
+{
+    a = fmin(1.0, fmax(-1.0, a));
+    b = fmin(1.0, fmax(-1.0, b));
+    const double ca = sqrt_unit(1.0 - a * a), cb = sqrt_unit(1.0 - b * b);
+    const double d = ca * cb + a * b >= 0.0 ? asin(fmin(1.0, fmax(-1.0, b * ca - a * cb))) : asin(b) - asin(a);
+    return 0.5 * (d + b * cb - a * ca);
 }
 
 // F dm_y along the segment P -> Q
