@@ -123,6 +123,12 @@ constexpr uint32_t kHitPlane = 1u << 30, kHitCluster = 2u << 30;
 // whose region lies wholly inside the query's box, so that its descendants skip the
 // spatial tests.
 constexpr uint32_t kInside = 1u << 31;
+// With the cluster cut, bit 30 marks a node whose residual is within the query's
+// threshold (it answers with its two cluster triangles): decided when the node is
+// listed, from the four children's residuals read with their boxes, so popping a
+// node starts its own loads at once instead of waiting for its residual.
+constexpr uint32_t kCut = 1u << 30;
+constexpr uint32_t kCodeMask = (1u << 30) - 1u;
 
 // Inclusive same-sign test of a triangle's three edge values: h inside or on it.
 __device__ __forceinline__ uint32_t same_sign3(float a, float b, float c)
@@ -431,12 +437,16 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         bool ok = root_ok;
         if (ok && !roots_tested) {
             acc.nodes += 1;
-            ok = in_box(q, boxes[level_offset(H.logn, root_level) + (root_item & ~kInside)]);
+            ok = in_box(q, boxes[level_offset(H.logn, root_level) + (root_item & kCodeMask)]);
         }
         const uint64_t bal = __ballot(ok);
         const int pos = __popcll(bal & ((1ull << lane) - 1ull));
         const int tot = __popcll(bal);
-        if (ok) lists[(root_level - 1) * kListCap + pos] = root_item;
+        if (ok) {
+            uint32_t it = root_item & ~kCut;
+            if (CUT && H.clu_e[level_offset(H.logn, root_level) + (it & kCodeMask)] <= q.t) it |= kCut;
+            lists[(root_level - 1) * kListCap + pos] = it;
+        }
         if (lane == root_level) cntv = tot;
         if (tot) nonempty |= 1u << root_level;
         wave_sync();
@@ -492,7 +502,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 slot = uniform_u64(slot);
                 if (d > 0) {
                     if (lane < d) {
-                        const uint32_t mm = lists[(lh - 1) * kListCap + ch - 1 - lane] & ~kInside;  // the top d items
+                        const uint32_t mm = lists[(lh - 1) * kListCap + ch - 1 - lane] & kCodeMask;  // the top d items
                         Q.tasks[slot + lane] = (qidx << 32) | ((unsigned long long)lh << 26) | (unsigned long long)mm;
                         // the release store orders the task word before its flag
                         __hip_atomic_store(&Q.flags[slot + lane], Q.ctl->epoch, __ATOMIC_RELEASE,
@@ -528,13 +538,14 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         uint32_t cin = 0;     // children wholly inside the box (bit c)
         uint32_t m4 = 0;      // 4m: the first child's code
         uint32_t tested = 0;  // child boxes read by this lane
-        uint32_t entry = 0;   // the lane's list item (Morton code | kInside)
+        uint32_t cut4 = 0;    // children under the cut (bit c)
+        uint32_t entry = 0;   // the lane's list item (Morton code | kInside | kCut)
         if (lane < k) {
             entry = lists[(l - 1) * kListCap + base + lane];
-            const uint32_t m = entry & ~kInside;
+            const uint32_t m = entry & kCodeMask;
             const bool inside = (entry & kInside) != 0u;
             const int64_t idx = level_offset(H.logn, l) + m;
-            if (CUT && l <= q.l0 && H.clu_e[idx] <= q.t) {
+            if (CUT && (entry & kCut)) {
                 pend = cluster_mask(H, q, l, idx, acc);
                 ebase = kHitCluster | ((uint32_t)l << 25) | (m << 1);
             } else if (l == 1) {
@@ -545,6 +556,12 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 // extra traffic), children outside the support masked afterwards
                 const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
                 const float4 b0 = cb[0], b1 = cb[1], b2 = cb[2], b3 = cb[3];
+                if (CUT) {
+                    // the children's residuals: 16 B at a multiple of 4 nodes
+                    const float4 ce = *reinterpret_cast<const float4*>(H.clu_e + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
+                    cut4 = (uint32_t)(ce.x <= q.t) | ((uint32_t)(ce.y <= q.t) << 1) | ((uint32_t)(ce.z <= q.t) << 2) |
+                           ((uint32_t)(ce.w <= q.t) << 3);
+                }
                 uint32_t ov = 0xfu;  // children meeting the support box
                 cin = 0xfu;
                 if (!inside) {
@@ -579,7 +596,8 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (chm & (1u << c))
-                        dst[pos + __popc(chm & ((1u << c) - 1u))] = (m4 + c) | ((cin >> c) & 1u ? kInside : 0u);
+                        dst[pos + __popc(chm & ((1u << c) - 1u))] =
+                            (m4 + c) | ((cin >> c) & 1u ? kInside : 0u) | ((cut4 >> c) & 1u ? kCut : 0u);
                 acc.nodes += tested;
             }
             const int pushed = bb ? __builtin_amdgcn_readlane(pos, __builtin_ctzll(bb)) : total;
