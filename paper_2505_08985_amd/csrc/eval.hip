@@ -615,20 +615,21 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
     }
 }
 
-// Root items of a query: the entry-level nodes overlapping the box (<= 4 per
-// axis), one per lane of lanes 0..15 where *ok is set; Morton codes (level >= 1)
-// or packed texel cells (entry level 0).
-__device__ __forceinline__ uint32_t root_item(const HierDev& H, const QuerySetup& q, bool* ok)
+// Root items of a query: the level-lr nodes overlapping the box, one per lane of an
+// 8 x 8 lane grid where *ok is set; Morton codes (level >= 1) or packed texel cells
+// (level 0).  At the entry level l0 (node side >= r) at most 3 nodes per axis overlap
+// the box, at l0 - 1 at most 5.
+__device__ __forceinline__ uint32_t root_item(const HierDev& H, const QuerySetup& q, int lr, bool* ok)
 {
     const int lane = threadIdx.x & 63;
-    const int l0 = q.l0, M = H.n >> l0, mm = M - 1;
-    const int kx0 = q.cxlo >> l0, ky0 = q.cylo >> l0;
-    const int nkx = min((q.cxhi >> l0) - kx0 + 1, M), nky = min((q.cyhi >> l0) - ky0 + 1, M);
-    const int ra = lane & 3, rb = lane >> 2;
-    *ok = lane < 16 && ra < nkx && rb < nky;
+    const int M = H.n >> lr, mm = M - 1;
+    const int kx0 = q.cxlo >> lr, ky0 = q.cylo >> lr;
+    const int nkx = min((q.cxhi >> lr) - kx0 + 1, M), nky = min((q.cyhi >> lr) - ky0 + 1, M);
+    const int ra = lane & 7, rb = lane >> 3;
+    *ok = ra < nkx && rb < nky;
     const uint32_t I = (uint32_t)((kx0 + ra) & mm), J = (uint32_t)((ky0 + rb) & mm);
-    if (l0 == 0) return I | (J << 16);
-    const int side = 1 << l0;
+    if (lr == 0) return I | (J << 16);
+    const int side = 1 << lr;
     const bool inside = axis_inside((int)I * side, side, q.cxlo, q.cxhi, H.logn) &&
                         axis_inside((int)J * side, side, q.cylo, q.cyhi, H.logn);
     return morton(I, J) | (inside ? kInside : 0u);
@@ -724,10 +725,22 @@ __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
     Acc acc;
     Rec rec{a.ids, a.terms, MODE == kModeRecord ? a.offsets[qi] : 0,
             MODE == kModeRecord ? a.offsets[qi + 1] : 0};
+    // Without the cut the descent starts below the entry level: the entry level's few
+    // large boxes seldom prune, and testing their children (at most 5 x 5), or their
+    // grandchildren when those fit the 8 x 8 lane grid, as roots skips steps that
+    // would run with at most 9 or 25 of 64 lanes.  (With the cut the entry-level
+    // nodes' own residuals decide first, so it starts there.)
+    int lr = CUT ? q.l0 : max(q.l0 - 1, 0);
+    if (!CUT && lr >= 1) {
+        // one more level down while the roots still fit the 8 x 8 lane grid
+        const int l2 = lr - 1, M2 = H.n >> l2;
+        if (min((q.cxhi >> l2) - (q.cxlo >> l2) + 1, M2) <= 8 && min((q.cyhi >> l2) - (q.cylo >> l2) + 1, M2) <= 8)
+            lr = l2;
+    }
     bool ok;
-    const uint32_t item = root_item(H, q, &ok);
+    const uint32_t item = root_item(H, q, lr, &ok);
     TaskQueue none{};
-    descend<MODE, CUT, false, KER>(H, q, lists, q.l0, ok, item, false, 0, 0, none, acc, rec);
+    descend<MODE, CUT, false, KER>(H, q, lists, lr, ok, item, false, 0, 0, none, acc, rec);
     finish<MODE>(a, qi, q, acc);
 }
 
@@ -987,7 +1000,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         Acc acc;
         if (lev < 0) {
             lev = q.l0;
-            item = root_item(H, q, &root_ok);
+            item = root_item(H, q, q.l0, &root_ok);
         }
         // a query whose levels are all below split_level never donates; a stolen
         // subtree may be split again
