@@ -635,6 +635,24 @@ __device__ __forceinline__ uint32_t root_item(const HierDev& H, const QuerySetup
     return morton(I, J) | (inside ? kInside : 0u);
 }
 
+// The level a query's descent starts at.  Without the cut it starts below the entry
+// level: the entry level's few large boxes seldom prune, and testing their children
+// (at most 5 x 5), or their grandchildren when those fit the 8 x 8 lane grid, as
+// roots skips steps that would run with at most 9 or 25 of 64 lanes.  (With the cut
+// the entry-level nodes' own residuals decide first, so it starts there.)
+template <bool CUT>
+__device__ __forceinline__ int descent_start(const HierDev& H, const QuerySetup& q)
+{
+    if (CUT || q.l0 == 0) return q.l0;
+    int lr = q.l0 - 1;
+    if (lr >= 1) {
+        const int l2 = lr - 1, M2 = H.n >> l2;
+        if (min((q.cxhi >> l2) - (q.cxlo >> l2) + 1, M2) <= 8 && min((q.cyhi >> l2) - (q.cylo >> l2) + 1, M2) <= 8)
+            lr = l2;
+    }
+    return lr;
+}
+
 template <int MODE>
 __device__ __forceinline__ void finish(const EvalArgs& a, int64_t qi, const QuerySetup& q,
                                        const Acc& acc)
@@ -725,18 +743,7 @@ __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
     Acc acc;
     Rec rec{a.ids, a.terms, MODE == kModeRecord ? a.offsets[qi] : 0,
             MODE == kModeRecord ? a.offsets[qi + 1] : 0};
-    // Without the cut the descent starts below the entry level: the entry level's few
-    // large boxes seldom prune, and testing their children (at most 5 x 5), or their
-    // grandchildren when those fit the 8 x 8 lane grid, as roots skips steps that
-    // would run with at most 9 or 25 of 64 lanes.  (With the cut the entry-level
-    // nodes' own residuals decide first, so it starts there.)
-    int lr = CUT ? q.l0 : max(q.l0 - 1, 0);
-    if (!CUT && lr >= 1) {
-        // one more level down while the roots still fit the 8 x 8 lane grid
-        const int l2 = lr - 1, M2 = H.n >> l2;
-        if (min((q.cxhi >> l2) - (q.cxlo >> l2) + 1, M2) <= 8 && min((q.cyhi >> l2) - (q.cylo >> l2) + 1, M2) <= 8)
-            lr = l2;
-    }
+    const int lr = descent_start<CUT>(H, q);
     bool ok;
     const uint32_t item = root_item(H, q, lr, &ok);
     TaskQueue none{};
@@ -999,8 +1006,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         const QuerySetup q = uniform_query(setup_query(qs[qi], pa.s2r, CUT ? pa.tau : 0.f, H.L, H.eps, pa.kernel));
         Acc acc;
         if (lev < 0) {
-            lev = q.l0;
-            item = root_item(H, q, q.l0, &root_ok);
+            lev = descent_start<CUT>(H, q);
+            item = root_item(H, q, lev, &root_ok);
         }
         // a query whose levels are all below split_level never donates; a stolen
         // subtree may be split again
