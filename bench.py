@@ -416,8 +416,9 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(queries are independent; see the sharding note in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (queries are "
+              "independent and would shard by batch, each GPU holding the whole map and hierarchy)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
