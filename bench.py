@@ -59,15 +59,19 @@ def algorithmic_bytes(counts, tau):
     return float(np.sum(28.0 + per_node * c[:, 0] + 9.0 * c[:, 1] + 41.0 * c[:, 2] + 4.0 * c[:, 3]))
 
 
-def load_traffic(workload, algo, kernel="gaussian"):
+def load_traffic(workload, algo, kernel="gaussian", sigma_to_r=3.0, queries=None):
+    """The measured HBM bytes per launch, if the committed counters were taken on this
+    source and this exact launch: the workload's own batch at the default support."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         t = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
+    import workloads
     if (t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload or t.get("algo") != algo
-            or t.get("kernel", "gaussian") != kernel):
+            or t.get("kernel", "gaussian") != kernel or sigma_to_r != 3.0
+            or queries != workloads.CONFIGS[workload]["queries"]["count"]):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -521,7 +525,7 @@ def main():
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
     aops = algorithmic_ops(counts)
     achieved_ops = aops / (kernel_ms * 1e-3) / 1e12
-    traffic = load_traffic(args.workload, args.algo, kern)
+    traffic = load_traffic(args.workload, args.algo, kern, s2r, count)
     work = {"nodes_per_query": float(counts[:, 0].mean()), "cells_per_query": float(counts[:, 1].mean()),
             "clusters_per_query": float(counts[:, 2].mean()), "hits_per_query": float(counts[:, 3].mean()),
             "algorithmic_bytes_per_launch": abytes, "algorithmic_alu_ops_per_launch": aops}
