@@ -61,6 +61,7 @@ static void fill_view(pndf_hier* h)
     d.clu_e = h->clu_e;
     d.clu_det = h->clu_det;
     d.clu_deg = h->clu_deg;
+    d.bbox_h = h->bbox_h;
     d.quad = h->quad;
     d.n = m->n;
     d.L = m->L;
@@ -226,6 +227,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         if (e == hipSuccess) e = hipMalloc(&h->clu_e, sizeof(float) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_det, sizeof(float2) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_deg, nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->bbox_h, sizeof(uint2) * nodes);
     }
     fill_view(h);
     if (e == hipSuccess) e = build_hierarchy_levels(h, (hipStream_t)stream);
@@ -233,7 +235,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + (cluster ? 16 + 32 + 4 + 8 + 1 : 0)) +
+    h->bytes = (int64_t)nodes * (16 + (cluster ? 16 + 8 + 32 + 4 + 8 + 1 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
@@ -249,6 +251,7 @@ void pndf_destroy_hierarchy(pndf_hier* h)
     (void)hipFree(h->clu_e);
     (void)hipFree(h->clu_det);
     (void)hipFree(h->clu_deg);
+    (void)hipFree(h->bbox_h);
     mesh_release(h->mesh);
     delete h;
 }

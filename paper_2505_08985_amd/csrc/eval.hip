@@ -397,6 +397,15 @@ __device__ __forceinline__ void queue_hits(uint32_t* hq, int& hn, uint32_t& pend
     wave_sync();
 }
 
+// A box stored as four halves (min x, min y | max x, max y).
+__device__ __forceinline__ float4 half_box(uint2 v)
+{
+    return make_float4(__half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(v.x >> 16))),
+                       __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(v.y >> 16))));
+}
+
 __device__ __forceinline__ bool in_box(const QuerySetup& q, const float4& bb)
 {
     return q.hx >= bb.x && q.hy >= bb.y && q.hx <= bb.z && q.hy <= bb.w;
@@ -437,7 +446,8 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         bool ok = root_ok;
         if (ok && !roots_tested) {
             acc.nodes += 1;
-            ok = in_box(q, boxes[level_offset(H.logn, root_level) + (root_item & kCodeMask)]);
+            ok = CUT ? in_box(q, half_box(H.bbox_h[level_offset(H.logn, root_level) + (root_item & kCodeMask)]))
+                     : in_box(q, boxes[level_offset(H.logn, root_level) + (root_item & kCodeMask)]);
         }
         const uint64_t bal = __ballot(ok);
         const int pos = __popcll(bal & ((1ull << lane) - 1ull));
@@ -554,8 +564,18 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             } else {
                 // the four child boxes are one 64-byte Morton segment: loaded whole (no
                 // extra traffic), children outside the support masked afterwards
-                const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
-                const float4 b0 = cb[0], b1 = cb[1], b2 = cb[2], b3 = cb[3];
+                float4 b0, b1, b2, b3;
+                if (CUT) {
+                    // the half-precision boxes (rounded outward): 32 B for the four
+                    const uint4* hb =
+                        reinterpret_cast<const uint4*>(H.bbox_h + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
+                    const uint4 h01 = hb[0], h23 = hb[1];
+                    b0 = half_box(make_uint2(h01.x, h01.y)); b1 = half_box(make_uint2(h01.z, h01.w));
+                    b2 = half_box(make_uint2(h23.x, h23.y)); b3 = half_box(make_uint2(h23.z, h23.w));
+                } else {
+                    const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
+                    b0 = cb[0]; b1 = cb[1]; b2 = cb[2]; b3 = cb[3];
+                }
                 if (CUT) {
                     // the children's residuals: 16 B at a multiple of 4 nodes
                     const float4 ce = *reinterpret_cast<const float4*>(H.clu_e + level_offset(H.logn, l - 1) + 4 * (int64_t)m);

@@ -330,6 +330,20 @@ hipError_t export_rowmajor(const void* src, void* dst, int m, int words, hipStre
     return hipGetLastError();
 }
 
+// The cut traversal's boxes in half precision, minima rounded down and maxima up: a
+// rounded box contains the exact one, so it prunes a little less but never wrongly,
+// and a parent's four child boxes take 32 B instead of 64 (the traversal under the
+// cut is bound by memory traffic; the float32 boxes stay for the exports).
+__global__ void k_half_boxes(const float4* __restrict__ src, uint2* __restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 b = src[i];
+    const uint32_t x0 = __half_as_ushort(__float2half_rd(b.x)), y0 = __half_as_ushort(__float2half_rd(b.y));
+    const uint32_t x1 = __half_as_ushort(__float2half_ru(b.z)), y1 = __half_as_ushort(__float2half_ru(b.w));
+    dst[i] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+}
+
 hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
 {
     const HierDev& H = h->dev;
@@ -369,6 +383,11 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
         hipLaunchKernelGGL(k_level_up, dim3((unsigned)((m + bs - 1) / bs)), dim3(bs), 0, s, H,
                            level, out_for(level), h->bbox + coff,
                            h->cluster ? h->bbox_all + coff : nullptr, cm, om, h->cluster);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess && h->cluster) {
+        hipLaunchKernelGGL(k_half_boxes, dim3((unsigned)((h->nodes + 255) / 256)), dim3(256), 0, s, h->bbox_all,
+                           h->bbox_h, h->nodes);
         err = hipGetLastError();
     }
     if (err == hipSuccess) err = hipStreamSynchronize(s);

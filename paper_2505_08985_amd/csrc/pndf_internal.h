@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
 #include <atomic>
 #include <cstdint>
@@ -51,6 +52,7 @@ struct HierDev {
     const float2* det;      // n x n Jacobians used by the evaluation (lower, upper)
     const float4* bbox;     // all levels packed: min x, min y, max x, max y (map triangles)
     const float4* bbox_all; // same, extended by cluster triangles (nullptr without clusters)
+    const uint2* bbox_h;    // bbox_all as halves rounded outward (min down, max up): the cut traversal's boxes
     const float4* clu_n;    // 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x, N2.y, N3.x, N3.y)
     const float* clu_e;     // e^l per node
     const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
@@ -191,6 +193,7 @@ struct pndf_hier {
     int64_t nodes = 0;
     float4* bbox = nullptr;
     float4* bbox_all = nullptr;
+    uint2* bbox_h = nullptr;
     float4* clu_n = nullptr;
     float* clu_e = nullptr;
     float2* clu_det = nullptr;
