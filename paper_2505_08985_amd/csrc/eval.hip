@@ -429,7 +429,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 {
     static_assert(!SPAWN || MODE == kModeValue, "donation is only used by value-mode workers");
     const int lane = threadIdx.x & 63;
-    const float4* __restrict__ boxes = CUT ? H.bbox_all : H.bbox;
+    const float4* __restrict__ boxes = H.bbox;  // (the cut traversal reads H.bbox_h)
     uint32_t* hq = lists + H.L * kListCap;  // hit queue
     int hn = 0;                             // queued hits (wave-uniform)
     uint32_t pend = 0, ebase = 0;           // this lane's float32 hits not yet queued
@@ -562,11 +562,12 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 pend = leaf_quad_mask(H, q, m, inside, rx0, ry0, acc);
                 ebase = m << 3;
             } else {
-                // the four child boxes are one 64-byte Morton segment: loaded whole (no
-                // extra traffic), children outside the support masked afterwards
+                // the four child boxes are one Morton segment (64 B, or 32 B in half
+                // precision under the cut): loaded whole (no extra traffic), children
+                // outside the support masked afterwards
                 float4 b0, b1, b2, b3;
                 if (CUT) {
-                    // the half-precision boxes (rounded outward): 32 B for the four
+                    // the boxes of map and cluster triangles, as halves rounded outward
                     const uint4* hb =
                         reinterpret_cast<const uint4*>(H.bbox_h + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
                     const uint4 h01 = hb[0], h23 = hb[1];
