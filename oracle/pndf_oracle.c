@@ -374,6 +374,13 @@ typedef struct {
  * inclusion of a hit point can flip under rounding (flags bit 1) */
 #define OR_KERNEL_BAND 1e-9
 
+/* relative band around the cut threshold t within which a cut decision can flip
+ * between two independent FP64 cluster fits: both agree to far better than float32
+ * precision, so their float32 residuals differ by at most one unit in the last
+ * place, and the decision fl32(e) <= t can differ only when fl32(e) is t or its
+ * neighbour: |fl32(e) - t| <= ulp(t) <= 2^-23 t.  The band is 2^-22 (flags bit 0). */
+#define OR_CUT_BAND 2.384185791015625e-7
+
 typedef struct {
     double D;
     long nhit, namb;
@@ -527,6 +534,23 @@ static void test_cell(const map_t* m, const query_t* q, acc_t* acc, long i, long
     }
 }
 
+/* Band around eps s^2 within which the clamp decision of a cluster triangle with
+ * float32 vertices nv can flip when its normals move by one float32 unit in the
+ * last place (two independent fits agree to far better than float32 precision,
+ * so their rounded normals differ by at most that): each coordinate moves by at
+ * most d = 2^-23 max|coordinate|, the edge vectors by 2d per component, the cross
+ * product by at most 2d (|c - a|_1 + |b - a|_1) + 4 d^2; twice that is the band. */
+static double clamp_band(const double nv[3][2])
+{
+    double mx = 0.0;
+    for (int k = 0; k < 3; k++)
+        for (int c = 0; c < 2; c++) mx = fmax(mx, fabs(nv[k][c]));
+    double d = 1.1920928955078125e-7 * mx;
+    double e1 = fabs(nv[2][0] - nv[0][0]) + fabs(nv[2][1] - nv[0][1]);
+    double e2 = fabs(nv[1][0] - nv[0][0]) + fabs(nv[1][1] - nv[0][1]);
+    return 2.0 * (2.0 * d * (e1 + e2) + 4.0 * d * d);
+}
+
 /* the two cluster triangles of node (level, I, J): corners at spacing s, normals
  * from the cluster fit; Jacobian with respect to u is 2 area_n / s^2, clamped at
  * eps with an equilateral triangle of area eps s^2 / 2 */
@@ -538,8 +562,9 @@ static void test_cluster(const map_t* m, const query_t* q, acc_t* acc, int level
     double N[4][2];
     for (int k = 0; k < 4; k++) { N[k][0] = cn[2 * k]; N[k][1] = cn[2 * k + 1]; }
     double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
+    const double s2 = (double)s * (double)s;
     for (int half = 0; half < 2; half++) {
-        double nv[3][2], uv[3][2];
+        double nv[3][2], uv[3][2], eq[3][2];
         double X0 = (double)(I * s), Y0 = (double)(J * s), X1 = X0 + s, Y1 = Y0 + s;
         if (half == 0) {
             memcpy(nv[0], N[0], sizeof nv[0]); memcpy(nv[1], N[1], sizeof nv[0]);
@@ -550,12 +575,23 @@ static void test_cluster(const map_t* m, const query_t* q, acc_t* acc, int level
             memcpy(nv[2], N[1], sizeof nv[0]);
             uv[0][0] = X1; uv[0][1] = Y1; uv[1][0] = X0; uv[1][1] = Y1; uv[2][0] = X1; uv[2][1] = Y0;
         }
-        double du = jac(nv[0], nv[1], nv[2]) / ((double)s * (double)s);
-        if (du < m->eps) {
-            eqtri(centre, eq_rho(0.5 * m->eps * (double)s * (double)s), nv);
-            du = m->eps;
+        double jn = jac(nv[0], nv[1], nv[2]);
+        double du = jn / s2;
+        eqtri(centre, eq_rho(0.5 * m->eps * s2), eq);
+        if (fabs(jn - m->eps * s2) <= clamp_band(nv)) {
+            /* the clamp decision is within rounding: it matters if either version of
+             * the triangle holds a hit or an edge-ambiguous query normal */
+            acc_t a, b;
+            memset(&a, 0, sizeof a);
+            memset(&b, 0, sizeof b);
+            test_tri(m, q, &a, OR_ID(level, I, J, half), nv, uv, du, I, J, s);
+            test_tri(m, q, &b, OR_ID(level, I, J, half), eq, uv, m->eps, I, J, s);
+            if (a.nhit || a.namb || b.nhit || b.namb) acc->flags |= 1;
         }
-        test_tri(m, q, acc, OR_ID(level, I, J, half), nv, uv, du, I, J, s);
+        if (du < m->eps)
+            test_tri(m, q, acc, OR_ID(level, I, J, half), eq, uv, m->eps, I, J, s);
+        else
+            test_tri(m, q, acc, OR_ID(level, I, J, half), nv, uv, du, I, J, s);
     }
 }
 
@@ -578,7 +614,7 @@ static void descend(const map_t* m, const query_t* q, acc_t* acc, int level, lon
     long mm = m->n >> level;
     float e = m->clu_e[level_offset(m->n, level) + J * mm + I];
     double de = (double)e - (double)q->t;
-    if (fabs(de) <= 1e-5 * fabs((double)q->t)) {
+    if (fabs(de) <= OR_CUT_BAND * fabs((double)q->t)) {
         /* the decision sits within rounding of the threshold; it can change the
          * result only if one of its two outcomes (this node's cluster triangles,
          * or the cut beneath it) holds a hit or an edge-ambiguous triangle */
@@ -671,8 +707,10 @@ static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
  *  D[k]      the P-NDF value (NaN for an invalid query: non-finite input, sigma <= 0,
  *            |x|, |y| or r above 2^24)
  *  nhit[k]   number of hit triangles, namb[k] number of triangles within `band` of h
- *  flags[k]  bit0 = some cut decision is within 1e-5 relative of the threshold and
- *            one of its two outcomes holds a hit or an edge-ambiguous triangle;
+ *  flags[k]  bit0 = some cut decision is within 2^-22 relative of the threshold and
+ *            one of its two outcomes holds a hit or an edge-ambiguous triangle, or a
+ *            cluster triangle's clamp decision is within rounding of eps and one of
+ *            its two versions is hit or edge-ambiguous;
  *            bit1 = (disk / box) a hit point lies within 1e-9 relative of the support edge
  * kernel: 0 Gaussian (sigma the standard deviation, support r = s2r sigma), 1 disk
  * (the ellipse of half-axes r), 2 box (|u - x| <= r per axis); disk and box are
@@ -815,7 +853,7 @@ static double trunc_gauss(double x, double sig, double a, double b, double xi)
 }
 
 /* the unit of the cut that contains u: level (0 = a cell) and its torus node;
- * flag bit0 when a decision on the way is within 1e-5 relative of t */
+ * flag bit0 when a decision on the way is within 2^-22 relative of t */
 static int cut_unit(const map_t* m, const query_t* q, const double u[2], long* I, long* J, int* flag)
 {
     if (q->use_cut)
@@ -823,7 +861,7 @@ static int cut_unit(const map_t* m, const query_t* q, const double u[2], long* I
             long s = 1L << l, mm = m->n >> l;
             long Il = wrap((long)floor(u[0] / (double)s), mm), Jl = wrap((long)floor(u[1] / (double)s), mm);
             float e = m->clu_e[level_offset(m->n, l) + Jl * mm + Il];
-            if (fabs((double)e - (double)q->t) <= 1e-5 * fabs((double)q->t)) *flag |= 1;
+            if (fabs((double)e - (double)q->t) <= OR_CUT_BAND * fabs((double)q->t)) *flag |= 1;
             if (e <= q->t) { *I = Il; *J = Jl; return l; }
         }
     *I = wrap((long)floor(u[0]), m->n);
@@ -874,8 +912,11 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
         memcpy(nv[0], N[3], sizeof nv[0]); memcpy(nv[1], N[2], sizeof nv[0]); memcpy(nv[2], N[1], sizeof nv[0]);
         w[0] = U + V - 1.0; w[1] = 1.0 - U; w[2] = 1.0 - V;
     }
-    /* the clamp of the evaluation (test_cell / test_cluster): Jacobian per unit uv area */
-    if (jac(nv[0], nv[1], nv[2]) / (s * s) < m->eps) {
+    /* the clamp of the evaluation (test_cell / test_cluster): Jacobian per unit uv area;
+     * a cluster's decision within rounding of eps is flagged as in the evaluation */
+    const double jn = jac(nv[0], nv[1], nv[2]);
+    if (level > 0 && fabs(jn - m->eps * s * s) <= clamp_band(nv)) *flag |= 1;
+    if (jn / (s * s) < m->eps) {
         double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
         eqtri(centre, eq_rho(0.5 * m->eps * s * s), nv);
     }
@@ -889,7 +930,8 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
  * xi: attempts pairs of uniforms in [0, 1) per query, row-major (nq x 2 attempts).
  * Outputs: u (2 per query, unrolled texture coordinates), m (2 per query), tri
  * (triangle id as in the evaluation's hit lists), flags: bit0 a cut decision on
- * the way within 1e-5 relative of t; bit1 u within `band` of a unit edge or
+ * the way within 2^-22 relative of t, or a cluster clamp decision within rounding
+ * of eps; bit1 u within `band` of a unit edge or
  * diagonal (the triangle may differ under rounding) or of the rejection
  * boundary; bit2 every attempt was rejected (m = NaN).  Invalid queries, or a
  * pair of uniforms outside [0, 1) among those used, give NaN with tri = ~0.
