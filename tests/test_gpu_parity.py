@@ -134,6 +134,30 @@ def triangle_boxes(nrm, deg, rho):
     return lo, hi
 
 
+def check_cluster_fit(ex, ns, e, m, level):
+    """The GPU fit of one level against the oracle's FP64 fit (Eq. normal_optimization,
+    e^l its minimised value).  Both are FP64 fits of the same objective that agree to
+    far better than float32 precision, so the stored float32 values may differ from
+    the rounded oracle values by at most one unit in the last place (rounding of
+    values that sit next to a rounding boundary); residuals below 1e-12 of the
+    level's largest (fits that are exact up to rounding) are compared absolutely."""
+    gn = ex["clu_n"].cpu().numpy().reshape(m * m, 4, 2)
+    ge = ex["clu_e"].cpu().numpy().reshape(m * m)
+    scale = float(np.abs(ns).max()) + 1e-30
+    n32 = ns.astype(np.float32)
+    dn = np.abs(gn.astype(np.float64) - ns)
+    assert (dn <= np.spacing(np.abs(n32)).astype(np.float64) + 1e-12 * scale).all(), \
+        (level, float(dn.max()), float((gn != n32).sum()))
+    emax = float(e.max()) + 1e-300
+    big = e > 1e-12 * emax
+    e32 = e.astype(np.float32)
+    de = np.abs(ge.astype(np.float64) - e32.astype(np.float64))
+    assert (de[big] <= np.spacing(e32[big]).astype(np.float64)).all(), (level, float((de[big] / e[big]).max()))
+    assert (np.abs(ge[~big].astype(np.float64) - e[~big]) <= 1e-12 * emax).all(), level
+    print("level %d: float32 N* differ in %d of %d, e^l in %d of %d (largest residuals)"
+          % (level, int((gn != n32).sum()), gn.size, int((ge[big] != e32[big]).sum()), int(big.sum())))
+
+
 @pytest.mark.parametrize("name", sorted(MAPS))
 def test_hierarchy_boxes_and_clusters(P, oracle_mod, name):
     announce("hierarchy build %s" % name)
@@ -156,13 +180,7 @@ def test_hierarchy_boxes_and_clusters(P, oracle_mod, name):
         assert (box[..., 2] >= hi[..., 0]).all() and (box[..., 3] >= hi[..., 1]).all()
         assert (box[..., 0] >= lo[..., 0] - 2e-6).all() and (box[..., 2] <= hi[..., 0] + 2e-6).all()
         ns, e = oracle_mod.cluster_level(nrm, level)
-        gn = ex["clu_n"].cpu().numpy().reshape(m * m, 4, 2).astype(np.float64)
-        ge = ex["clu_e"].cpu().numpy().reshape(m * m).astype(np.float64)
-        scale = np.abs(ns).max() + 1e-3
-        np.testing.assert_allclose(gn, ns, rtol=0, atol=2e-6 * scale)
-        rel = np.abs(ge - e) / np.maximum(np.abs(e), 1e-300)
-        print("level %d: max rel diff of e %.3g, of N* %.3g" % (level, rel.max(), np.abs(gn - ns).max()))
-        np.testing.assert_allclose(ge, e, rtol=2e-5, atol=1e-9 * (np.abs(e).max() + 1e-30))
+        check_cluster_fit(ex, ns, e, m, level)
         # cluster boxes cover the cluster triangles
         ball = ex["bbox_all"].cpu().numpy()
         assert (ball[..., 0] <= box[..., 0]).all() and (ball[..., 2] >= box[..., 2]).all()
