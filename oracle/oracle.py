@@ -45,16 +45,16 @@ def load():
                                      ctypes.c_int64, _dp, _dp]
     lib.or_fine_contrib.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     _dp, _dp, _dp, _dp]
-    lib.or_eval.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, _fp, _fp, ctypes.c_int64,
+    lib.or_eval.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, _dp, _fp, ctypes.c_int64,
                             ctypes.c_float, ctypes.c_float, ctypes.c_double,
                             _dp, _i64p, _i64p, _i32p,
                             _i64p, _u64p, _dp, _i64p, _u64p, _dp, _u8p]
-    lib.or_eval_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, _fp, _fp, ctypes.c_int64,
+    lib.or_eval_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, _dp, _fp, ctypes.c_int64,
                               ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_int,
                               _dp, _i64p, _i64p, _i32p,
                               _i64p, _u64p, _dp, _i64p, _u64p, _dp, _u8p]
     lib.or_sample_normals.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, ctypes.c_int64, _dp]
-    lib.or_sample_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, _fp, _fp, _dp, ctypes.c_int64,
+    lib.or_sample_k.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _dp, _dp, _fp, _dp, ctypes.c_int64,
                                 ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_int,
                                 _dp, _dp, _u64p, _i32p]
     lib.or_projected_area.argtypes = [ctypes.c_int, _fp, ctypes.c_float, _fp, ctypes.c_int64, ctypes.c_float,
@@ -116,20 +116,32 @@ def cluster_level(nrm, level, eps=1e-6, ids=None):
 
 
 def cluster_all(nrm, eps=1e-6):
-    """Every level's cluster fit.  Returns dict with per-level FP64 arrays and the
-    packed float32 arrays (levels 1..L, row-major nodes) that `evaluate` takes."""
+    """Every level's cluster fit.  Returns a dict: `levels` {l: (nstar (m*m, 4, 2),
+    e (m*m,)) FP64, row-major nodes}, views into the packed FP64 arrays `clu_n64`
+    (8 per node) and `clu_e64` (levels 1..L), which `evaluate` and `sample` take
+    (they decide on the float32 roundings, as a stored hierarchy does), and those
+    roundings `clu_n`, `clu_e` (float32)."""
     nrm = _map(nrm)
     n = nrm.shape[0]
     L = int(np.log2(n))
+    total = sum((n >> l) ** 2 for l in range(1, L + 1))
+    clu_n64 = np.empty(total * 8, dtype=np.float64)
+    clu_e64 = np.empty(total, dtype=np.float64)
     levels = {}
-    packed_n, packed_e = [], []
+    off = 0
+    lib = load()
     for l in range(1, L + 1):
-        ns, e = cluster_level(nrm, l, eps)
+        m = (n >> l) ** 2
+        ns = clu_n64[8 * off:8 * (off + m)].reshape(m, 4, 2)
+        e = clu_e64[off:off + m]
+        ids = np.arange(m, dtype=np.int64)
+        rc = lib.or_cluster_nodes(n, _p(nrm, _fp), eps, l, _p(ids, _i64p), m, _p(ns, _dp), _p(e, _dp))
+        if rc:
+            raise ValueError("or_cluster_nodes failed (%d)" % rc)
         levels[l] = (ns, e)
-        packed_n.append(ns.astype(np.float32).reshape(-1))
-        packed_e.append(e.astype(np.float32))
-    return dict(levels=levels, clu_n=np.ascontiguousarray(np.concatenate(packed_n)),
-                clu_e=np.ascontiguousarray(np.concatenate(packed_e)))
+        off += m
+    return dict(levels=levels, clu_n64=clu_n64, clu_e64=clu_e64,
+                clu_n=clu_n64.astype(np.float32), clu_e=clu_e64.astype(np.float32))
 
 
 def fine_contrib(a, i, j, half, nv):
@@ -161,14 +173,14 @@ def evaluate(nrm, queries, tau=0.0, eps=1e-6, sigma_to_r=3.0, band=1e-6, cluster
     nq = q.shape[0]
     if tau > 0 and clusters is None:
         clusters = cluster_all(nrm, eps)
-    cn = clusters["clu_n"] if clusters is not None else None
-    ce = clusters["clu_e"] if clusters is not None else None
+    cn = clusters["clu_n64"] if clusters is not None else None
+    ce = clusters["clu_e64"] if clusters is not None else None
     D = np.empty(nq, dtype=np.float64)
     nhit = np.empty(nq, dtype=np.int64)
     namb = np.empty(nq, dtype=np.int64)
     flags = np.empty(nq, dtype=np.int32)
     lib = load()
-    args = [n, _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp), nq, tau, sigma_to_r,
+    args = [n, _p(nrm, _fp), eps, _p(cn, _dp), _p(ce, _dp), _p(q, _fp), nq, tau, sigma_to_r,
             band, kid, _p(D, _dp), _p(nhit, _i64p), _p(namb, _i64p), _p(flags, _i32p)]
     rc = lib.or_eval_k(*args, None, None, None, None, None, None, None)
     if rc:
@@ -186,7 +198,7 @@ def evaluate(nrm, queries, tau=0.0, eps=1e-6, sigma_to_r=3.0, band=1e-6, cluster
     aterm = np.zeros(max(1, aoff[-1]), dtype=np.float64)
     ahit = np.zeros(max(1, aoff[-1]), dtype=np.uint8)
     D2 = np.empty(nq, dtype=np.float64)
-    rc = lib.or_eval_k(n, _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp), nq, tau,
+    rc = lib.or_eval_k(n, _p(nrm, _fp), eps, _p(cn, _dp), _p(ce, _dp), _p(q, _fp), nq, tau,
                      sigma_to_r, band, kid, _p(D2, _dp), _p(nhit, _i64p), _p(namb, _i64p),
                      _p(flags, _i32p), _p(hoff, _i64p), _p(hid, _u64p), _p(hterm, _dp),
                      _p(aoff, _i64p), _p(aid, _u64p), _p(aterm, _dp), _p(ahit, _u8p))
@@ -216,7 +228,8 @@ def sample(nrm, queries, xi, tau=0.0, eps=1e-6, sigma_to_r=3.0, kernel="gaussian
     """Draw one sample of the P-NDF per query (Q, 6) float32 (x, y, sx, sy used)
     from the uniforms xi (Q, 2 * attempts) float64 in [0, 1).  Returns dict u (Q, 2)
     unrolled texture coordinates, m (Q, 2) sampled normals, tri (Q,) triangle ids,
-    flags (Q,): bit0 a cut decision within 1e-5 of the threshold, bit1 u within
+    flags (Q,): bit0 a cut or cluster clamp decision that another FP64 fit could take
+    differently after float32 rounding, bit1 u within
     `band` of a unit edge / diagonal, bit2 every attempt rejected."""
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     nrm = _map(nrm)
@@ -227,13 +240,13 @@ def sample(nrm, queries, xi, tau=0.0, eps=1e-6, sigma_to_r=3.0, kernel="gaussian
     assert xi.shape[1] == 2 * attempts and attempts >= 1
     if tau > 0 and clusters is None:
         clusters = cluster_all(nrm, eps)
-    cn = clusters["clu_n"] if clusters is not None else None
-    ce = clusters["clu_e"] if clusters is not None else None
+    cn = clusters["clu_n64"] if clusters is not None else None
+    ce = clusters["clu_e64"] if clusters is not None else None
     u = np.empty((nq, 2))
     m = np.empty((nq, 2))
     tri = np.empty(nq, dtype=np.uint64)
     flags = np.empty(nq, dtype=np.int32)
-    rc = load().or_sample_k(nrm.shape[0], _p(nrm, _fp), eps, _p(cn, _fp), _p(ce, _fp), _p(q, _fp),
+    rc = load().or_sample_k(nrm.shape[0], _p(nrm, _fp), eps, _p(cn, _dp), _p(ce, _dp), _p(q, _fp),
                             _p(xi, _dp), nq, attempts, tau, sigma_to_r, band, kid,
                             _p(u, _dp), _p(m, _dp), _p(tri, _u64p), _p(flags, _i32p))
     if rc:

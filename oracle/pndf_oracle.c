@@ -348,8 +348,9 @@ typedef struct {
     int n, L;
     const float* nrm;
     double eps;
-    const float* clu_n; /* all levels 1..L packed, 8 floats per node (oracle's own fit, rounded) */
-    const float* clu_e; /* all levels 1..L packed, 1 float per node */
+    const double* clu_n; /* all levels 1..L packed, 8 FP64 values per node (the oracle's own fit) */
+    const double* clu_e; /* all levels 1..L packed, 1 FP64 value per node */
+    double emax[32];     /* largest e^l of each level */
 } map_t;
 
 static long level_offset(int n, int level) /* first node of `level` in packed arrays */
@@ -374,12 +375,15 @@ typedef struct {
  * inclusion of a hit point can flip under rounding (flags bit 1) */
 #define OR_KERNEL_BAND 1e-9
 
-/* relative band around the cut threshold t within which a cut decision can flip
- * between two independent FP64 cluster fits: both agree to far better than float32
- * precision, so their float32 residuals differ by at most one unit in the last
- * place, and the decision fl32(e) <= t can differ only when fl32(e) is t or its
- * neighbour: |fl32(e) - t| <= ulp(t) <= 2^-23 t.  The band is 2^-22 (flags bit 0). */
-#define OR_CUT_BAND 2.384185791015625e-7
+/* Agreement of two independent FP64 fits of the cluster objective (the same
+ * definition summed in different orders), used to flag the decisions that their
+ * float32-rounded values could take differently (flags bit 0): e^l to 1e-10
+ * relative plus 1e-20 of the level's largest e^l (for fits that are exact up to
+ * rounding), the normals to 1e-10 absolute.  Measured agreement is ~1e-13 and
+ * ~1e-12; the GPU tests check these bounds node by node. */
+#define OR_FIT_E_REL 1e-10
+#define OR_FIT_E_ABS 1e-20
+#define OR_FIT_N_ABS 1e-10
 
 typedef struct {
     double D;
@@ -393,6 +397,39 @@ typedef struct {
 
 #define OR_ID(l, I, J, half) \
     (((uint64_t)(l) << 58) | ((uint64_t)(J) << 29) | ((uint64_t)(I) << 1) | (uint64_t)(half))
+
+/* Could two fits within the agreement bound take the cut decision fl32(e) <= t
+ * differently?  fl32(x) <= t exactly when x lies at or below the midpoint between
+ * t and the next float32 (up to the tie), so only when e is that close to it. */
+static int cut_may_flip(const map_t* m, int level, double e, float t)
+{
+    const double mid = 0.5 * ((double)t + (double)nextafterf(t, INFINITY));
+    const double w = OR_FIT_E_REL * fabs(e) + OR_FIT_E_ABS * m->emax[level];
+    return fabs(e - mid) <= w;
+}
+
+/* Could the float32 rounding of a fitted normal component differ between two fits
+ * within OR_FIT_N_ABS of each other: is a rounding midpoint that close to it? */
+static int round_may_differ(double x)
+{
+    const float f = (float)x;
+    const double lo = 0.5 * ((double)f + (double)nextafterf(f, -INFINITY));
+    const double hi = 0.5 * ((double)f + (double)nextafterf(f, INFINITY));
+    return fabs(x - lo) <= OR_FIT_N_ABS || fabs(x - hi) <= OR_FIT_N_ABS;
+}
+
+/* largest e^l of every level (for the absolute part of the agreement bound) */
+static void level_emax(map_t* m)
+{
+    for (int l = 0; l < 32; l++) m->emax[l] = 0.0;
+    if (!m->clu_e) return;
+    for (int l = 1; l <= m->L; l++) {
+        const long off = level_offset(m->n, l), cnt = (long)(m->n >> l) * (m->n >> l);
+        double mx = 0.0;
+        for (long k = 0; k < cnt; k++) mx = fmax(mx, m->clu_e[off + k]);
+        m->emax[l] = mx;
+    }
+}
 
 /* images p along one axis for a node of side s starting at torus cell `start`:
  * the node's closed square [start + pN, start + s + pN] meets the box iff one of
@@ -537,7 +574,8 @@ static void test_cell(const map_t* m, const query_t* q, acc_t* acc, long i, long
 /* Band around eps s^2 within which the clamp decision of a cluster triangle with
  * float32 vertices nv can flip when its normals move by one float32 unit in the
  * last place (two independent fits agree to far better than float32 precision,
- * so their rounded normals differ by at most that): each coordinate moves by at
+ * so their rounded normals differ by at most that, and only where a normal lies
+ * next to a rounding midpoint): each coordinate moves by at
  * most d = 2^-23 max|coordinate|, the edge vectors by 2d per component, the cross
  * product by at most 2d (|c - a|_1 + |b - a|_1) + 4 d^2; twice that is the band. */
 static double clamp_band(const double nv[3][2])
@@ -558,9 +596,14 @@ static void test_cluster(const map_t* m, const query_t* q, acc_t* acc, int level
 {
     const long s = 1L << level;
     const long mm = m->n >> level;
-    const float* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * mm + I);
+    const double* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * mm + I);
     double N[4][2];
-    for (int k = 0; k < 4; k++) { N[k][0] = cn[2 * k]; N[k][1] = cn[2 * k + 1]; }
+    int near = 0; /* could another fit's float32 normals differ from these? */
+    for (int k = 0; k < 4; k++)
+        for (int c = 0; c < 2; c++) {
+            N[k][c] = (double)(float)cn[2 * k + c];
+            near |= round_may_differ(cn[2 * k + c]);
+        }
     double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
     const double s2 = (double)s * (double)s;
     for (int half = 0; half < 2; half++) {
@@ -578,7 +621,7 @@ static void test_cluster(const map_t* m, const query_t* q, acc_t* acc, int level
         double jn = jac(nv[0], nv[1], nv[2]);
         double du = jn / s2;
         eqtri(centre, eq_rho(0.5 * m->eps * s2), eq);
-        if (fabs(jn - m->eps * s2) <= clamp_band(nv)) {
+        if (near && fabs(jn - m->eps * s2) <= clamp_band(nv)) {
             /* the clamp decision is within rounding: it matters if either version of
              * the triangle holds a hit or an edge-ambiguous query normal */
             acc_t a, b;
@@ -612,9 +655,9 @@ static void descend(const map_t* m, const query_t* q, acc_t* acc, int level, lon
     if (!node_in(q, m->n, level, I, J)) return;
     if (level == 0) { test_cell(m, q, acc, I, J); return; }
     long mm = m->n >> level;
-    float e = m->clu_e[level_offset(m->n, level) + J * mm + I];
-    double de = (double)e - (double)q->t;
-    if (fabs(de) <= OR_CUT_BAND * fabs((double)q->t)) {
+    const double e64 = m->clu_e[level_offset(m->n, level) + J * mm + I];
+    const float e = (float)e64;
+    if (cut_may_flip(m, level, e64, q->t)) {
         /* the decision sits within rounding of the threshold; it can change the
          * result only if one of its two outcomes (this node's cluster triangles,
          * or the cut beneath it) holds a hit or an edge-ambiguous triangle */
@@ -707,10 +750,10 @@ static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
  *  D[k]      the P-NDF value (NaN for an invalid query: non-finite input, sigma <= 0,
  *            |x|, |y| or r above 2^24)
  *  nhit[k]   number of hit triangles, namb[k] number of triangles within `band` of h
- *  flags[k]  bit0 = some cut decision is within 2^-22 relative of the threshold and
- *            one of its two outcomes holds a hit or an edge-ambiguous triangle, or a
- *            cluster triangle's clamp decision is within rounding of eps and one of
- *            its two versions is hit or edge-ambiguous;
+ *  flags[k]  bit0 = a cut decision that another FP64 fit (within the agreement
+ *            bound above) could take differently after float32 rounding, with a hit or
+ *            an edge-ambiguous triangle in one of its two outcomes; or likewise a
+ *            cluster triangle's clamp decision, with either version hit or ambiguous;
  *            bit1 = (disk / box) a hit point lies within 1e-9 relative of the support edge
  * kernel: 0 Gaussian (sigma the standard deviation, support r = s2r sigma), 1 disk
  * (the ellipse of half-axes r), 2 box (|u - x| <= r per axis); disk and box are
@@ -718,9 +761,10 @@ static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
  * k_r is zero beyond r), the cells included are those meeting the support box.
  * If hoff/aoff (prefix offsets from a previous counting call) are given, the
  * records are written: hit ids + terms, ambiguous ids + terms + hit flags.
- * tau > 0 requires clu_n / clu_e (all levels packed).
+ * tau > 0 requires clu_n / clu_e: the FP64 cluster fit, all levels packed (the
+ * evaluation uses their float32 roundings, as stored by a hierarchy).
  */
-int or_eval_k(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+int or_eval_k(int n, const float* nrm, float eps, const double* clu_n, const double* clu_e,
               const float* queries, int64_t nq, float tau, float s2r, double band, int kernel,
               double* D, int64_t* nhit, int64_t* namb, int32_t* flags,
               const int64_t* hoff, uint64_t* hid, double* hterm,
@@ -735,6 +779,7 @@ int or_eval_k(int n, const float* nrm, float eps, const float* clu_n, const floa
     m.eps = (double)eps;
     m.clu_n = clu_n;
     m.clu_e = clu_e;
+    level_emax(&m);
     if (tau > 0.0f && (!clu_n || !clu_e)) return 2;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < nq; k++) {
@@ -760,7 +805,7 @@ int or_eval_k(int n, const float* nrm, float eps, const float* clu_n, const floa
 }
 
 /* or_eval_k with the Gaussian footprint kernel */
-int or_eval(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+int or_eval(int n, const float* nrm, float eps, const double* clu_n, const double* clu_e,
             const float* queries, int64_t nq, float tau, float s2r, double band,
             double* D, int64_t* nhit, int64_t* namb, int32_t* flags,
             const int64_t* hoff, uint64_t* hid, double* hterm,
@@ -853,15 +898,16 @@ static double trunc_gauss(double x, double sig, double a, double b, double xi)
 }
 
 /* the unit of the cut that contains u: level (0 = a cell) and its torus node;
- * flag bit0 when a decision on the way is within 2^-22 relative of t */
+ * flag bit0 when another fit could take a decision on the way differently */
 static int cut_unit(const map_t* m, const query_t* q, const double u[2], long* I, long* J, int* flag)
 {
     if (q->use_cut)
         for (int l = q->l0; l >= 1; l--) {
             long s = 1L << l, mm = m->n >> l;
             long Il = wrap((long)floor(u[0] / (double)s), mm), Jl = wrap((long)floor(u[1] / (double)s), mm);
-            float e = m->clu_e[level_offset(m->n, l) + Jl * mm + Il];
-            if (fabs((double)e - (double)q->t) <= OR_CUT_BAND * fabs((double)q->t)) *flag |= 1;
+            const double e64 = m->clu_e[level_offset(m->n, l) + Jl * mm + Il];
+            const float e = (float)e64;
+            if (cut_may_flip(m, l, e64, q->t)) *flag |= 1;
             if (e <= q->t) { *I = Il; *J = Jl; return l; }
         }
     *I = wrap((long)floor(u[0]), m->n);
@@ -894,14 +940,19 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
     if (fabs(U + V - 1.0) < dmin) dmin = fabs(U + V - 1.0);
     if (dmin < band) *flag |= 2;
     double N[4][2];
+    int near = 0; /* could another fit's float32 normals differ from these? */
     if (level == 0) {
         texel(m->nrm, m->n, I, J, N[0]);
         texel(m->nrm, m->n, I + 1, J, N[1]);
         texel(m->nrm, m->n, I, J + 1, N[2]);
         texel(m->nrm, m->n, I + 1, J + 1, N[3]);
     } else {
-        const float* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * (m->n >> level) + I);
-        for (int k = 0; k < 4; k++) { N[k][0] = cn[2 * k]; N[k][1] = cn[2 * k + 1]; }
+        const double* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * (m->n >> level) + I);
+        for (int k = 0; k < 4; k++)
+            for (int c = 0; c < 2; c++) {
+                N[k][c] = (double)(float)cn[2 * k + c];
+                near |= round_may_differ(cn[2 * k + c]);
+            }
     }
     int half = U + V < 1.0 ? 0 : 1;
     double nv[3][2], w[3];
@@ -915,7 +966,7 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
     /* the clamp of the evaluation (test_cell / test_cluster): Jacobian per unit uv area;
      * a cluster's decision within rounding of eps is flagged as in the evaluation */
     const double jn = jac(nv[0], nv[1], nv[2]);
-    if (level > 0 && fabs(jn - m->eps * s * s) <= clamp_band(nv)) *flag |= 1;
+    if (near && fabs(jn - m->eps * s * s) <= clamp_band(nv)) *flag |= 1;
     if (jn / (s * s) < m->eps) {
         double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
         eqtri(centre, eq_rho(0.5 * m->eps * s * s), nv);
@@ -930,13 +981,13 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
  * xi: attempts pairs of uniforms in [0, 1) per query, row-major (nq x 2 attempts).
  * Outputs: u (2 per query, unrolled texture coordinates), m (2 per query), tri
  * (triangle id as in the evaluation's hit lists), flags: bit0 a cut decision on
- * the way within 2^-22 relative of t, or a cluster clamp decision within rounding
- * of eps; bit1 u within `band` of a unit edge or
+ * the way, or a cluster clamp decision, that another fit could take differently
+ * (as for the evaluation); bit1 u within `band` of a unit edge or
  * diagonal (the triangle may differ under rounding) or of the rejection
  * boundary; bit2 every attempt was rejected (m = NaN).  Invalid queries, or a
  * pair of uniforms outside [0, 1) among those used, give NaN with tri = ~0.
  */
-int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const float* clu_e,
+int or_sample_k(int n, const float* nrm, float eps, const double* clu_n, const double* clu_e,
                 const float* queries, const double* xi, int64_t nq, int attempts, float tau, float s2r,
                 double band, int kernel, double* uout, double* mout, uint64_t* tri, int32_t* flags)
 {
@@ -950,6 +1001,7 @@ int or_sample_k(int n, const float* nrm, float eps, const float* clu_n, const fl
     m.eps = (double)eps;
     m.clu_n = clu_n;
     m.clu_e = clu_e;
+    level_emax(&m);
     if (tau > 0.0f && (!clu_n || !clu_e)) return 2;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < nq; k++) {

@@ -570,34 +570,82 @@ def test_cut_threshold_rule(oracle_mod):
 
 
 def test_cut_ambiguity_flag_only_when_it_matters(oracle_mod):
-    """A cut decision within rounding of the threshold (e^l vs r_x r_y tau) is
-    flagged only when one of its outcomes (the node's cluster triangles, or the
+    """A cut decision fl32(e^l) <= t (e^l vs r_x r_y tau) that another FP64 fit,
+    within the stated agreement (1e-10 relative), could take differently after
+    float32 rounding -- e^l next to the midpoint between t and the next float32 --
+    is flagged only when one of its outcomes (the node's cluster triangles, or the
     cut beneath it) contributes a hit or an edge-ambiguous triangle: for a query
     normal far outside every normal of the map the two outcomes are both empty and
-    the decision is irrelevant; for the node's own mean normal it matters."""
+    the decision is irrelevant; for the node's own mean normal it matters.  A
+    residual 1e-6 away from that midpoint is decided the same way by any such fit
+    and is not flagged."""
     n = 8
     nrm = random_disk_map(n, 41, radius=0.35)
     clusters = oracle_mod.cluster_all(nrm)
     m = n // 2
-    ns, e = clusters["levels"][1]
+    L = 3
     I0, J0 = 1, 1
-    e0 = np.float32(e[J0 * m + I0])
+    k0 = J0 * m + I0                           # level 1 is the first packed level
+    e0 = float(clusters["clu_e64"][k0])
     s = np.float32(0.5)                        # r = 1.5: entry level 1, roots (1..2, 1..2)
     rr = np.float32(np.float32(3) * s) ** 2
-    tau = np.float32(e0 / rr)                  # threshold within float rounding of e0
-    t = np.float32(rr * tau)
-    assert abs(float(t) - float(e0)) <= 1e-5 * float(e0)
+    tau = np.float32(e0 / rr)
+    t = np.float32(rr * tau)                   # the threshold as the definition rounds it
+    mid = 0.5 * (float(t) + float(np.nextafter(t, np.float32(np.inf))))
     inside = nrm[2 * J0:2 * J0 + 2, 2 * I0:2 * I0 + 2].reshape(-1, 2).astype(np.float64).mean(0)
     qs = np.array([[4.0, 4.0, s, s, 0.95, 0.0],                    # no normal anywhere near
                    [4.0, 4.0, s, s, inside[0], inside[1]]], dtype=np.float32)
-    res = oracle_mod.evaluate(nrm, qs, tau=float(tau), clusters=clusters, records=True)
+
+    def with_e(value):
+        c = dict(clusters)
+        c["clu_e64"] = clusters["clu_e64"].copy()
+        c["clu_e64"][k0] = value
+        return c
+
+    res = oracle_mod.evaluate(nrm, qs, tau=float(tau), clusters=with_e(mid), records=True)
     assert res["nhit"][0] == 0 and res["namb"][0] == 0
     assert res["flags"][0] == 0
     assert res["nhit"][1] > 0
     assert res["flags"][1] & 1
-    # far from the threshold nothing is flagged, whatever h
-    res2 = oracle_mod.evaluate(nrm, qs, tau=float(tau) * 4, clusters=clusters)
-    assert not (res2["flags"] & 1).any()
+    # away from the midpoint (or far from the threshold) nothing is flagged, whatever h
+    for value, tt in ((mid * (1 + 1e-6), tau), (mid * (1 - 1e-6), tau), (mid, tau * 4)):
+        res2 = oracle_mod.evaluate(nrm, qs, tau=float(tt), clusters=with_e(value))
+        assert not (res2["flags"] & 1).any(), (value, tt)
+
+
+def test_cluster_clamp_flag_only_near_rounding(oracle_mod):
+    """A cluster triangle's clamp decision (2 area_n < eps 4^l) is flagged only when
+    another fit's float32 normals could differ from these (a fitted component next
+    to a float32 rounding midpoint) and the Jacobian is within what a one-ulp move
+    of the normals can change, with the triangle (or its replacement) hit."""
+    n = 8
+    nrm = random_disk_map(n, 43, radius=0.35)
+    clusters = oracle_mod.cluster_all(nrm)
+    m = n // 2
+    I0, J0 = 1, 1
+    k0 = J0 * m + I0
+    eps = np.float32(1e-6)
+    d = float(np.float32(np.sqrt(float(eps) * 4.0)))     # lower cluster triangle: Jacobian ~ eps 2^2
+    base = np.array([[0.25, 0.125], [0.25 + d, 0.125], [0.25, 0.125 + d], [0.3, 0.2]])
+    f = np.float32(0.3)
+    mid = 0.5 * (float(f) + float(np.nextafter(f, np.float32(np.inf))))
+    s = np.float32(0.5)
+    h = base[:3].mean(0)
+    qs = np.array([[2.0 * I0 + 1.0, 2.0 * J0 + 1.0, s, s, h[0], h[1]]], dtype=np.float32)
+
+    def run(n3x):
+        c = dict(clusters)
+        c["clu_n64"] = clusters["clu_n64"].copy()
+        N = base.copy()
+        N[3, 0] = n3x
+        c["clu_n64"][8 * k0:8 * k0 + 8] = N.reshape(-1)
+        return oracle_mod.evaluate(nrm, qs, tau=1e30, clusters=c, records=True)
+
+    near = run(mid)                      # a component sits on a rounding midpoint
+    assert near["nhit"][0] > 0 and near["flags"][0] & 1
+    far = run(0.3)                       # every component far from one: the same floats for any fit
+    assert not (far["flags"] & 1).any()
+    assert far["nhit"][0] == near["nhit"][0]
 
 
 # ----------------------------------------------------- disk and box footprints
