@@ -389,7 +389,8 @@ typedef struct {
     double D;
     long nhit, namb;
     int flags; /* bit0: a cut decision that matters sits within rounding of the threshold;
-                * bit1: a hit point sits within rounding of the disk / box support edge */
+                * bit1: a hit point sits within rounding of the disk / box support edge;
+                * bit2: a cluster clamp decision that matters sits within rounding */
     /* optional record buffers (NULL = count only) */
     uint64_t* hid; double* hterm;
     uint64_t* aid; double* aterm; uint8_t* ahit;
@@ -406,16 +407,6 @@ static int cut_may_flip(const map_t* m, int level, double e, float t)
     const double mid = 0.5 * ((double)t + (double)nextafterf(t, INFINITY));
     const double w = OR_FIT_E_REL * fabs(e) + OR_FIT_E_ABS * m->emax[level];
     return fabs(e - mid) <= w;
-}
-
-/* Could the float32 rounding of a fitted normal component differ between two fits
- * within OR_FIT_N_ABS of each other: is a rounding midpoint that close to it? */
-static int round_may_differ(double x)
-{
-    const float f = (float)x;
-    const double lo = 0.5 * ((double)f + (double)nextafterf(f, -INFINITY));
-    const double hi = 0.5 * ((double)f + (double)nextafterf(f, INFINITY));
-    return fabs(x - lo) <= OR_FIT_N_ABS || fabs(x - hi) <= OR_FIT_N_ABS;
 }
 
 /* largest e^l of every level (for the absolute part of the agreement bound) */
@@ -571,22 +562,39 @@ static void test_cell(const map_t* m, const query_t* q, acc_t* acc, long i, long
     }
 }
 
-/* Band around eps s^2 within which the clamp decision of a cluster triangle with
- * float32 vertices nv can flip when its normals move by one float32 unit in the
- * last place (two independent fits agree to far better than float32 precision,
- * so their rounded normals differ by at most that, and only where a normal lies
- * next to a rounding midpoint): each coordinate moves by at
- * most d = 2^-23 max|coordinate|, the edge vectors by 2d per component, the cross
- * product by at most 2d (|c - a|_1 + |b - a|_1) + 4 d^2; twice that is the band. */
-static double clamp_band(const double nv[3][2])
+/* Could another fit, whose normals round to float32 values within
+ * [fl32(x - 1e-10), fl32(x + 1e-10)] of this fit's FP64 normals x, take the clamp
+ * decision Jacobian < lim of the cluster triangle with FP64 vertices v (a, b, c)
+ * differently?  The Jacobian |(c - a) x (b - a)| over those intervals, by interval
+ * arithmetic (with a relative slack for its own FP64 rounding), must contain lim. */
+static void ivl_mul(double a0, double a1, double b0, double b1, double* lo, double* hi)
 {
-    double mx = 0.0;
+    double p[4] = {a0 * b0, a0 * b1, a1 * b0, a1 * b1};
+    *lo = *hi = p[0];
+    for (int k = 1; k < 4; k++) {
+        if (p[k] < *lo) *lo = p[k];
+        if (p[k] > *hi) *hi = p[k];
+    }
+}
+
+static int clamp_may_flip(const double v[3][2], double lim)
+{
+    double lo[3][2], hi[3][2];
     for (int k = 0; k < 3; k++)
-        for (int c = 0; c < 2; c++) mx = fmax(mx, fabs(nv[k][c]));
-    double d = 1.1920928955078125e-7 * mx;
-    double e1 = fabs(nv[2][0] - nv[0][0]) + fabs(nv[2][1] - nv[0][1]);
-    double e2 = fabs(nv[1][0] - nv[0][0]) + fabs(nv[1][1] - nv[0][1]);
-    return 2.0 * (2.0 * d * (e1 + e2) + 4.0 * d * d);
+        for (int c = 0; c < 2; c++) {
+            lo[k][c] = (double)(float)(v[k][c] - OR_FIT_N_ABS);
+            hi[k][c] = (double)(float)(v[k][c] + OR_FIT_N_ABS);
+        }
+    double pl, ph, ql, qh;
+    ivl_mul(lo[2][0] - hi[0][0], hi[2][0] - lo[0][0], lo[1][1] - hi[0][1], hi[1][1] - lo[0][1], &pl, &ph);
+    ivl_mul(lo[2][1] - hi[0][1], hi[2][1] - lo[0][1], lo[1][0] - hi[0][0], hi[1][0] - lo[0][0], &ql, &qh);
+    const double dl = pl - qh, dh = ph - ql;
+    double al, ah;
+    if (dl >= 0.0) { al = dl; ah = dh; }
+    else if (dh <= 0.0) { al = -dh; ah = -dl; }
+    else { al = 0.0; ah = fmax(-dl, dh); }
+    const double slack = 1e-14 * (fmax(fabs(pl), fabs(ph)) + fmax(fabs(ql), fabs(qh)));
+    return al - slack <= lim && lim <= ah + slack;
 }
 
 /* the two cluster triangles of node (level, I, J): corners at spacing s, normals
@@ -597,39 +605,39 @@ static void test_cluster(const map_t* m, const query_t* q, acc_t* acc, int level
     const long s = 1L << level;
     const long mm = m->n >> level;
     const double* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * mm + I);
-    double N[4][2];
-    int near = 0; /* could another fit's float32 normals differ from these? */
+    double N[4][2], N64[4][2];
     for (int k = 0; k < 4; k++)
         for (int c = 0; c < 2; c++) {
+            N64[k][c] = cn[2 * k + c];
             N[k][c] = (double)(float)cn[2 * k + c];
-            near |= round_may_differ(cn[2 * k + c]);
         }
     double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
     const double s2 = (double)s * (double)s;
     for (int half = 0; half < 2; half++) {
-        double nv[3][2], uv[3][2], eq[3][2];
+        double nv[3][2], uv[3][2], eq[3][2], v64[3][2];
         double X0 = (double)(I * s), Y0 = (double)(J * s), X1 = X0 + s, Y1 = Y0 + s;
+        const int vi[2][3] = {{0, 1, 2}, {3, 2, 1}};
+        for (int k = 0; k < 3; k++) {
+            memcpy(nv[k], N[vi[half][k]], sizeof nv[k]);
+            memcpy(v64[k], N64[vi[half][k]], sizeof v64[k]);
+        }
         if (half == 0) {
-            memcpy(nv[0], N[0], sizeof nv[0]); memcpy(nv[1], N[1], sizeof nv[0]);
-            memcpy(nv[2], N[2], sizeof nv[0]);
             uv[0][0] = X0; uv[0][1] = Y0; uv[1][0] = X1; uv[1][1] = Y0; uv[2][0] = X0; uv[2][1] = Y1;
         } else {
-            memcpy(nv[0], N[3], sizeof nv[0]); memcpy(nv[1], N[2], sizeof nv[0]);
-            memcpy(nv[2], N[1], sizeof nv[0]);
             uv[0][0] = X1; uv[0][1] = Y1; uv[1][0] = X0; uv[1][1] = Y1; uv[2][0] = X1; uv[2][1] = Y0;
         }
         double jn = jac(nv[0], nv[1], nv[2]);
         double du = jn / s2;
         eqtri(centre, eq_rho(0.5 * m->eps * s2), eq);
-        if (near && fabs(jn - m->eps * s2) <= clamp_band(nv)) {
-            /* the clamp decision is within rounding: it matters if either version of
-             * the triangle holds a hit or an edge-ambiguous query normal */
+        if (clamp_may_flip(v64, m->eps * s2)) {
+            /* the clamp decision could differ: it matters if either version of the
+             * triangle holds a hit or an edge-ambiguous query normal */
             acc_t a, b;
             memset(&a, 0, sizeof a);
             memset(&b, 0, sizeof b);
             test_tri(m, q, &a, OR_ID(level, I, J, half), nv, uv, du, I, J, s);
             test_tri(m, q, &b, OR_ID(level, I, J, half), eq, uv, m->eps, I, J, s);
-            if (a.nhit || a.namb || b.nhit || b.namb) acc->flags |= 1;
+            if (a.nhit || a.namb || b.nhit || b.namb) acc->flags |= 4;
         }
         if (du < m->eps)
             test_tri(m, q, acc, OR_ID(level, I, J, half), eq, uv, m->eps, I, J, s);
@@ -752,8 +760,9 @@ static void eval_one(const map_t* m, const query_t* q, acc_t* acc)
  *  nhit[k]   number of hit triangles, namb[k] number of triangles within `band` of h
  *  flags[k]  bit0 = a cut decision that another FP64 fit (within the agreement
  *            bound above) could take differently after float32 rounding, with a hit or
- *            an edge-ambiguous triangle in one of its two outcomes; or likewise a
- *            cluster triangle's clamp decision, with either version hit or ambiguous;
+ *            an edge-ambiguous triangle in one of its two outcomes;
+ *            bit2 = likewise a cluster triangle's clamp decision, with either version
+ *            hit or edge-ambiguous;
  *            bit1 = (disk / box) a hit point lies within 1e-9 relative of the support edge
  * kernel: 0 Gaussian (sigma the standard deviation, support r = s2r sigma), 1 disk
  * (the ellipse of half-axes r), 2 box (|u - x| <= r per axis); disk and box are
@@ -939,8 +948,7 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
     if (1.0 - V < dmin) dmin = 1.0 - V;
     if (fabs(U + V - 1.0) < dmin) dmin = fabs(U + V - 1.0);
     if (dmin < band) *flag |= 2;
-    double N[4][2];
-    int near = 0; /* could another fit's float32 normals differ from these? */
+    double N[4][2], N64[4][2];
     if (level == 0) {
         texel(m->nrm, m->n, I, J, N[0]);
         texel(m->nrm, m->n, I + 1, J, N[1]);
@@ -950,8 +958,8 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
         const double* cn = m->clu_n + 8 * (level_offset(m->n, level) + J * (m->n >> level) + I);
         for (int k = 0; k < 4; k++)
             for (int c = 0; c < 2; c++) {
+                N64[k][c] = cn[2 * k + c];
                 N[k][c] = (double)(float)cn[2 * k + c];
-                near |= round_may_differ(cn[2 * k + c]);
             }
     }
     int half = U + V < 1.0 ? 0 : 1;
@@ -966,7 +974,12 @@ static int unit_normal(const map_t* m, int level, long I, long J, const double u
     /* the clamp of the evaluation (test_cell / test_cluster): Jacobian per unit uv area;
      * a cluster's decision within rounding of eps is flagged as in the evaluation */
     const double jn = jac(nv[0], nv[1], nv[2]);
-    if (near && fabs(jn - m->eps * s * s) <= clamp_band(nv)) *flag |= 1;
+    if (level > 0) {
+        const int vi[2][3] = {{0, 1, 2}, {3, 2, 1}};
+        double v64[3][2];
+        for (int k = 0; k < 3; k++) memcpy(v64[k], N64[vi[half][k]], sizeof v64[k]);
+        if (clamp_may_flip(v64, m->eps * s * s)) *flag |= 1;
+    }
     if (jn / (s * s) < m->eps) {
         double centre[2] = {0.5 * (N[1][0] + N[2][0]), 0.5 * (N[1][1] + N[2][1])};
         eqtri(centre, eq_rho(0.5 * m->eps * s * s), nv);

@@ -615,37 +615,42 @@ def test_cut_ambiguity_flag_only_when_it_matters(oracle_mod):
 
 def test_cluster_clamp_flag_only_near_rounding(oracle_mod):
     """A cluster triangle's clamp decision (2 area_n < eps 4^l) is flagged only when
-    another fit's float32 normals could differ from these (a fitted component next
-    to a float32 rounding midpoint) and the Jacobian is within what a one-ulp move
-    of the normals can change, with the triangle (or its replacement) hit."""
+    another fit, whose normals round to float32 values within 1e-10 of these FP64
+    normals, could take it differently, and the triangle (or its replacement) is
+    hit: a vertex component on the midpoint between the two floats on either side
+    of the clamp threshold flags it; the same component on one of those floats
+    (every other fit rounds it the same way) does not."""
     n = 8
     nrm = random_disk_map(n, 43, radius=0.35)
     clusters = oracle_mod.cluster_all(nrm)
     m = n // 2
     I0, J0 = 1, 1
     k0 = J0 * m + I0
-    eps = np.float32(1e-6)
-    d = float(np.float32(np.sqrt(float(eps) * 4.0)))     # lower cluster triangle: Jacobian ~ eps 2^2
-    base = np.array([[0.25, 0.125], [0.25 + d, 0.125], [0.25, 0.125 + d], [0.3, 0.2]])
-    f = np.float32(0.3)
-    mid = 0.5 * (float(f) + float(np.nextafter(f, np.float32(np.inf))))
+    lim = float(np.float32(1e-6)) * 4.0                    # eps s^2 at level 1
+    ax, ay, dy = 0.25, 0.125, 2.0 ** -9                     # exact in float32
+    f = np.float32(ax + lim / dy)
+    if float(f) > ax + lim / dy:
+        f = np.nextafter(f, np.float32(-np.inf))
+    f1 = np.nextafter(f, np.float32(np.inf))
+    assert (float(f) - ax) * dy <= lim <= (float(f1) - ax) * dy   # the threshold lies between the two floats
+    mid = 0.5 * (float(f) + float(f1))
     s = np.float32(0.5)
-    h = base[:3].mean(0)
-    qs = np.array([[2.0 * I0 + 1.0, 2.0 * J0 + 1.0, s, s, h[0], h[1]]], dtype=np.float32)
 
-    def run(n3x):
+    def run(bx):
         c = dict(clusters)
         c["clu_n64"] = clusters["clu_n64"].copy()
-        N = base.copy()
-        N[3, 0] = n3x
+        N = np.array([[ax, ay], [bx, ay], [ax, ay + dy], [0.3, 0.2]])
         c["clu_n64"][8 * k0:8 * k0 + 8] = N.reshape(-1)
+        h = N[:3].mean(0)
+        qs = np.array([[2.0 * I0 + 1.0, 2.0 * J0 + 1.0, s, s, h[0], h[1]]], dtype=np.float32)
         return oracle_mod.evaluate(nrm, qs, tau=1e30, clusters=c, records=True)
 
-    near = run(mid)                      # a component sits on a rounding midpoint
-    assert near["nhit"][0] > 0 and near["flags"][0] & 1
-    far = run(0.3)                       # every component far from one: the same floats for any fit
-    assert not (far["flags"] & 1).any()
-    assert far["nhit"][0] == near["nhit"][0]
+    near = run(mid)
+    assert near["nhit"][0] > 0 and near["flags"][0] & 4
+    for bx in (float(f), float(f1)):
+        far = run(bx)
+        assert not (far["flags"] & 4).any()
+        assert far["nhit"][0] > 0
 
 
 # ----------------------------------------------------- disk and box footprints
