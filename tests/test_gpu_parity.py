@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from conftest import gpu_available
-from parity import compare
+from parity import check_cluster_fit, compare
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
@@ -132,30 +132,6 @@ def triangle_boxes(nrm, deg, rho):
         lo = np.minimum(lo, vmin)
         hi = np.maximum(hi, vmax)
     return lo, hi
-
-
-def check_cluster_fit(ex, ns, e, m, level):
-    """The GPU fit of one level against the oracle's FP64 fit (Eq. normal_optimization,
-    e^l its minimised value).  Both are FP64 fits of the same objective that agree to
-    far better than float32 precision, so the stored float32 values may differ from
-    the rounded oracle values by at most one unit in the last place (rounding of
-    values that sit next to a rounding boundary); residuals below 1e-12 of the
-    level's largest (fits that are exact up to rounding) are compared absolutely."""
-    gn = ex["clu_n"].cpu().numpy().reshape(m * m, 4, 2)
-    ge = ex["clu_e"].cpu().numpy().reshape(m * m)
-    scale = float(np.abs(ns).max()) + 1e-30
-    n32 = ns.astype(np.float32)
-    dn = np.abs(gn.astype(np.float64) - ns)
-    assert (dn <= np.spacing(np.abs(n32)).astype(np.float64) + 1e-12 * scale).all(), \
-        (level, float(dn.max()), float((gn != n32).sum()))
-    emax = float(e.max()) + 1e-300
-    big = e > 1e-12 * emax
-    e32 = e.astype(np.float32)
-    de = np.abs(ge.astype(np.float64) - e32.astype(np.float64))
-    assert (de[big] <= np.spacing(e32[big]).astype(np.float64)).all(), (level, float((de[big] / e[big]).max()))
-    assert (np.abs(ge[~big].astype(np.float64) - e[~big]) <= 1e-12 * emax).all(), level
-    print("level %d: float32 N* differ in %d of %d, e^l in %d of %d (largest residuals)"
-          % (level, int((gn != n32).sum()), gn.size, int((ge[big] != e32[big]).sum()), int(big.sum())))
 
 
 @pytest.mark.parametrize("name", sorted(MAPS))
@@ -449,76 +425,6 @@ def test_deterministic_alone_and_in_the_mix(P):
         c = P.eval_batch(hier, to_dev(q[perm]), tau=tau)
         inv = np.argsort(perm)
         assert torch.equal(c[torch.from_numpy(inv).cuda()].view(torch.int32), a.view(torch.int32))
-
-
-def test_full_size_powerlaw2048_sampled(P, oracle_mod):
-    """The measured workload at full size (2048^2 power-law map, 2^20 queries, sigma
-    log-uniform in [1, 64], |h| < 0.4), in the launch configuration the benchmark
-    times; a stratified sample is checked against the oracle query by query."""
-    import torch
-    import workloads
-    announce("full size powerlaw2048, 1M queries, sampled parity")
-    cfg = workloads.CONFIGS["powerlaw2048"]
-    nrm = workloads.make_map(**cfg["map"])
-    qc = cfg["queries"]
-    q = workloads.uniform_queries(2048, qc["count"], qc["seed"], qc["sigma"], qc["radius"])
-    _, hier = gpu_build(P, nrm, cluster=True)
-    tq = to_dev(q)
-    d = P.eval_batch(hier, tq).cpu().numpy()
-    assert np.isfinite(d).all() and (d >= 0).all()
-    # stratified sample: 160 per sigma octave, plus the nonzero ones are well represented
-    rng = np.random.default_rng(0)
-    oct_ = np.floor(np.log2(q[:, 2])).astype(int)
-    sample = np.concatenate([rng.choice(np.where(oct_ == o)[0], 160, replace=False) for o in range(6)])
-    ref = oracle_mod.evaluate(nrm, q[sample], records=True)
-    dh, off, ids, terms = gpu_hits(P, hier, q[sample])
-    np.testing.assert_array_equal(dh.view(np.uint32), d[sample].view(np.uint32))
-    st = compare(ref, dh, off, ids)
-    assert st["nonzero"] > 100
-
-
-@pytest.mark.parametrize("name", ["scratched4096", "powerlaw8192"])
-def test_full_size_cut_configs_sampled(P, oracle_mod, name):
-    """The two heavy configurations at full size, in the plain kernel's launch
-    configuration: 4096^2 scratched metal with 2^22 queries (sigma log-uniform in
-    [4, 1024], tau = 1e-4) and 8192^2 power-law with 2^24 queries (sigma
-    log-uniform in [1, 8192], |h| < 0.6, tau = 1e-3).  The whole batch is
-    evaluated; a sample stratified by sigma octave is checked against the oracle
-    query by query (ids and values), and for the scratched map the persistent
-    plan must return the plain kernel's bits on a 2^18-query prefix."""
-    import torch
-    import workloads
-    cfg = workloads.CONFIGS[name]
-    mc, qc, tau = cfg["map"], cfg["queries"], float(cfg["tau"])
-    n = mc["n"]
-    announce("full size %s, %d queries, tau=%g, sampled parity" % (name, qc["count"], tau))
-    nrm = workloads.make_map(**mc)
-    q = workloads.uniform_queries(n, qc["count"], qc["seed"], qc["sigma"], qc["radius"])
-    _, hier = gpu_build(P, nrm, cluster=True)
-    tq = to_dev(q)
-    d = P.eval_batch(hier, tq, tau=tau).cpu().numpy()
-    assert np.isfinite(d).all() and (d >= 0).all()
-    rng = np.random.default_rng(1)
-    oct_ = np.floor(np.log2(q[:, 2])).astype(int)
-    sample = np.concatenate([rng.choice(np.where(oct_ == o)[0], min(32, int((oct_ == o).sum())), replace=False)
-                             for o in np.unique(oct_)])
-    ref = oracle_mod.evaluate(nrm, q[sample], tau=tau, records=True)
-    dh, off, ids, terms = gpu_hits(P, hier, q[sample], tau=tau)
-    np.testing.assert_array_equal(dh.view(np.uint32), d[sample].view(np.uint32))
-    st = compare(ref, dh, off, ids)
-    print(st)
-    assert st["nonzero"] > len(sample) // 4
-    # a query with any of its many cut decisions within 1e-5 of the threshold is left
-    # out of the strict comparison (large footprints make thousands of decisions);
-    # most of the sample must still be compared
-    assert len(sample) - st["cut_ambiguous"] >= len(sample) // 2, st
-    if name == "scratched4096":
-        pre = tq[: 1 << 18]
-        plan = P.Plan(hier, pre.shape[0], tau=tau)
-        got = plan.eval(pre)
-        assert plan.stats()["error"] == 0
-        assert torch.equal(got.view(torch.int32), torch.from_numpy(d[: 1 << 18]).cuda().view(torch.int32))
-        plan.close()
 
 
 # ------------------------------------------------------- footprint kernels
