@@ -5,7 +5,8 @@ CPU-baseline leg use it; the library never imports it.  See pndf_oracle.c for th
 definitions it follows and oracle.py for the Python entry points.
 """
 from .oracle import (build, load, mesh, cluster_level, cluster_all, fine_contrib,
-                     evaluate, sample, projected_area, tri_projected, sample_normals, triangle_id, decode_id, num_threads)
+                     evaluate, sample, projected_area, tri_projected, sample_normals, triangle_id, decode_id, num_threads,
+                     set_threads)
 
 __all__ = ["build", "load", "mesh", "cluster_level", "cluster_all", "fine_contrib", "sample", "projected_area", "tri_projected",
-           "evaluate", "sample_normals", "triangle_id", "decode_id", "num_threads"]
+           "evaluate", "sample_normals", "triangle_id", "decode_id", "num_threads", "set_threads"]

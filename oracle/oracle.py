@@ -62,11 +62,18 @@ def load():
     lib.or_tri_projected.argtypes = [_dp, _dp]
     lib.or_tri_projected.restype = ctypes.c_double
     lib.or_num_threads.argtypes = []
+    lib.or_set_threads.argtypes = [ctypes.c_int]
+    lib.or_set_threads.restype = None
     for f in (lib.or_mesh, lib.or_cluster_nodes, lib.or_fine_contrib, lib.or_eval, lib.or_eval_k,
               lib.or_sample_normals, lib.or_sample_k, lib.or_projected_area, lib.or_num_threads):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def set_threads(n):
+    """Run the oracle's parallel loops on n host threads from now on."""
+    load().or_set_threads(int(n))
 
 
 def num_threads():

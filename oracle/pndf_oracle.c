@@ -1389,3 +1389,13 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of the oracle's parallel loops from now on (n >= 1) */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
