@@ -330,19 +330,24 @@ pndf_status pndf_autotune(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
  * example one render tile: a block of queries against one map) as they arrive.
  * A request is admitted when its pinned staging fits the memory budget and the
  * pending queue has room; otherwise pndf_server_submit returns PNDF_EAGAIN.  A
- * scheduler thread packs admitted requests of the same map into batches (up to
- * max_batch_queries) and runs each batch with a persistent plan on one of
- * `slots` streams, so batches formed while others execute overlap on the device
- * (continuous batching).  Results are bit-identical to pndf_eval_batch for the
- * same queries, whatever the batch a request lands in.  Latency is measured from
- * submission to the moment its results are in host memory.
+ * scheduler thread packs waiting requests of the same map into batches of up to
+ * max_batch_queries: each waiting request gives a piece of at most chunk_queries
+ * queries, and a request with queries left goes to the back of the queue, so
+ * requests share the device piece by piece and a small request does not wait for
+ * the whole of a large one.  Each batch runs on one of `slots` streams (a plain
+ * per-batch launch, or the slot's persistent plan), so batches formed while others
+ * execute overlap on the device (continuous batching).  Results are bit-identical
+ * to pndf_eval_batch for the same queries, whatever batch or piece a query lands
+ * in.  Latency is measured from submission (or the trace's arrival time) to the
+ * moment all of a request's results are in host memory.
  */
 typedef struct pndf_server pndf_server;
 
 typedef struct pndf_server_opts {
-    int32_t slots;              /* concurrent batches in flight (streams), >= 1 */
+    int32_t slots;              /* concurrent batches in flight (streams), 1..16 */
     int64_t max_batch_queries;  /* queries per batch (and the largest request), >= 1 */
-    int64_t memory_budget;      /* bytes of pinned staging for admitted requests (28 B per query) */
+    int64_t memory_budget;      /* bytes of pinned staging for admitted requests (28 B per query, plus
+                                 * 256 B per request), >= one batch */
     int32_t max_pending;        /* admitted requests not yet finished, >= 1 */
     float tau;                  /* cluster cut threshold for every request (0 = exact) */
     float sigma_to_r;           /* support half-width in standard deviations (3) */
@@ -351,6 +356,7 @@ typedef struct pndf_server_opts {
                                  * pndf_eval_batch on the slot's stream; PNDF_ALGO_PERSISTENT:
                                  * the slot's persistent plan for the batch's map */
     int32_t kernel;             /* footprint kernel of every request (pndf_kernel) */
+    int64_t chunk_queries;      /* largest piece of one request in one batch (0: whole requests) */
 } pndf_server_opts;
 
 typedef struct pndf_server_stats {
@@ -388,9 +394,14 @@ pndf_status pndf_server_reset_stats(pndf_server* srv);
 
 /*
  * Replay an arrival trace: request k (map map_ids[k], nq[k] queries at h_q[k],
- * results to h_out[k]) is submitted arrival_s[k] seconds after the call starts
- * (non-decreasing), retrying while it is refused; returns after every request has
- * completed.  latency_ms[k] (may be NULL) receives each latency.
+ * results to h_out[k]) is submitted arrival_s[k] seconds after the call starts,
+ * retrying while it is refused; returns after every submitted request has
+ * completed.  latency_ms[k] (may be NULL) receives each latency.  The whole trace
+ * is validated first (arrival times finite, >= 0 and non-decreasing; map ids in
+ * range; 1 <= nq[k] <= max_batch_queries; non-NULL buffers): PNDF_EINVAL and
+ * nothing submitted.  If a submission fails later (a device error), the requests
+ * already submitted are still waited for before the call returns that status, so
+ * no result is written into h_out after the call.
  */
 pndf_status pndf_server_replay(pndf_server* srv, int64_t nreq, const int32_t* map_ids,
                                const double* arrival_s, const pndf_query* const* h_q,

@@ -380,7 +380,8 @@ def autotune(hier, queries, tau=0.0, sigma_to_r=3.0, stream=None, kernel=0):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", _i32), ("max_batch_queries", _i64), ("memory_budget", _i64), ("max_pending", _i32),
-                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning), ("algo", _i32), ("kernel", _i32)]
+                ("tau", _f32), ("sigma_to_r", _f32), ("tuning", Tuning), ("algo", _i32), ("kernel", _i32),
+                ("chunk_queries", _i64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -410,7 +411,7 @@ class Server:
     """Continuous-batching server over resident hierarchies (host-side requests)."""
 
     def __init__(self, hiers, slots=2, max_batch_queries=1 << 16, memory_budget=None, max_pending=256,
-                 tau=0.0, sigma_to_r=3.0, tuning=None, algo="plain", kernel=0):
+                 tau=0.0, sigma_to_r=3.0, tuning=None, algo="plain", kernel=0, chunk_queries=0):
         import numpy as np
         self._np = np
         self.hiers = list(hiers)  # keep the hierarchies alive
@@ -419,7 +420,7 @@ class Server:
         t = Tuning(0, 1, 16, 1) if tuning is None else (tuning if isinstance(tuning, Tuning) else Tuning(**tuning))
         o = ServerOpts(int(slots), int(max_batch_queries), int(memory_budget), int(max_pending), float(tau),
                        float(sigma_to_r), t, ALGOS[algo] if isinstance(algo, str) else int(algo),
-                       KERNELS[kernel] if isinstance(kernel, str) else int(kernel))
+                       KERNELS[kernel] if isinstance(kernel, str) else int(kernel), int(chunk_queries))
         arr = (_vp * len(self.hiers))(*[h.handle for h in self.hiers])
         h = _vp()
         _check(_server_create(arr, len(self.hiers), ctypes.byref(o), ctypes.byref(h)), "pndf_server_create")

@@ -1,6 +1,6 @@
 """Build the gfx950 shared library libpndf.so in-tree with hipcc.
 
-    python -m paper_2505_08985_amd.build
+    python paper_2505_08985_amd/build.py     (or __graft_entry__.build())
 
 Every HIP source is compiled for gfx950 only, with IEEE semantics (no fast-math),
 denormals kept, and packed-FP32 instruction selection disabled.

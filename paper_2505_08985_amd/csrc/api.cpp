@@ -2,6 +2,7 @@
 // ownership, device allocation and kernel dispatch.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -17,6 +18,16 @@ static thread_local std::string g_last_error;
 constexpr int64_t kOrderMin = 4096;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+int64_t launch_chunk()
+{
+    const char* v = std::getenv("PNDF_LAUNCH_CHUNK");
+    if (v) {
+        const long long c = std::atoll(v);
+        if (c > 0 && c < kLaunchChunk) return (int64_t)c;
+    }
+    return kLaunchChunk;
+}
 
 pndf_status hip_fail(hipError_t e, const char* what)
 {
@@ -98,7 +109,7 @@ static pndf_status resolve_opts(const pndf_hier* h, const pndf_eval_opts* o, pnd
     if (d.flags & ~PNDF_EVAL_INPUT_ORDER) return invalid("unknown flags");
     if (d.algo < PNDF_ALGO_AUTO || d.algo > PNDF_ALGO_PERSISTENT) return invalid("unknown algo");
     if (d.algo == PNDF_ALGO_PERSISTENT) {
-        set_error("use pndf_eval_persistent for the persistent traversal");
+        set_error("the persistent traversal runs through a plan (pndf_plan_create, pndf_plan_eval)");
         return PNDF_EUNSUPPORTED;
     }
     if (d.tau > 0.f && !h->cluster) return invalid("tau > 0 needs a hierarchy built with clusters");
@@ -298,7 +309,7 @@ static pndf_status eval_common(const pndf_hier* h, const pndf_query* d_q, int64_
     if (!h) return invalid("hierarchy is NULL");
     if (nq < 0) return invalid("nq < 0");
     if (nq > 0 && (!d_q || !d_out)) return invalid("query or output pointer is NULL");
-    if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
+    if (nq > (int64_t)UINT32_MAX) return invalid("nq above 2^32 - 1 (the spatial order holds 32-bit indices)");
     pndf_status st = resolve_opts(h, opts, o);
     if (st != PNDF_OK) return st;
     return check_sticky();
@@ -310,7 +321,7 @@ pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t
 {
     if (!h) return invalid("hierarchy is NULL");
     if (nq < 0) return invalid("nq < 0");
-    if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
+    if (nq > (int64_t)UINT32_MAX) return invalid("nq above 2^32 - 1");
     if (attempts < 1 || attempts > 64) return invalid("attempts must be in [1, 64]");
     if (nq > 0 && (!d_q || !d_xi || !d_m)) return invalid("query, uniform or output pointer is NULL");
     // (the kernel reads the uniforms as pairs of doubles and writes m, u as pairs)
@@ -328,8 +339,8 @@ pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t
     if (st != PNDF_OK) return st;
     st = check_sticky();
     if (st != PNDF_OK) return st;
-    SampleArgs a{d_q, d_xi, nq, attempts, r.tau, r.sigma_to_r, r.kernel, reinterpret_cast<float2*>(d_m), d_tri,
-                 reinterpret_cast<double2*>(d_u)};
+    SampleArgs a{d_q, d_xi, nq, 0, nq, attempts, r.tau, r.sigma_to_r, r.kernel, reinterpret_cast<float2*>(d_m),
+                 d_tri, reinterpret_cast<double2*>(d_u)};
     const hipError_t e = launch_sample(h->dev, a, (hipStream_t)stream);
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_sample_batch");
 }
@@ -339,7 +350,7 @@ pndf_status pndf_projected_area(const pndf_hier* h, const pndf_query* d_q, int64
 {
     if (!h) return invalid("hierarchy is NULL");
     if (nq < 0) return invalid("nq < 0");
-    if (nq > ((int64_t)1 << 33)) return invalid("nq too large");
+    if (nq > (int64_t)UINT32_MAX) return invalid("nq above 2^32 - 1");
     if (nq > 0 && (!d_q || !d_P)) return invalid("query or output pointer is NULL");
     pndf_eval_opts o{PNDF_KERNEL_GAUSSIAN, 0.f, 3.f, PNDF_ALGO_AUTO, 0};
     if (opts) {

@@ -1069,16 +1069,16 @@ __global__ void k_persist_finalize(const QueueCtl* ctl, const Fix192* acc, const
     }
 }
 
-// Launches cover at most kChunk queries (grid dimensions stay far below 2^32 work-items).
-constexpr int64_t kChunk = (int64_t)1 << 24;
-
+// Launches cover at most launch_chunk() queries (grid dimensions stay far below
+// 2^32 work-items).
 template <int MODE, int KER>
 hipError_t launch_mode(const HierDev& H, const EvalArgs& a0, int algo, hipStream_t s)
 {
-    for (int64_t off = 0; off < a0.nq; off += kChunk) {
+    const int64_t chunk = launch_chunk();
+    for (int64_t off = 0; off < a0.nq; off += chunk) {
         EvalArgs a = a0;
         a.slot0 = off;
-        a.slots = std::min<int64_t>(kChunk, a0.nq - off);
+        a.slots = std::min<int64_t>(chunk, a0.nq - off);
         if (algo == PNDF_ALGO_BRUTE) {
             const unsigned blocks = (unsigned)((a.slots + 3) / 4);
             hipLaunchKernelGGL((k_eval_brute<MODE, KER>), dim3(blocks), dim3(256), 0, s, H, a);

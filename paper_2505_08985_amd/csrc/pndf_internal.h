@@ -20,10 +20,21 @@ constexpr int kWave = 64;
 #define PNDF_LIST_CAP 128
 #endif
 // Per-level traversal list entries.  A wave expands up to 64 parents at a time;
-// parents whose children do not fit wait in their own list, so any capacity of at
-// least 16 (the roots of a query) is correct; smaller lists mean more waves per CU.
+// parents whose children do not fit wait in their own list.  The roots of a query
+// fill up to an 8 x 8 lane grid (64 entries of one list), and children are appended
+// to a list that is empty or holds fewer than 32 entries (the short lowest list,
+// expanded after the level above it), so with at least 64 entries the first
+// parent's four children always fit and the descent progresses.  (Fewer entries
+// would mean more waves per CU, but roots would overflow.)
 constexpr int kListCap = PNDF_LIST_CAP;
-static_assert(kListCap >= 16, "the list of the entry level holds up to 16 roots");
+static_assert(kListCap >= 64, "a list holds up to 64 roots; a short list (< 32) plus four children must fit");
+
+// Kernel launches cover at most this many queries (one workgroup or one wavefront
+// each), so grids stay far below 2^32 work-items.  PNDF_LAUNCH_CHUNK in the
+// environment lowers it (any positive value; used by the tests to force several
+// launches per call, which must give the same bits).
+constexpr int64_t kLaunchChunk = (int64_t)1 << 24;
+int64_t launch_chunk();
 
 // Hit queue of a wavefront: float32 hits wait here for the FP64 stage, which takes
 // them 64 at a time (fewer than 64 wait between steps; one step adds at most 64 x 8).
@@ -237,6 +248,7 @@ struct SampleArgs {
     const pndf_query* q;
     const double* xi;          // attempts x nq pairs of uniforms, attempt-major
     int64_t nq;
+    int64_t first, end;        // the launch covers queries [first, end)
     int attempts;
     float tau;
     float s2r;

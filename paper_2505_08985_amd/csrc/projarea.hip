@@ -405,14 +405,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
 hipError_t launch_projected_area(const HierDev& H, const ProjArgs& a, hipStream_t s)
 {
-    // one workgroup per query, in launches of at most 2^30 workgroups
-    constexpr int64_t kMaxGrid = (int64_t)1 << 30;
-    for (int64_t off = 0; off < a.nq; off += kMaxGrid) {
+    // one wavefront-sized workgroup per query, in launches of at most launch_chunk()
+    // workgroups (2^24 x 64 = 2^30 work-items)
+    const int64_t chunk = launch_chunk();
+    for (int64_t off = 0; off < a.nq; off += chunk) {
         ProjArgs c = a;
         c.q = a.q + off;
         c.P = a.P + off;
         if (a.lambda) c.lambda = a.lambda + off;
-        c.nq = std::min(kMaxGrid, a.nq - off);
+        c.nq = std::min(chunk, a.nq - off);
         const dim3 grid((unsigned)c.nq), block(64);
         if (a.kernel == PNDF_KERNEL_DISK)
             hipLaunchKernelGGL(k_projected_area<PNDF_KERNEL_DISK>, grid, block, 0, s, H, c);

@@ -20,6 +20,8 @@
 // residuals (4 B each, from the entry level down to the cut), the unit's four corner
 // normals and clamp bits (for a texel cell from its leaf record), and the outputs.
 // Nothing is shared between samples: the kernel is a gather-bound stream.
+#include <algorithm>
+
 #include "pndf_internal.h"
 
 namespace pndf {
@@ -55,8 +57,8 @@ __device__ __forceinline__ bool unit_meets(double u, int l, int clo, int chi)
 template <int KER, bool CUT>
 __global__ __launch_bounds__(256) void k_sample(HierDev H, SampleArgs a)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.nq) return;
+    const int64_t k = a.first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.end) return;
     const QuerySetup q = setup_query(a.q[k], a.s2r, CUT ? a.tau : 0.f, H.L, H.eps, KER);
     bool ok = q.valid;
     const double2* xi = reinterpret_cast<const double2*>(a.xi);
@@ -157,14 +159,23 @@ __global__ __launch_bounds__(256) void k_sample(HierDev H, SampleArgs a)
     if (a.u) a.u[k] = u;
 }
 
+// One thread per sample, in launches of at most launch_chunk() samples (the
+// uniforms keep their stride nq: attempt t of sample k at t nq + k).
 template <int KER>
-void launch_kernel(const HierDev& H, const SampleArgs& a, hipStream_t s)
+void launch_kernel(const HierDev& H, const SampleArgs& a0, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.nq + 255) / 256)), block(256);
-    if (a.tau > 0.f)
-        hipLaunchKernelGGL((k_sample<KER, true>), grid, block, 0, s, H, a);
-    else
-        hipLaunchKernelGGL((k_sample<KER, false>), grid, block, 0, s, H, a);
+    const int64_t chunk = launch_chunk();
+    for (int64_t off = 0; off < a0.nq; off += chunk) {
+        SampleArgs a = a0;
+        a.first = off;
+        a.end = std::min(a0.nq, off + chunk);
+        const dim3 grid((unsigned)((a.end - a.first + 255) / 256)), block(256);
+        if (a.tau > 0.f)
+            hipLaunchKernelGGL((k_sample<KER, true>), grid, block, 0, s, H, a);
+        else
+            hipLaunchKernelGGL((k_sample<KER, false>), grid, block, 0, s, H, a);
+        if (hipPeekAtLastError() != hipSuccess) return;
+    }
 }
 
 }  // namespace

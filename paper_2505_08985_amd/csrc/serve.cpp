@@ -2,14 +2,17 @@
 //
 // Threads: callers submit / wait; one scheduler thread owns the streams.  The
 // scheduler repeatedly (1) retires finished batches (event query), copying each
-// request's results from pinned staging to the caller's buffer and releasing its
-// staging, and (2) fills every idle slot with a new batch: the oldest admitted
-// request fixes the map, then later requests of that map join in arrival order
-// while they fit.  A batch is H2D copies into the slot's contiguous query buffer,
-// one evaluation (a plain per-batch launch or the slot's persistent plan), D2H
-// copies into staging and an event, all on the slot's stream, so the batches of
-// different slots overlap on the device: one batch's tail runs beside the next
-// batch's bulk.
+// piece's results from pinned staging to the caller's buffer, and completing a
+// request (releasing its staging) once all its pieces are back, and (2) fills
+// every idle slot with a new batch: the first waiting request fixes the map, then
+// waiting requests of that map each give a piece of at most chunk_queries queries,
+// in queue order, while the batch has room.  A request that still has queries left
+// after giving a piece goes to the back of the queue, so requests share the device
+// piece by piece (round robin) and a small request never waits for the whole of a
+// large one.  A batch is H2D copies into the slot's contiguous query buffer, one
+// evaluation (a plain per-batch launch or the slot's persistent plan), D2H copies
+// into staging and an event, all on the slot's stream, so the batches of different
+// slots overlap on the device: one batch's tail runs beside the next batch's bulk.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -18,6 +21,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -94,11 +98,18 @@ struct Request {
     uint64_t ticket = 0;
     int map = 0;
     int64_t nq = 0;
+    int64_t dispatched = 0;   // queries handed to batches
+    int64_t returned = 0;     // queries whose results are in user_out
     pndf_query* q = nullptr;  // pinned staging: queries, then nq floats of results
     float* res = nullptr;
     float* user_out = nullptr;
     double t_arrive = 0, t_done = 0;
-    int state = 0;  // 0 admitted, 1 running, 2 done
+    int state = 0;  // 0 waiting (queries left to dispatch), 1 all dispatched, 2 done
+};
+
+struct Piece {
+    Request* r;
+    int64_t off, n;  // queries [off, off + n) of the request
 };
 
 struct Slot {
@@ -107,7 +118,7 @@ struct Slot {
     pndf_query* d_q = nullptr;
     float* d_out = nullptr;
     std::vector<pndf_plan*> plans;  // one per map
-    std::vector<Request*> reqs;
+    std::vector<Piece> pieces;
     bool busy = false;
 };
 
@@ -139,8 +150,11 @@ void finish_slot(pndf_server* s, Slot& sl)
 {
     const double now = seconds(Clock::now());
     std::lock_guard<std::mutex> g(s->mu);
-    for (Request* r : sl.reqs) {
-        std::memcpy(r->user_out, r->res, sizeof(float) * (size_t)r->nq);
+    for (const Piece& p : sl.pieces) {
+        Request* r = p.r;
+        std::memcpy(r->user_out + p.off, r->res + p.off, sizeof(float) * (size_t)p.n);
+        r->returned += p.n;
+        if (r->returned < r->nq) continue;
         s->pool.release(r->q);
         r->q = nullptr;
         r->res = nullptr;
@@ -151,41 +165,58 @@ void finish_slot(pndf_server* s, Slot& sl)
         --s->admitted;
     }
     s->t_last = now;
-    sl.reqs.clear();
+    sl.pieces.clear();
     sl.busy = false;
     s->cv_done.notify_all();
 }
 
-// Build a batch for `sl` from the pending queue (caller holds the lock).
+// Build a batch for `sl` from the waiting queue (caller holds the lock): requests of
+// the first waiting request's map give pieces of at most chunk queries in queue
+// order while the batch has room; those with queries left move to the back.
 bool take_batch(pndf_server* s, Slot& sl)
 {
     if (s->pending.empty()) return false;
     const int map = s->pending.front()->map;
+    const int64_t chunk = s->opts.chunk_queries > 0 ? s->opts.chunk_queries : s->opts.max_batch_queries;
     int64_t total = 0;
-    for (auto it = s->pending.begin(); it != s->pending.end();) {
-        Request* r = *it;
-        if (r->map == map && total + r->nq <= s->opts.max_batch_queries) {
-            total += r->nq;
-            r->state = 1;
-            sl.reqs.push_back(r);
-            it = s->pending.erase(it);
-        } else {
-            ++it;
+    std::deque<Request*> kept, rotated;
+    for (Request* r : s->pending) {
+        const int64_t room = s->opts.max_batch_queries - total;
+        if (r->map != map || room <= 0) {
+            kept.push_back(r);
+            continue;
         }
+        const int64_t left = r->nq - r->dispatched;
+        // a request is split only when it exceeds a chunk: a whole request that fits
+        // the remaining room goes in one piece
+        const int64_t n = left <= room && left <= chunk ? left : std::min(chunk, room);
+        if (n < left && n < chunk && left <= chunk) {
+            kept.push_back(r);  // would split a small request across batches: wait for a batch with room
+            continue;
+        }
+        sl.pieces.push_back(Piece{r, r->dispatched, n});
+        r->dispatched += n;
+        total += n;
+        if (r->dispatched < r->nq)
+            rotated.push_back(r);
+        else
+            r->state = 1;
     }
-    return !sl.reqs.empty();
+    s->pending.swap(kept);
+    for (Request* r : rotated) s->pending.push_back(r);
+    return !sl.pieces.empty();
 }
 
 hipError_t launch_slot(pndf_server* s, Slot& sl)
 {
-    const int map = sl.reqs.front()->map;
+    const int map = sl.pieces.front().r->map;
     int64_t off = 0;
     hipError_t e = hipSuccess;
-    for (Request* r : sl.reqs) {
+    for (const Piece& p : sl.pieces) {
         if (e == hipSuccess)
-            e = hipMemcpyAsync(sl.d_q + off, r->q, sizeof(pndf_query) * (size_t)r->nq, hipMemcpyHostToDevice,
-                               sl.stream);
-        off += r->nq;
+            e = hipMemcpyAsync(sl.d_q + off, p.r->q + p.off, sizeof(pndf_query) * (size_t)p.n,
+                               hipMemcpyHostToDevice, sl.stream);
+        off += p.n;
     }
     if (e == hipSuccess) {
         pndf_status st;
@@ -198,11 +229,11 @@ hipError_t launch_slot(pndf_server* s, Slot& sl)
         if (st != PNDF_OK) e = hipErrorLaunchFailure;
     }
     off = 0;
-    for (Request* r : sl.reqs) {
+    for (const Piece& p : sl.pieces) {
         if (e == hipSuccess)
-            e = hipMemcpyAsync(r->res, sl.d_out + off, sizeof(float) * (size_t)r->nq, hipMemcpyDeviceToHost,
-                               sl.stream);
-        off += r->nq;
+            e = hipMemcpyAsync(p.r->res + p.off, sl.d_out + off, sizeof(float) * (size_t)p.n,
+                               hipMemcpyDeviceToHost, sl.stream);
+        off += p.n;
     }
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     return e;
@@ -232,7 +263,7 @@ void scheduler(pndf_server* s)
                 got = take_batch(s, sl);
                 if (got) {
                     ++s->batches;
-                    s->batch_reqs += sl.reqs.size();
+                    s->batch_reqs += sl.pieces.size();
                 }
             }
             if (!got) break;
@@ -344,6 +375,7 @@ pndf_status pndf_server_create(const pndf_hier* const* maps, int32_t nmaps, cons
     if (o.slots < 1 || o.slots > 16) return fail("slots must be in [1, 16]");
     if (o.max_batch_queries < 1 || o.max_batch_queries >= ((int64_t)1 << 31)) return fail("bad max_batch_queries");
     if (o.max_pending < 1) return fail("max_pending must be >= 1");
+    if (o.chunk_queries < 0) return fail("chunk_queries must be >= 0");
     if (o.memory_budget < (int64_t)(28 * o.max_batch_queries + 512)) return fail("memory budget below one batch");
     if (o.algo != PNDF_ALGO_AUTO && o.algo != PNDF_ALGO_PLAIN && o.algo != PNDF_ALGO_PERSISTENT)
         return fail("algo must be AUTO, PLAIN or PERSISTENT");
@@ -465,28 +497,47 @@ pndf_status pndf_server_replay(pndf_server* srv, int64_t nreq, const int32_t* ma
 {
     if (!srv || nreq < 0 || (nreq > 0 && (!map_ids || !arrival_s || !h_q || !nq || !h_out)))
         return fail("bad replay arguments");
-    std::vector<uint64_t> tickets((size_t)nreq, 0);
-    const Clock::time_point t0 = Clock::now();
+    // the whole trace is checked before anything is submitted
     for (int64_t k = 0; k < nreq; ++k) {
-        if (k > 0 && arrival_s[k] < arrival_s[k - 1]) return fail("arrival times must be non-decreasing");
+        if (!(arrival_s[k] >= 0.0) || (k > 0 && arrival_s[k] < arrival_s[k - 1]))
+            return fail("arrival times must be finite, >= 0 and non-decreasing");
+        if (map_ids[k] < 0 || map_ids[k] >= (int32_t)srv->maps.size()) return fail("map index out of range");
+        if (nq[k] < 1 || nq[k] > srv->opts.max_batch_queries) return fail("request size out of range");
+        if (!h_q[k] || !h_out[k]) return fail("NULL query or output pointer");
+    }
+    std::vector<uint64_t> tickets((size_t)nreq, 0);
+    pndf_status failed = PNDF_OK;
+    int64_t submitted = 0;
+    const Clock::time_point t0 = Clock::now();
+    for (int64_t k = 0; k < nreq && failed == PNDF_OK; ++k) {
         const Clock::time_point due =
             t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[k]));
         std::this_thread::sleep_until(due);
         const double t_arr = seconds(due);
         while (true) {
             const pndf_status st = submit_at(srv, map_ids[k], h_q[k], nq[k], h_out[k], t_arr, &tickets[k]);
-            if (st == PNDF_OK) break;
-            if (st != PNDF_EAGAIN) return st;
+            if (st == PNDF_OK) {
+                ++submitted;
+                break;
+            }
+            if (st != PNDF_EAGAIN) {
+                failed = st;
+                break;
+            }
             std::this_thread::sleep_for(std::chrono::microseconds(50));
         }
     }
-    for (int64_t k = 0; k < nreq; ++k) {
+    // every submitted request is waited for, also after a failure: their results go
+    // to the caller's buffers, which must not be released before
+    const std::string first_error = failed != PNDF_OK ? std::string(pndf_last_error()) : std::string();
+    for (int64_t k = 0; k < submitted; ++k) {
         double ms = 0;
         const pndf_status st = pndf_server_wait(srv, tickets[k], -1.0, &ms);
-        if (st != PNDF_OK) return st;
+        if (st != PNDF_OK && failed == PNDF_OK) failed = st;
         if (latency_ms) latency_ms[k] = ms;
     }
-    return PNDF_OK;
+    if (!first_error.empty()) pndf::set_error(first_error);
+    return failed;
 }
 
 void pndf_server_destroy(pndf_server* srv) { destroy_server(srv); }

@@ -477,3 +477,49 @@ def test_footprint_kernels_differ_from_gaussian(P, oracle_mod):
         ref = oracle_mod.evaluate(nrm, q, kernel=k, sigma_to_r=1.5)["D"][0]
         assert abs(out[k] - ref) <= 1e-4 * ref, (k, out[k], ref)
     assert len({round(v, 3) for v in out.values()}) == 3
+
+
+def test_launches_split_into_chunks(P, oracle_mod):
+    """Calls whose batch exceeds a launch's query count run as several launches (each
+    covering its own slots); with the launch size forced down to 1000 queries every
+    entry point returns the bits of a single launch."""
+    import os
+    import torch
+    import workloads
+    announce("launch chunking: 5000 queries in launches of 1000")
+    nrm = workloads.make_map("powerlaw", 128, 7)
+    _, hier = gpu_build(P, nrm, cluster=True)
+    q = mixed_queries(128, 5000, 41, 0.3, 30.0, normal_radius(nrm), spread=0)
+    tq = to_dev(q)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    xi = torch.rand((2, 5000, 2), dtype=torch.float64, device="cuda", generator=g)
+    w = q.copy()
+    w[:, 4:6] = 0.5 * w[:, 4:6]
+    tw = to_dev(w)
+
+    def run():
+        out = {}
+        for algo in ("plain", "brute"):
+            out[algo] = P.eval_batch(hier, tq, algo=algo).cpu().numpy()
+        out["cut"] = P.eval_batch(hier, tq, tau=1e-3).cpu().numpy()
+        out["counts"] = P.eval_counts(hier, tq)[1].cpu().numpy()
+        d, off, ids, terms = P.eval_hits(hier, tq, tau=1e-3)
+        out["hits"] = (d.cpu().numpy(), off.cpu().numpy(), ids.cpu().numpy())
+        m, tri, u = P.sample_batch(hier, tq, xi, tau=1e-3, u=True)
+        out["sample"] = (m.cpu().numpy(), tri.cpu().numpy(), u.cpu().numpy())
+        out["proj"] = P.projected_area(hier, tw).cpu().numpy()
+        torch.cuda.synchronize()
+        return out
+
+    one = run()
+    os.environ["PNDF_LAUNCH_CHUNK"] = "1000"
+    try:
+        many = run()
+    finally:
+        del os.environ["PNDF_LAUNCH_CHUNK"]
+    for key in one:
+        a, b = one[key], many[key]
+        for x, y in (zip(a, b) if isinstance(a, tuple) else [(a, b)]):
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), key
+    assert np.isfinite(one["plain"]).all() and (one["plain"] > 0).sum() > 500
