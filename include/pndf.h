@@ -152,6 +152,22 @@ pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t n
                             const pndf_eval_opts* opts, float* d_out, void* stream);
 
 /*
+ * pndf_eval_batch for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results, bit for bit, with the spatial-order workspace taken from a static
+ * array of the library (one per GPU, 32 MiB + 16 KiB, held until the process
+ * ends) instead of a stream-ordered allocation.  nq is limited to 2^22 (larger:
+ * PNDF_EINVAL, nothing launched); no hipMalloc, hipFree or allocating library call
+ * is made (the array's device address is looked up once per device, on the first
+ * call there).  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams or threads, not ordered by the caller) race and
+ * give wrong results; order them on one stream.  Arguments, ownership and errors
+ * as for pndf_eval_batch.
+ */
+pndf_status pndf_eval_batch_noalloc(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                                    const pndf_eval_opts* opts, float* d_out, void* stream);
+
+/*
  * As pndf_eval_batch, plus per-query work counters (debug/roofline accounting):
  *   d_counts  device pointer to nq * 4 uint32: nodes tested, leaf cells tested,
  *             cluster nodes used, hit triangles (for the brute-force algorithm the

@@ -56,6 +56,7 @@ def _sig(name, res, args):
 _build_mesh = _sig("pndf_build_mesh", _i32, [_vp, _i32, _f32, _vp, ctypes.POINTER(_vp)])
 _build_hier = _sig("pndf_build_hierarchy", _i32, [_vp, ctypes.POINTER(HierOpts), _vp, ctypes.POINTER(_vp)])
 _eval_batch = _sig("pndf_eval_batch", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp])
+_eval_batch_noalloc = _sig("pndf_eval_batch_noalloc", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp])
 _eval_counts = _sig("pndf_eval_counts", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp])
 _eval_hits = _sig("pndf_eval_hits", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), _vp, _vp, _vp, _vp,
                                            _u64, ctypes.POINTER(_u64), _vp])
@@ -81,7 +82,7 @@ _plan_destroy = _sig("pndf_plan_destroy", None, [_vp])
 _autotune = _sig("pndf_autotune", _i32, [_vp, _vp, _i64, ctypes.POINTER(EvalOpts), ctypes.POINTER(Tuning),
                                          ctypes.POINTER(ctypes.c_double), _vp])
 
-EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_eval_counts",
+EXPORTED = ["pndf_build_mesh", "pndf_build_hierarchy", "pndf_eval_batch", "pndf_eval_batch_noalloc", "pndf_eval_counts",
             "pndf_eval_hits", "pndf_sample_batch", "pndf_projected_area", "pndf_destroy_mesh", "pndf_destroy_hierarchy", "pndf_status_string",
             "pndf_last_error", "pndf_mesh_info", "pndf_mesh_export", "pndf_hier_info",
             "pndf_hier_export_level", "pndf_default_tuning", "pndf_plan_create", "pndf_plan_eval",
@@ -205,6 +206,19 @@ def eval_batch(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, st
     o = _opts(tau, sigma_to_r, algo, kernel, EVAL_INPUT_ORDER if input_order else 0)
     _check(_eval_batch(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
                        _stream(stream)), "pndf_eval_batch")
+    return out
+
+
+def eval_batch_noalloc(hier, queries, tau=0.0, sigma_to_r=3.0, algo="auto", out=None, stream=None, kernel=0,
+                       input_order=False):
+    """pndf_eval_batch_noalloc: as eval_batch, with the library's static workspace
+    (at most 2^22 queries; calls on one GPU must not overlap)."""
+    qp, nq = _queries(queries)
+    if out is None:
+        out = torch.empty(nq, dtype=torch.float32, device=queries.device)
+    o = _opts(tau, sigma_to_r, algo, kernel, EVAL_INPUT_ORDER if input_order else 0)
+    _check(_eval_batch_noalloc(hier.handle, qp, nq, ctypes.byref(o), _dev_ptr(out, torch.float32, "out"),
+                               _stream(stream)), "pndf_eval_batch_noalloc")
     return out
 
 

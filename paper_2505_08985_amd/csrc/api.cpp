@@ -386,6 +386,23 @@ pndf_status pndf_eval_batch(const pndf_hier* h, const pndf_query* d_q, int64_t n
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_batch");
 }
 
+pndf_status pndf_eval_batch_noalloc(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
+                                    const pndf_eval_opts* opts, float* d_out, void* stream)
+{
+    pndf_eval_opts o;
+    pndf_status st = eval_common(h, d_q, nq, opts, d_out, &o);
+    if (st != PNDF_OK) return st;
+    if (nq > kStaticOrderQueries) return invalid("nq above 2^22, the no-allocation workspace's limit");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* order = nullptr;
+    hipError_t e = hipSuccess;
+    if (nq >= kOrderMin && o.algo != PNDF_ALGO_BRUTE && !(o.flags & PNDF_EVAL_INPUT_ORDER))
+        e = make_order_static(h->dev, d_q, nq, &order, s);
+    EvalArgs a{d_q, order, nq, 0, 0, d_out, nullptr, nullptr, nullptr, nullptr, o.tau, o.sigma_to_r, o.kernel};
+    if (e == hipSuccess) e = launch_eval(h->dev, a, o.algo, s);
+    return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_eval_batch_noalloc");
+}
+
 pndf_status pndf_eval_counts(const pndf_hier* h, const pndf_query* d_q, int64_t nq,
                              const pndf_eval_opts* opts, float* d_out, uint32_t* d_counts,
                              void* stream)

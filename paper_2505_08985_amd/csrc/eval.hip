@@ -21,6 +21,7 @@
 // which hits are found: all algorithms, batch compositions and work splits give
 // the same bits.
 #include <algorithm>
+#include <mutex>
 
 #include "pndf_internal.h"
 
@@ -1203,6 +1204,22 @@ void order_shape(int logn, int* nb, int* bshift)
     *bshift = logn - bits;
 }
 
+// The four passes of the spatial order into buf = order[nq] | key[nq] | hist[nb]
+// (the histogram is cleared by a kernel, never a memset node).
+static hipError_t order_passes(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t* buf, hipStream_t s)
+{
+    int nb, bshift;
+    order_shape(H.logn, &nb, &bshift);
+    uint32_t* key = buf + nq;
+    uint32_t* hist = key + nq;
+    const unsigned g = (unsigned)std::min<int64_t>(2048, (nq + 255) / 256);
+    hipLaunchKernelGGL(k_order_zero, dim3(16), dim3(256), 0, s, hist, nb);
+    hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, s, q, nq, H.n, bshift, key, hist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, hist, nb);
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, s, key, nq, hist, buf);
+    return hipGetLastError();
+}
+
 hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s)
 {
     *order = nullptr;
@@ -1211,20 +1228,54 @@ hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_
     uint32_t* buf = nullptr;  // order[nq] | key[nq] | hist[nb]
     hipError_t e = hipMallocAsync((void**)&buf, sizeof(uint32_t) * (2 * (size_t)nq + nb), s);
     if (e != hipSuccess) return e;
-    uint32_t* key = buf + nq;
-    uint32_t* hist = key + nq;
-    const unsigned g = (unsigned)std::min<int64_t>(2048, (nq + 255) / 256);
-    hipLaunchKernelGGL(k_order_zero, dim3(16), dim3(256), 0, s, hist, nb);
-    hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, s, q, nq, H.n, bshift, key, hist);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, hist, nb);
-    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, s, key, nq, hist, buf);
-    e = hipGetLastError();
+    e = order_passes(H, q, nq, buf, s);
     if (e != hipSuccess) {
         (void)hipFreeAsync(buf, s);
         return e;
     }
     *order = buf;
     return hipSuccess;
+}
+
+// Workspace of the spatial order for callers that cannot allocate: one array per
+// GPU, held until the process ends, for batches of up to kStaticOrderQueries
+// queries (order, keys and the largest histogram: 32 MiB + 16 KiB).  Its device
+// address is looked up once per device; host code uses that address, never the
+// array's name.  Every call on a GPU shares it, so calls that overlap on one GPU
+// race.
+static __device__ __align__(256) uint32_t scratch[2 * kStaticOrderQueries + 4096];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t make_order_static(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s)
+{
+    *order = nullptr;
+    if (nq > kStaticOrderQueries) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    uint32_t* buf = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+        }
+        buf = g_scratch_ptr[dev];
+    }
+    int nb, bshift;
+    order_shape(H.logn, &nb, &bshift);
+    if (nb > 4096) return hipErrorInvalidValue;
+    e = order_passes(H, q, nq, buf, s);
+    if (e == hipSuccess) *order = buf;
+    return e;
 }
 
 void free_order(uint32_t* order, hipStream_t s)

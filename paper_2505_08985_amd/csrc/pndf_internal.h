@@ -273,6 +273,10 @@ hipError_t launch_projected_area(const HierDev& H, const ProjArgs& a, hipStream_
 // Spatial processing order of a batch: queries bucketed by the Morton code of their
 // centre cell (64 x 64 buckets over the torus), stream-ordered workspace.
 hipError_t make_order(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s);
+// The same in the library's static per-GPU workspace (no allocation), for batches of
+// at most kStaticOrderQueries queries; the order must not be freed.
+constexpr int64_t kStaticOrderQueries = (int64_t)1 << 22;
+hipError_t make_order_static(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t** order, hipStream_t s);
 // Bucket count and coordinate shift of the spatial order for a map of side 2^logn.
 void order_shape(int logn, int* nb, int* bshift);
 void free_order(uint32_t* order, hipStream_t s);
