@@ -73,6 +73,7 @@ static void fill_view(pndf_hier* h)
     d.clu_det = h->clu_det;
     d.clu_deg = h->clu_deg;
     d.bbox_h = h->bbox_h;
+    d.bbox_k = h->bbox_k;
     d.quad = h->quad;
     d.n = m->n;
     d.L = m->L;
@@ -231,6 +232,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
     for (int l = 1; l <= m->L; ++l) nodes += (int64_t)(m->n >> l) * (m->n >> l);
     h->nodes = nodes;
     hipError_t e = hipMalloc(&h->bbox, sizeof(float4) * nodes);
+    if (e == hipSuccess) e = hipMalloc(&h->bbox_k, sizeof(uint2) * nodes);
     if (e == hipSuccess) e = hipMalloc(&h->quad, sizeof(QuadRec) * (size_t)(m->n >> 1) * (size_t)(m->n >> 1));
     if (cluster) {
         if (e == hipSuccess) e = hipMalloc(&h->bbox_all, sizeof(float4) * nodes);
@@ -246,7 +248,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + (cluster ? 16 + 8 + 32 + 4 + 8 + 1 : 0)) +
+    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 8 + 32 + 4 + 8 + 1 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
@@ -263,6 +265,7 @@ void pndf_destroy_hierarchy(pndf_hier* h)
     (void)hipFree(h->clu_det);
     (void)hipFree(h->clu_deg);
     (void)hipFree(h->bbox_h);
+    (void)hipFree(h->bbox_k);
     mesh_release(h->mesh);
     delete h;
 }

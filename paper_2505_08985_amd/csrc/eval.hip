@@ -122,13 +122,11 @@ constexpr uint32_t kHitPlane = 1u << 30, kHitCluster = 2u << 30;
 
 // Traversal list items are Morton codes (at most 24 bits); the top bit marks a node
 // whose region lies wholly inside the query's box, so that its descendants skip the
-// spatial tests.
+// spatial tests.  (With the cluster cut, a node's residual is compared with the
+// query's threshold when its parent expands -- the four children's residuals are
+// read with their boxes -- and a node under the cut goes to the cluster queue
+// instead of a list.)
 constexpr uint32_t kInside = 1u << 31;
-// With the cluster cut, bit 30 marks a node whose residual is within the query's
-// threshold (it answers with its two cluster triangles): decided when the node is
-// listed, from the four children's residuals read with their boxes, so popping a
-// node starts its own loads at once instead of waiting for its residual.
-constexpr uint32_t kCut = 1u << 30;
 constexpr uint32_t kCodeMask = (1u << 30) - 1u;
 
 // Inclusive same-sign test of a triangle's three edge values: h inside or on it.
@@ -398,31 +396,36 @@ __device__ __forceinline__ void queue_hits(uint32_t* hq, int& hn, uint32_t& pend
     wave_sync();
 }
 
-// A box stored as four halves (min x, min y | max x, max y).
-__device__ __forceinline__ float4 half_box(uint2 v)
+// Is the query normal inside a box stored as order keys (half_key) of its corners,
+// (min x | min y << 16, max x | max y << 16)?  The query's key is that of h rounded
+// to the nearest half: rounding is monotone, so a box that contains h contains it.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bool key_in_box(uint32_t hk, uint32_t lo, uint32_t hi)
 {
-    return make_float4(__half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu))),
-                       __half2float(__ushort_as_half((unsigned short)(v.x >> 16))),
-                       __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu))),
-                       __half2float(__ushort_as_half((unsigned short)(v.y >> 16))));
+    const u16x2 h = __builtin_bit_cast(u16x2, hk);
+    const u16x2 a = __builtin_elementwise_max(h, __builtin_bit_cast(u16x2, lo));
+    const u16x2 c = __builtin_elementwise_min(h, __builtin_bit_cast(u16x2, hi));
+    return (__builtin_bit_cast(uint32_t, a) == hk) & (__builtin_bit_cast(uint32_t, c) == hk);
 }
 
-__device__ __forceinline__ bool in_box(const QuerySetup& q, const float4& bb)
-{
-    return q.hx >= bb.x && q.hy >= bb.y && q.hx <= bb.z && q.hy <= bb.w;
-}
+// Cluster queue entry: level (4 bits) << 24 | Morton code of the node (< 2^24).
+constexpr int kCluShift = 24;
 
-// The shared descent.  List items are nodes (Morton codes) whose box contains h
-// and whose region meets the support box.  A lane takes one item: a node under the
-// cut answers with its cluster triangles; a level-1 node tests its 2 x 2 cells from
-// its leaf record; any other node loads its (up to) four overlapping children's
-// boxes together and pushes those that contain h.  Roots: every lane with root_ok
-// holds a root of level root_level (level 0: texel cell packed i | j << 16; else a
-// Morton code), box-tested here unless roots_tested.  With SPAWN (persistent
-// workers), while some worker of the plan is idle the wave gives away part of its
-// pending work before each step: half of the items of its highest non-empty list
-// (the largest subtrees it holds), if that level is at least split_level, become
-// tasks of the global queue.  A full queue simply leaves them here.
+// The shared descent.  List items are nodes (Morton codes) whose box contains h,
+// whose region meets the support box and which are not under the cluster cut.  A
+// lane takes one item: a level-1 node tests its 2 x 2 cells from its leaf record;
+// any other node loads its (up to) four overlapping children's boxes together and
+// keeps those that contain h: children under the cut go to the wave's cluster
+// queue, the others to the list of the level below.  The cluster queue is taken 64
+// nodes at a time, one per lane, each testing its node's two cluster triangles, so
+// the cluster tests and the descent never share a step (a step runs every branch
+// any lane takes).  Roots: every lane with root_ok holds a root of level
+// root_level (level 0: texel cell packed i | j << 16; else a Morton code),
+// box-tested here unless roots_tested.  With SPAWN (persistent workers), while
+// some worker of the plan is idle the wave gives away part of its pending work
+// before each step: half of the items of its highest non-empty list (the largest
+// subtrees it holds), if that level is at least split_level, become tasks of the
+// global queue.  A full queue simply leaves them here.
 template <int MODE, bool CUT, bool SPAWN, int KER>
 __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, int root_level,
                         bool root_ok, uint32_t root_item, bool roots_tested, int split_level,
@@ -430,9 +433,12 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 {
     static_assert(!SPAWN || MODE == kModeValue, "donation is only used by value-mode workers");
     const int lane = threadIdx.x & 63;
-    const float4* __restrict__ boxes = H.bbox;  // (the cut traversal reads H.bbox_h)
+    // node boxes as order keys: map triangles, or map and cluster triangles under the cut
+    const uint2* __restrict__ boxes = CUT ? H.bbox_h : H.bbox_k;
     uint32_t* hq = lists + H.L * kListCap;  // hit queue
+    uint32_t* cq = hq + kHitCap;            // cluster queue (CUT)
     int hn = 0;                             // queued hits (wave-uniform)
+    int cn = 0;                             // queued cluster nodes (wave-uniform)
     uint32_t pend = 0, ebase = 0;           // this lane's float32 hits not yet queued
     uint32_t nonempty = 0;   // bit l: list of level l non-empty (wave-uniform)
     int cntv = 0;            // lane l holds the size of list l
@@ -445,19 +451,22 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         }
     } else {
         bool ok = root_ok;
+        const uint32_t m = root_item & kCodeMask;
+        const int64_t idx = level_offset(H.logn, root_level) + m;
         if (ok && !roots_tested) {
             acc.nodes += 1;
-            ok = CUT ? in_box(q, half_box(H.bbox_h[level_offset(H.logn, root_level) + (root_item & kCodeMask)]))
-                     : in_box(q, boxes[level_offset(H.logn, root_level) + (root_item & kCodeMask)]);
+            const uint2 b = boxes[idx];
+            ok = key_in_box(q.hkey, b.x, b.y);
         }
-        const uint64_t bal = __ballot(ok);
-        const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-        const int tot = __popcll(bal);
-        if (ok) {
-            uint32_t it = root_item & ~kCut;
-            if (CUT && H.clu_e[level_offset(H.logn, root_level) + (it & kCodeMask)] <= q.t) it |= kCut;
-            lists[(root_level - 1) * kListCap + pos] = it;
+        const bool cut = CUT && ok && H.clu_e[idx] <= q.t;
+        const uint64_t bl = __ballot(ok && !cut);
+        if (ok && !cut) lists[(root_level - 1) * kListCap + __popcll(bl & ((1ull << lane) - 1ull))] = root_item;
+        if (CUT) {
+            const uint64_t bc = __ballot(cut);
+            if (cut) cq[__popcll(bc & ((1ull << lane) - 1ull))] = ((uint32_t)root_level << kCluShift) | m;
+            cn = __popcll(bc);
         }
+        const int tot = __popcll(bl);
         if (lane == root_level) cntv = tot;
         if (tot) nonempty |= 1u << root_level;
         wave_sync();
@@ -467,11 +476,25 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
     unsigned hungry = 0;
     while (true) {
         queue_hits(hq, hn, pend, ebase);
-        if (hn >= 64 || (hn > 0 && !nonempty)) {
+        if (hn >= 64 || (hn > 0 && !nonempty && cn == 0)) {
             // (lanes still holding hits imply a full queue, so they get here too)
             const int c = min(hn, 64);
             hn -= c;
             hit_round<MODE, KER>(H, q, hq + hn, c, acc, rec);
+            continue;
+        }
+        if (CUT && (cn >= 64 || (cn > 0 && !nonempty))) {
+            // a round of cluster nodes, one per lane (every lane's hits are queued)
+            const int c = min(cn, 64);
+            cn -= c;
+            if (lane < c) {
+                const uint32_t e = cq[cn + lane];
+                const int lev = (int)(e >> kCluShift);
+                const uint32_t m = e & ((1u << kCluShift) - 1u);
+                pend = cluster_mask(H, q, lev, level_offset(H.logn, lev) + m, acc);
+                ebase = kHitCluster | ((uint32_t)lev << 25) | (m << 1);
+            }
+            wave_sync();
             continue;
         }
         if (!nonempty) break;
@@ -523,7 +546,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                     if (ch == d) nonempty &= ~(1u << lh);
                     acc.donated = true;
                     wave_sync();
-                    if (!nonempty) break;  // (cannot happen: one item is always kept)
+                    if (!nonempty) continue;  // (cannot happen: one item is always kept)
                 }
             }
         }
@@ -552,34 +575,19 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         uint32_t m4 = 0;      // 4m: the first child's code
         uint32_t tested = 0;  // child boxes read by this lane
         uint32_t cut4 = 0;    // children under the cut (bit c)
-        uint32_t entry = 0;   // the lane's list item (Morton code | kInside | kCut)
+        uint32_t entry = 0;   // the lane's list item (Morton code | kInside)
         if (lane < k) {
             entry = lists[(l - 1) * kListCap + base + lane];
             const uint32_t m = entry & kCodeMask;
             const bool inside = (entry & kInside) != 0u;
-            const int64_t idx = level_offset(H.logn, l) + m;
-            if (CUT && (entry & kCut)) {
-                pend = cluster_mask(H, q, l, idx, acc);
-                ebase = kHitCluster | ((uint32_t)l << 25) | (m << 1);
-            } else if (l == 1) {
+            if (l == 1) {
                 pend = leaf_quad_mask(H, q, m, inside, rx0, ry0, acc);
                 ebase = m << 3;
             } else {
-                // the four child boxes are one Morton segment (64 B, or 32 B in half
-                // precision under the cut): loaded whole (no extra traffic), children
-                // outside the support masked afterwards
-                float4 b0, b1, b2, b3;
-                if (CUT) {
-                    // the boxes of map and cluster triangles, as halves rounded outward
-                    const uint4* hb =
-                        reinterpret_cast<const uint4*>(H.bbox_h + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
-                    const uint4 h01 = hb[0], h23 = hb[1];
-                    b0 = half_box(make_uint2(h01.x, h01.y)); b1 = half_box(make_uint2(h01.z, h01.w));
-                    b2 = half_box(make_uint2(h23.x, h23.y)); b3 = half_box(make_uint2(h23.z, h23.w));
-                } else {
-                    const float4* cb = boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m;
-                    b0 = cb[0]; b1 = cb[1]; b2 = cb[2]; b3 = cb[3];
-                }
+                // the four child boxes are one Morton segment (32 B of keys): loaded
+                // whole, children outside the support masked afterwards
+                const uint4* cb = reinterpret_cast<const uint4*>(boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
+                const uint4 b01 = cb[0], b23 = cb[1];
                 if (CUT) {
                     // the children's residuals: 16 B at a multiple of 4 nodes
                     const float4 ce = *reinterpret_cast<const float4*>(H.clu_e + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
@@ -597,32 +605,45 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                     cin = quad_bits(pair_in_run(I, rx.ai, rx.ni, mk), pair_in_run(J, ry.ai, ry.ni, mk));
                 }
                 tested = (uint32_t)__popc(ov);
-                chm = ((uint32_t)in_box(q, b0) | ((uint32_t)in_box(q, b1) << 1) | ((uint32_t)in_box(q, b2) << 2) |
-                       ((uint32_t)in_box(q, b3) << 3)) & ov;
+                chm = ((uint32_t)key_in_box(q.hkey, b01.x, b01.y) | ((uint32_t)key_in_box(q.hkey, b01.z, b01.w) << 1) |
+                       ((uint32_t)key_in_box(q.hkey, b23.x, b23.y) << 2) |
+                       ((uint32_t)key_in_box(q.hkey, b23.z, b23.w) << 3)) & ov;
                 m4 = 4 * m;
             }
         }
         if (l >= 2) {
+            // Children under the cut go to the cluster queue (which holds fewer than 64
+            // entries here, so up to 64 x 4 more fit), the others are appended to the
+            // level below (which holds fewer than 64 items: it is empty or the short
+            // lowest list).  A parent whose list children would run past the list's end
+            // goes back to its own list whole and is expanded again later.  Child
+            // positions grow with the lane, so the parents that fit are a prefix and the
+            // first one with children always fits.
+            const uint32_t chl = CUT ? chm & ~cut4 : chm, chc = CUT ? chm & cut4 : 0u;
             int total;
-            const int nch = __popc(chm);
+            const int nch = __popc(chl);
             const int pos = wave_prefix_small(nch, &total);
-            // The children are appended to the level below (which holds fewer than 64
-            // items: it is empty or the short lowest list).  A parent whose children
-            // would run past the end goes back to its own list whole and is expanded
-            // again later.  Child positions grow with the lane, so the parents that fit
-            // are a prefix and the first one with children always fits.
             const int below = __builtin_amdgcn_readlane(cntv, l - 1);
             const bool back = nch > 0 && below + pos + nch > kListCap;
             const uint64_t bb = __ballot(back);
             uint32_t* dst = lists + (l - 2) * kListCap + below;
             if (!back) {
-                // child c goes to pos + (number of passing children before it)
+                // child c goes to pos + (number of list children before it)
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (chm & (1u << c))
-                        dst[pos + __popc(chm & ((1u << c) - 1u))] =
-                            (m4 + c) | ((cin >> c) & 1u ? kInside : 0u) | ((cut4 >> c) & 1u ? kCut : 0u);
+                    if (chl & (1u << c))
+                        dst[pos + __popc(chl & ((1u << c) - 1u))] = (m4 + c) | ((cin >> c) & 1u ? kInside : 0u);
                 acc.nodes += tested;
+            }
+            if (CUT) {
+                const uint32_t mine = back ? 0u : chc;
+                int ctot;
+                const int cpos = cn + wave_prefix_small(__popc(mine), &ctot);
+                const uint32_t lev = (uint32_t)(l - 1) << kCluShift;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (mine & (1u << c)) cq[cpos + __popc(mine & ((1u << c) - 1u))] = lev | (m4 + c);
+                cn += ctot;
             }
             const int pushed = bb ? __builtin_amdgcn_readlane(pos, __builtin_ctzll(bb)) : total;
             if (lane == l - 1) cntv = below + pushed;
@@ -881,7 +902,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
 {
     extern __shared__ uint32_t lds[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t* lists = lds + (size_t)wave * wave_lds_words(H.L);
+    uint32_t* lists = lds + (size_t)wave * wave_lds_words(H.L, CUT);
     QueueCtl* ctl = pa.Q.ctl;
     const long long nq = ctl->nq;
     const pndf_query* qs = ctl->q;
@@ -1085,7 +1106,7 @@ hipError_t launch_mode(const HierDev& H, const EvalArgs& a0, int algo, hipStream
             hipLaunchKernelGGL((k_eval_brute<MODE, KER>), dim3(blocks), dim3(256), 0, s, H, a);
         } else {
             const unsigned blocks = (unsigned)a.slots;
-            const size_t lds = sizeof(uint32_t) * wave_lds_words(H.L);
+            const size_t lds = sizeof(uint32_t) * wave_lds_words(H.L, a.tau > 0.f);
             if (a.tau > 0.f)
                 hipLaunchKernelGGL((k_eval_plain<MODE, true, KER>), dim3(blocks), dim3(64), lds, s, H, a);
             else
@@ -1332,7 +1353,7 @@ static void* persist_func(const PersistPlan& P)
 int persist_resident_blocks(const HierDev& H, const PersistPlan& P)
 {
     int nb = 0;
-    const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(H.L);
+    const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(H.L, P.tau > 0.f);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_func(P), 256, lds) != hipSuccess) return 0;
     return nb;
 }
@@ -1409,7 +1430,7 @@ hipError_t persist_graph_build(const HierDev& H, PersistPlan& P)
     work.func = persist_func(P);
     work.gridDim = dim3((unsigned)P.blocks);
     work.blockDim = dim3(256);
-    work.sharedMemBytes = (unsigned)(sizeof(uint32_t) * 4 * wave_lds_words(H.L));
+    work.sharedMemBytes = (unsigned)(sizeof(uint32_t) * 4 * wave_lds_words(H.L, P.tau > 0.f));
     work.kernelParams = P.wargs;
     work.extra = nullptr;
     P.fargs[0] = &P.ctl;
@@ -1457,7 +1478,7 @@ hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float*
         hipLaunchKernelGGL(k_porder_scatter, dim3(order_grid(P.max_nq)), dim3(256), 0, s, P.ctl, P.okey,
                            P.ohist, P.order);
     }
-    const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(P.H.L);
+    const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(P.H.L, P.tau > 0.f);
     void* args[] = {&P.H, &P.pa};
     const hipError_t e = hipLaunchKernel(persist_func(P), dim3((unsigned)P.blocks), dim3(256), args, lds, s);
     if (e != hipSuccess) return e;

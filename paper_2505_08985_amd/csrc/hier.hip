@@ -443,18 +443,23 @@ hipError_t export_rowmajor(const void* src, void* dst, int m, int words, hipStre
     return hipGetLastError();
 }
 
-// The cut traversal's boxes in half precision, minima rounded down and maxima up: a
-// rounded box contains the exact one, so it prunes a little less but never wrongly,
-// and a parent's four child boxes take 32 B instead of 64 (the traversal under the
-// cut is bound by memory traffic; the float32 boxes stay for the exports).
-__global__ void k_half_boxes(const float4* __restrict__ src, uint2* __restrict__ dst, int64_t n)
+// The traversal's boxes in half precision, minima rounded down and maxima up, as
+// order keys (half_key): a rounded box contains the exact one, so it prunes a little
+// less but never wrongly; four child boxes take 32 B instead of 64 and each test is
+// two packed 16-bit integer operations (the float32 boxes stay for the exports).
+__global__ void k_key_boxes(const float4* __restrict__ src, uint2* __restrict__ dst, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 b = src[i];
-    const uint32_t x0 = __half_as_ushort(__float2half_rd(b.x)), y0 = __half_as_ushort(__float2half_rd(b.y));
-    const uint32_t x1 = __half_as_ushort(__float2half_ru(b.z)), y1 = __half_as_ushort(__float2half_ru(b.w));
-    dst[i] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+    uint32_t x0 = __half_as_ushort(__float2half_rd(b.x)), y0 = __half_as_ushort(__float2half_rd(b.y));
+    uint32_t x1 = __half_as_ushort(__float2half_ru(b.z)), y1 = __half_as_ushort(__float2half_ru(b.w));
+    // the zeros: a minimum of +0 becomes -0, a maximum of -0 becomes +0
+    if (x0 == 0u) x0 = 0x8000u;
+    if (y0 == 0u) y0 = 0x8000u;
+    if (x1 == 0x8000u) x1 = 0u;
+    if (y1 == 0x8000u) y1 = 0u;
+    dst[i] = make_uint2(half_key(x0) | (half_key(y0) << 16), half_key(x1) | (half_key(y1) << 16));
 }
 
 hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
@@ -525,9 +530,10 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
         err = hipGetLastError();
         if (err == hipSuccess && h->cluster) err = residual(level);
     }
-    if (err == hipSuccess && h->cluster) {
-        hipLaunchKernelGGL(k_half_boxes, dim3((unsigned)((h->nodes + 255) / 256)), dim3(256), 0, s, h->bbox_all,
-                           h->bbox_h, h->nodes);
+    if (err == hipSuccess) {
+        const unsigned g = (unsigned)((h->nodes + 255) / 256);
+        hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox, h->bbox_k, h->nodes);
+        if (h->cluster) hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_all, h->bbox_h, h->nodes);
         err = hipGetLastError();
     }
     if (err == hipSuccess) err = hipStreamSynchronize(s);

@@ -40,9 +40,17 @@ int64_t launch_chunk();
 // them 64 at a time (fewer than 64 wait between steps; one step adds at most 64 x 8).
 constexpr int kHitCap = 128;
 
-// 32-bit LDS words per wavefront of the descent: one node list per level 1..L, then
-// the hit queue.
-__host__ __device__ inline size_t wave_lds_words(int L) { return (size_t)L * kListCap + kHitCap; }
+// Cluster queue of a wavefront (with the cluster cut): nodes under the cut wait here
+// to be tested 64 at a time; it holds fewer than 64 before a descent step, which adds
+// at most 64 x 4.
+constexpr int kCluCap = 64 + 4 * 64;
+
+// 32-bit LDS words per wavefront of the descent: one node list per level 1..L, the
+// hit queue, and with the cut the cluster queue.
+__host__ __device__ inline size_t wave_lds_words(int L, bool cut)
+{
+    return (size_t)L * kListCap + kHitCap + (cut ? kCluCap : 0);
+}
 
 // Level-1 leaf record: the 3 x 3 texel normals of a 2 x 2 cell block (row-major,
 // texel (2I + x, 2J + y) at t[3 y + x], periodic) and the clamp bits of its four
@@ -63,7 +71,8 @@ struct HierDev {
     const float2* det;      // n x n Jacobians used by the evaluation (lower, upper)
     const float4* bbox;     // all levels packed: min x, min y, max x, max y (map triangles)
     const float4* bbox_all; // same, extended by cluster triangles (nullptr without clusters)
-    const uint2* bbox_h;    // bbox_all as halves rounded outward (min down, max up): the cut traversal's boxes
+    const uint2* bbox_k;    // bbox as order keys of halves rounded outward (min down, max up): see half_key
+    const uint2* bbox_h;    // bbox_all the same way: the cut traversal's boxes
     const float4* clu_n;    // 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x, N2.y, N3.x, N3.y)
     const float* clu_e;     // e^l per node
     const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
@@ -73,6 +82,16 @@ struct HierDev {
     float eps;
     float rho;              // circumradius of the clamp replacement triangle (area eps / 2)
 };
+
+// Order key of a half-precision value (IEEE binary16 bits): unsigned keys compare
+// like the values (negative values mirrored below 0x8000, zero signs aside), so a
+// box test is two packed 16-bit integer min / max operations.  Box keys are
+// normalised so that the two zeros never exclude: a minimum of +0 is stored as -0
+// (key 0x7fff) and a maximum of -0 as +0 (key 0x8000).
+__host__ __device__ __forceinline__ uint32_t half_key(uint32_t bits)
+{
+    return (bits & 0x8000u) ? (~bits & 0xffffu) : (bits | 0x8000u);
+}
 
 // First node of level l (1 <= l <= logn + 1) in the packed per-level arrays: the
 // levels below hold sum_{k=1}^{l-1} (n / 2^k)^2 = (n^2 - (n / 2^(l-1))^2) / 3 nodes.
@@ -204,6 +223,7 @@ struct pndf_hier {
     int64_t nodes = 0;
     float4* bbox = nullptr;
     float4* bbox_all = nullptr;
+    uint2* bbox_k = nullptr;
     uint2* bbox_h = nullptr;
     float4* clu_n = nullptr;
     float* clu_e = nullptr;
@@ -300,6 +320,7 @@ struct QuerySetup {
     int cxlo, cxhi, cylo, cyhi;  // included unrolled cell range per axis
     int l0;                      // entry level
     float t;                     // cut threshold fl(fl(rx ry) tau)
+    uint32_t hkey;               // order keys (half_key) of h rounded to halves: x | y << 16
     double kx, ky;               // Gaussian: log2(e) / (2 sigma^2)
     double norm;                 // the kernel's peak: 1 / (2 pi sx sy), 1 / (pi rx ry) or 1 / (4 rx ry)
     int fexp;                    // binary point of the exact accumulator (units of 2^fexp)
@@ -321,6 +342,8 @@ __device__ inline QuerySetup setup_query(const pndf_query& qr, float s2r, float 
     q.valid = ok;
     q.rx = rx;
     q.ry = ry;
+    q.hkey = half_key(__half_as_ushort(__float2half_rn(qr.hx))) |
+             (half_key(__half_as_ushort(__float2half_rn(qr.hy))) << 16);
     if (!ok) {
         q.cxlo = q.cylo = 0; q.cxhi = q.cyhi = -1; q.l0 = 0; q.t = -1.f;
         q.kx = q.ky = q.norm = 0.0;
@@ -386,6 +409,7 @@ __device__ __forceinline__ QuerySetup uniform_query(const QuerySetup& q)
     u.cylo = __builtin_amdgcn_readfirstlane(q.cylo); u.cyhi = __builtin_amdgcn_readfirstlane(q.cyhi);
     u.l0 = __builtin_amdgcn_readfirstlane(q.l0);
     u.t = uniform_f32(q.t);
+    u.hkey = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.hkey);
     u.kx = uniform_f64(q.kx); u.ky = uniform_f64(q.ky); u.norm = uniform_f64(q.norm);
     u.fexp = __builtin_amdgcn_readfirstlane(q.fexp);
     u.valid = __builtin_amdgcn_readfirstlane((int)q.valid) != 0;
