@@ -86,17 +86,18 @@ def build_workcount(force=False):
     return WORKCOUNT_LIB
 
 
-def count_work(n, boxes, es, q, tau, s2r):
+def count_work(n, boxes, own, es, q, tau, s2r):
     """CPU counting pass: (nodes, cells, clusters) per query by the descent's rules."""
     import ctypes
     lib = ctypes.CDLL(build_workcount())
     fp = ctypes.POINTER(ctypes.c_float)
-    lib.wc_count.argtypes = [ctypes.c_int, fp, fp, fp, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+    lib.wc_count.argtypes = [ctypes.c_int, fp, fp, fp, fp, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                              ctypes.POINTER(ctypes.c_uint64)]
     lib.wc_count.restype = ctypes.c_int
     q = np.ascontiguousarray(q, dtype=np.float32)
     out = np.zeros((len(q), 3), dtype=np.uint64)
-    rc = lib.wc_count(n, boxes.ctypes.data_as(fp), es.ctypes.data_as(fp) if es is not None else None,
+    rc = lib.wc_count(n, boxes.ctypes.data_as(fp), own.ctypes.data_as(fp) if own is not None else None,
+                      es.ctypes.data_as(fp) if es is not None else None,
                       q.ctypes.data_as(fp), len(q), tau, s2r, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     if rc:
         raise RuntimeError("wc_count failed (%d)" % rc)
@@ -114,13 +115,15 @@ def algorithmic_work(P, hier, q, tq, n, tau, s2r, kw, per_octave=512, seed=3):
     also gives the kernel's own instrumented counts for comparison)."""
     import torch
     L = int(np.log2(n))
-    boxes, es = [], []
+    boxes, own, es = [], [], []
     for level in range(1, L + 1):
         ex = P.hier_export_level(hier, level)
         boxes.append(ex["bbox_all" if tau > 0 else "bbox"].cpu().numpy().reshape(-1))
         if tau > 0:
+            own.append(ex["bbox_clu"].cpu().numpy().reshape(-1))
             es.append(ex["clu_e"].cpu().numpy().reshape(-1))
     boxes = np.ascontiguousarray(np.concatenate(boxes))
+    own = np.ascontiguousarray(np.concatenate(own)) if tau > 0 else None
     es = np.ascontiguousarray(np.concatenate(es)) if tau > 0 else None
     oq = sigma_octave(q)
     rng = np.random.default_rng(seed)
@@ -130,7 +133,7 @@ def algorithmic_work(P, hier, q, tq, n, tau, s2r, kw, per_octave=512, seed=3):
     for o in np.unique(oq):
         pool = np.where(oq == o)[0]
         pick = np.sort(rng.choice(pool, min(per_octave, len(pool)), replace=False))
-        w = count_work(n, boxes, es, q[pick], tau, s2r)
+        w = count_work(n, boxes, own, es, q[pick], tau, s2r)
         _, c = P.eval_counts(hier, tq[torch.from_numpy(pick).cuda()], tau=tau, **kw)
         c = c.cpu().numpy().astype(np.float64)
         mean = np.concatenate([w.mean(axis=0), [c[:, 3].mean()]])

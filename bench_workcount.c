@@ -9,11 +9,13 @@
  * l0 = min(L, smallest l with 2^l >= max(r_x, r_y)), cut threshold
  * t = fl32(fl32(r_x r_y) tau).  The roots are every level-l0 node with a periodic
  * image meeting the cell range (cells when l0 = 0).  A visited node counts one box
- * test: it stops when h lies outside its normal-space box; with tau > 0 and
- * e^l <= t it is one cluster node (its two triangles); at level 1 it counts its
- * cells that meet the range; otherwise its children that meet the range are
- * visited.  The boxes are those of the map's triangles (tau = 0) or of the map's
- * and cluster triangles (tau > 0), as the hierarchy stores them in float32.
+ * test: with tau > 0 and e^l <= t it is one cluster node (its two triangles
+ * tested) when h lies inside its box, which from level 2 up is that of its own two
+ * cluster triangles; otherwise it stops when h lies outside its box, at level 1
+ * counts its cells that meet the range, and above visits its children that meet
+ * the range.  The boxes are those of the map's triangles (tau = 0) or of the map's
+ * and cluster triangles beneath the node (tau > 0), as the hierarchy stores them
+ * in float32.
  *
  * Build: gcc -O2 -shared -fPIC -fopenmp bench_workcount.c -o bench_workcount.so
  */
@@ -23,6 +25,7 @@
 typedef struct {
     int n, L;
     const float* box;  /* levels 1..L packed, row-major nodes, (min x, min y, max x, max y) */
+    const float* own;  /* the same for the node's own cluster triangles (NULL when tau = 0) */
     const float* e;    /* levels 1..L packed, row-major nodes (NULL when tau = 0) */
     long off[32];
 } hier_t;
@@ -51,11 +54,12 @@ static void visit(const hier_t* h, walk_t* w, int l, long I, long J)
     const long k = h->off[l] + J * m + I;
     const float* b = h->box + 4 * k;
     w->nodes++;
-    if (!(w->hx >= b[0] && w->hy >= b[1] && w->hx <= b[2] && w->hy <= b[3])) return;
     if (w->cut && h->e[k] <= w->t) {
-        w->clusters++;
+        const float* c = l >= 2 ? h->own + 4 * k : b;
+        if (w->hx >= c[0] && w->hy >= c[1] && w->hx <= c[2] && w->hy <= c[3]) w->clusters++;
         return;
     }
+    if (!(w->hx >= b[0] && w->hy >= b[1] && w->hx <= b[2] && w->hy <= b[3])) return;
     const long s = 1L << (l - 1);
     for (int dj = 0; dj < 2; dj++)
         for (int di = 0; di < 2; di++) {
@@ -73,7 +77,7 @@ static void visit(const hier_t* h, walk_t* w, int l, long I, long J)
  * q: nq queries (x, y, sx, sy, hx, hy); out: nq x 3 (nodes, cells, clusters).
  * Invalid queries (as the evaluation defines them) count nothing.
  */
-int wc_count(int n, const float* box, const float* e, const float* q, int64_t nq, float tau, float s2r,
+int wc_count(int n, const float* box, const float* own, const float* e, const float* q, int64_t nq, float tau, float s2r,
              uint64_t* out)
 {
     hier_t h;
@@ -81,8 +85,9 @@ int wc_count(int n, const float* box, const float* e, const float* q, int64_t nq
     h.L = 0;
     while ((1 << h.L) < n) h.L++;
     if ((1 << h.L) != n || h.L < 1 || h.L > 30) return 1;
-    if (tau > 0.0f && !e) return 2;
+    if (tau > 0.0f && (!e || !own)) return 2;
     h.box = box;
+    h.own = own;
     h.e = e;
     long off = 0;
     for (int l = 1; l <= h.L; l++) {

@@ -442,13 +442,15 @@ pndf_status pndf_hier_info(const pndf_hier* h, int32_t* levels, int32_t* cluster
  * node order (J * (N >> level) + I), into caller device buffers (any may be NULL):
  *   d_bbox      4 float32 per node: min x, min y, max x, max y over the map's triangles
  *   d_bbox_all  the same box extended by every cluster triangle at or below the node
+ *   d_bbox_clu  4 float32 per node: the box of the node's own two cluster triangles
+ *               (what the cut traversal tests a node under the cut against)
  *   d_clu_n     8 float32 per node: cluster normals N0..N3 (corners (0,0),(1,0),(0,1),(1,1))
  *   d_clu_e     1 float32 per node: e^l
  *   d_clu_det   2 float32 per node: Jacobians of the lower/upper cluster triangle
  *               (eps when clamped)
  * The cluster arrays need a hierarchy built with clusters (else PNDF_EINVAL). */
 pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_bbox,
-                                   float* d_bbox_all, float* d_clu_n, float* d_clu_e,
+                                   float* d_bbox_all, float* d_bbox_clu, float* d_clu_n, float* d_clu_e,
                                    float* d_clu_det, void* stream);
 
 #ifdef __cplusplus

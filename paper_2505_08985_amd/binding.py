@@ -70,7 +70,7 @@ _last_error = _sig("pndf_last_error", ctypes.c_char_p, [])
 _mesh_info = _sig("pndf_mesh_info", _i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_f32), ctypes.POINTER(_i64)])
 _mesh_export = _sig("pndf_mesh_export", _i32, [_vp, _vp, _vp, _vp])
 _hier_info = _sig("pndf_hier_info", _i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64)])
-_hier_export = _sig("pndf_hier_export_level", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp])
+_hier_export = _sig("pndf_hier_export_level", _i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 
 _default_tuning = _sig("pndf_default_tuning", _i32, [_vp, ctypes.POINTER(Tuning)])
 _plan_create = _sig("pndf_plan_create", _i32, [_vp, _i64, ctypes.POINTER(EvalOpts), ctypes.POINTER(Tuning), _vp,
@@ -316,16 +316,17 @@ def hier_export_level(hier, level, stream=None):
     bbox = torch.empty((m, m, 4), dtype=torch.float32, device="cuda")
     if hier.cluster:
         bbox_all = torch.empty((m, m, 4), dtype=torch.float32, device="cuda")
+        bbox_clu = torch.empty((m, m, 4), dtype=torch.float32, device="cuda")
         clu_n = torch.empty((m, m, 4, 2), dtype=torch.float32, device="cuda")
         clu_e = torch.empty((m, m), dtype=torch.float32, device="cuda")
         clu_det = torch.empty((m, m, 2), dtype=torch.float32, device="cuda")
-        ptrs = [_vp(t.data_ptr()) for t in (bbox_all, clu_n, clu_e, clu_det)]
+        ptrs = [_vp(t.data_ptr()) for t in (bbox_all, bbox_clu, clu_n, clu_e, clu_det)]
     else:
-        bbox_all = clu_n = clu_e = clu_det = None
-        ptrs = [None] * 4
+        bbox_all = bbox_clu = clu_n = clu_e = clu_det = None
+        ptrs = [None] * 5
     _check(_hier_export(hier.handle, int(level), _vp(bbox.data_ptr()), *ptrs, _stream(stream)),
            "pndf_hier_export_level")
-    return dict(bbox=bbox, bbox_all=bbox_all, clu_n=clu_n, clu_e=clu_e, clu_det=clu_det)
+    return dict(bbox=bbox, bbox_all=bbox_all, bbox_clu=bbox_clu, clu_n=clu_n, clu_e=clu_e, clu_det=clu_det)
 
 
 class Plan:

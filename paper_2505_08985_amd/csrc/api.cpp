@@ -73,6 +73,7 @@ static void fill_view(pndf_hier* h)
     d.clu_det = h->clu_det;
     d.clu_deg = h->clu_deg;
     d.bbox_h = h->bbox_h;
+    d.bbox_c = h->bbox_c;
     d.bbox_k = h->bbox_k;
     d.quad = h->quad;
     d.n = m->n;
@@ -241,6 +242,8 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         if (e == hipSuccess) e = hipMalloc(&h->clu_det, sizeof(float2) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_deg, nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_h, sizeof(uint2) * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->bbox_clu, sizeof(float4) * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->bbox_c, sizeof(uint2) * nodes);
     }
     fill_view(h);
     if (e == hipSuccess) e = build_hierarchy_levels(h, (hipStream_t)stream);
@@ -248,7 +251,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 8 + 32 + 4 + 8 + 1 : 0)) +
+    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 8 + 16 + 8 + 32 + 4 + 8 + 1 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
@@ -265,6 +268,8 @@ void pndf_destroy_hierarchy(pndf_hier* h)
     (void)hipFree(h->clu_det);
     (void)hipFree(h->clu_deg);
     (void)hipFree(h->bbox_h);
+    (void)hipFree(h->bbox_clu);
+    (void)hipFree(h->bbox_c);
     (void)hipFree(h->bbox_k);
     mesh_release(h->mesh);
     delete h;
@@ -280,12 +285,12 @@ pndf_status pndf_hier_info(const pndf_hier* h, int32_t* levels, int32_t* cluster
 }
 
 pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_bbox,
-                                   float* d_bbox_all, float* d_clu_n, float* d_clu_e,
+                                   float* d_bbox_all, float* d_bbox_clu, float* d_clu_n, float* d_clu_e,
                                    float* d_clu_det, void* stream)
 {
     if (!h) return invalid("hierarchy is NULL");
     if (level < 1 || level > h->L) return invalid("level out of range");
-    if (!h->cluster && (d_bbox_all || d_clu_n || d_clu_e || d_clu_det))
+    if (!h->cluster && (d_bbox_all || d_bbox_clu || d_clu_n || d_clu_e || d_clu_det))
         return invalid("hierarchy has no clusters");
     hipStream_t s = (hipStream_t)stream;
     const int64_t off = level_offset(h->dev.logn, level);
@@ -299,6 +304,7 @@ pndf_status pndf_hier_export_level(const pndf_hier* h, int32_t level, float* d_b
     cp(d_bbox, h->bbox + off, 4);
     if (h->cluster) {
         cp(d_bbox_all, h->bbox_all + off, 4);
+        cp(d_bbox_clu, h->bbox_clu + off, 4);
         cp(d_clu_n, h->clu_n + 2 * off, 8);
         cp(d_clu_e, h->clu_e + off, 1);
         cp(d_clu_det, h->clu_det + off, 2);

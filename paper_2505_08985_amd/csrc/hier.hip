@@ -205,6 +205,7 @@ __device__ __forceinline__ float4 empty_box()
 struct LevelOut {
     float4* bbox;
     float4* bbox_all;
+    float4* bbox_clu;
     float4* clu_n;
     float* clu_e;
     float2* clu_det;
@@ -294,6 +295,7 @@ __global__ void k_level1(HierDev H, LevelOut o, QuadRec* __restrict__ quad, doub
     double N[4][2];
     solve_cluster(lo, up, N);
     float4 cb = store_cluster(H, o, t, 2, N, nfit);
+    o.bbox_clu[t] = cb;
     box_union(cb, box);
     o.bbox_all[t] = cb;
 }
@@ -322,6 +324,7 @@ __global__ void k_level_up(HierDev H, int level, LevelOut o, const float4* __res
     double N[4][2];
     solve_cluster(lo, up, N);
     float4 cb = store_cluster(H, o, t, 1 << level, N, nfit);
+    o.bbox_clu[t] = cb;
     box_union(cb, cbox_all[c00]);
     box_union(cb, cbox_all[c00 + 1]);
     box_union(cb, cbox_all[c00 + 2]);
@@ -496,6 +499,7 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
         const int64_t off = level_offset(H.logn, level);
         o.bbox = h->bbox + off;
         o.bbox_all = h->cluster ? h->bbox_all + off : nullptr;
+        o.bbox_clu = h->cluster ? h->bbox_clu + off : nullptr;
         o.clu_n = h->cluster ? h->clu_n + 2 * off : nullptr;
         o.clu_e = h->cluster ? h->clu_e + off : nullptr;
         o.clu_det = h->cluster ? h->clu_det + off : nullptr;
@@ -533,7 +537,10 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
     if (err == hipSuccess) {
         const unsigned g = (unsigned)((h->nodes + 255) / 256);
         hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox, h->bbox_k, h->nodes);
-        if (h->cluster) hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_all, h->bbox_h, h->nodes);
+        if (h->cluster) {
+            hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_all, h->bbox_h, h->nodes);
+            hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_clu, h->bbox_c, h->nodes);
+        }
         err = hipGetLastError();
     }
     if (err == hipSuccess) err = hipStreamSynchronize(s);

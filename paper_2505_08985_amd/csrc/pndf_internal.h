@@ -73,6 +73,7 @@ struct HierDev {
     const float4* bbox_all; // same, extended by cluster triangles (nullptr without clusters)
     const uint2* bbox_k;    // bbox as order keys of halves rounded outward (min down, max up): see half_key
     const uint2* bbox_h;    // bbox_all the same way: the cut traversal's boxes
+    const uint2* bbox_c;    // the node's own two cluster triangles' box, the same way
     const float4* clu_n;    // 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x, N2.y, N3.x, N3.y)
     const float* clu_e;     // e^l per node
     const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
@@ -225,6 +226,8 @@ struct pndf_hier {
     float4* bbox_all = nullptr;
     uint2* bbox_k = nullptr;
     uint2* bbox_h = nullptr;
+    float4* bbox_clu = nullptr;   // box of the node's own cluster triangles (float32)
+    uint2* bbox_c = nullptr;
     float4* clu_n = nullptr;
     float* clu_e = nullptr;
     float2* clu_det = nullptr;

@@ -162,6 +162,24 @@ def test_hierarchy_boxes_and_clusters(P, oracle_mod, name):
         assert (ball[..., 0] <= box[..., 0]).all() and (ball[..., 2] >= box[..., 2]).all()
         cn = ex["clu_n"].cpu().numpy()
         cdet = ex["clu_det"].cpu().numpy()
+        # the node's own cluster box: inside the subtree's, covering its two cluster
+        # triangles (a clamped one by its replacement's square), and tight
+        bclu = ex["bbox_clu"].cpu().numpy().astype(np.float64)
+        assert (ball[..., :2] <= bclu[..., :2]).all() and (ball[..., 2:] >= bclu[..., 2:]).all()
+        cc = 0.5 * (cn[:, :, 1, :] + cn[:, :, 2, :])          # float32, as the kernels form it
+        rl = np.float32(rho) * np.float32(s)
+        own_lo = np.full((m, m, 2), np.inf)
+        own_hi = np.full((m, m, 2), -np.inf)
+        for half, idx in ((0, (0, 1, 2)), (1, (3, 2, 1))):
+            v = cn[:, :, list(idx), :].astype(np.float64)
+            dv = np.abs((v[:, :, 2, 0] - v[:, :, 0, 0]) * (v[:, :, 1, 1] - v[:, :, 0, 1])
+                        - (v[:, :, 2, 1] - v[:, :, 0, 1]) * (v[:, :, 1, 0] - v[:, :, 0, 0])) / (s * s)
+            cl = (dv < EPS32)[..., None]
+            own_lo = np.minimum(own_lo, np.where(cl, cc - rl, v.min(axis=2)))
+            own_hi = np.maximum(own_hi, np.where(cl, cc + rl, v.max(axis=2)))
+        assert (bclu[..., :2] <= own_lo).all() and (bclu[..., 2:] >= own_hi).all()
+        slack = 2e-6 + 2e-6 * float(rl)
+        assert (bclu[..., :2] >= own_lo - slack).all() and (bclu[..., 2:] <= own_hi + slack).all()
         for half, idx in ((0, (0, 1, 2)), (1, (3, 2, 1))):
             v = cn[:, :, list(idx), :]
             d = np.abs((v[:, :, 2, 0].astype(np.float64) - v[:, :, 0, 0]) * (v[:, :, 1, 1].astype(np.float64) - v[:, :, 0, 1])
