@@ -72,8 +72,8 @@ static void fill_view(pndf_hier* h)
     d.clu_e = h->clu_e;
     d.clu_det = h->clu_det;
     d.clu_deg = h->clu_deg;
-    d.bbox_h = h->bbox_h;
     d.bbox_c = h->bbox_c;
+    d.grp = h->grp;
     d.bbox_k = h->bbox_k;
     d.quad = h->quad;
     d.n = m->n;
@@ -241,9 +241,10 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         if (e == hipSuccess) e = hipMalloc(&h->clu_e, sizeof(float) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_det, sizeof(float2) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_deg, nodes);
-        if (e == hipSuccess) e = hipMalloc(&h->bbox_h, sizeof(uint2) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_clu, sizeof(float4) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_c, sizeof(uint2) * nodes);
+        // whole groups of four (the top level's single node fills one)
+        if (e == hipSuccess) e = hipMalloc(&h->grp, sizeof(uint4) * ((nodes + 3) & ~(int64_t)3));
     }
     fill_view(h);
     if (e == hipSuccess) e = build_hierarchy_levels(h, (hipStream_t)stream);
@@ -251,7 +252,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 8 + 16 + 8 + 32 + 4 + 8 + 1 : 0)) +
+    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 16 + 8 + 16 + 32 + 4 + 8 + 1 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
@@ -267,9 +268,9 @@ void pndf_destroy_hierarchy(pndf_hier* h)
     (void)hipFree(h->clu_e);
     (void)hipFree(h->clu_det);
     (void)hipFree(h->clu_deg);
-    (void)hipFree(h->bbox_h);
     (void)hipFree(h->bbox_clu);
     (void)hipFree(h->bbox_c);
+    (void)hipFree(h->grp);
     (void)hipFree(h->bbox_k);
     mesh_release(h->mesh);
     delete h;

@@ -125,8 +125,11 @@ constexpr uint32_t kHitPlane = 1u << 30, kHitCluster = 2u << 30;
 // spatial tests.  (With the cluster cut, a node's residual is compared with the
 // query's threshold when its parent expands -- the four children's residuals are
 // read with their boxes -- and a node under the cut goes to the cluster queue
-// instead of a list.)
+// instead of a list.  Bit 30 then marks a node whose four children are all under
+// the cut: the largest of their residuals, read with the node's own, is within the
+// threshold, so its expansion reads only the children's boxes.)
 constexpr uint32_t kInside = 1u << 31;
+constexpr uint32_t kAllCut = 1u << 30;
 constexpr uint32_t kCodeMask = (1u << 30) - 1u;
 
 // Inclusive same-sign test of a triangle's three edge values: h inside or on it.
@@ -441,8 +444,6 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 {
     static_assert(!SPAWN || MODE == kModeValue, "donation is only used by value-mode workers");
     const int lane = threadIdx.x & 63;
-    // node boxes as order keys: map triangles, or map and cluster triangles under the cut
-    const uint2* __restrict__ boxes = CUT ? H.bbox_h : H.bbox_k;
     uint32_t* hq = lists + H.L * kListCap;  // hit queue
     uint32_t* cq = hq + kHitCap;            // cluster queue (CUT)
     int hn = 0;                             // queued hits (wave-uniform)
@@ -462,8 +463,10 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         const uint32_t m = root_item & kCodeMask;
         const int64_t idx = level_offset(H.logn, root_level) + m;
         if (ok && !roots_tested) {
+            // the node's box as order keys: of the map triangles, or under the cut of the
+            // map and cluster triangles (from its group record)
             acc.nodes += 1;
-            const uint2 b = boxes[idx];
+            const uint2 b = CUT ? reinterpret_cast<const uint2*>(H.grp + (idx & ~(int64_t)3))[idx & 3] : H.bbox_k[idx];
             ok = key_in_box(q.hkey, b.x, b.y);
         }
         bool cut = false;
@@ -477,7 +480,13 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             }
         }
         const uint64_t bl = __ballot(ok && !cut);
-        if (ok && !cut) lists[(root_level - 1) * kListCap + __popcll(bl & ((1ull << lane) - 1ull))] = root_item;
+        if (ok && !cut) {
+            uint32_t item = root_item;
+            if (CUT && root_level >= 2 &&
+                __uint_as_float(reinterpret_cast<const uint32_t*>(H.grp)[4 * (idx & ~(int64_t)3) + 12 + (idx & 3)]) <= q.t)
+                item |= kAllCut;
+            lists[(root_level - 1) * kListCap + __popcll(bl & ((1ull << lane) - 1ull))] = item;
+        }
         if (CUT) {
             const uint64_t bc = __ballot(cut);
             if (cut) cq[__popcll(bc & ((1ull << lane) - 1ull))] = ((uint32_t)root_level << kCluShift) | m;
@@ -592,6 +601,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         uint32_t m4 = 0;      // 4m: the first child's code
         uint32_t tested = 0;  // child boxes read by this lane
         uint32_t cut4 = 0;    // children under the cut (bit c)
+        uint32_t all4 = 0;    // children whose own children are all under the cut (bit c)
         uint32_t entry = 0;   // the lane's list item (Morton code | kInside)
         if (lane < k) {
             entry = lists[(l - 1) * kListCap + base + lane];
@@ -602,14 +612,30 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 ebase = m << 3;
             } else {
                 // the four child boxes are one Morton segment (32 B of keys): loaded
-                // whole, children outside the support masked afterwards
-                const uint4* cb = reinterpret_cast<const uint4*>(boxes + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
-                const uint4 b01 = cb[0], b23 = cb[1];
-                if (CUT) {
-                    // the children's residuals: 16 B at a multiple of 4 nodes
-                    const float4 ce = *reinterpret_cast<const float4*>(H.clu_e + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
+                // whole, children outside the support masked afterwards.  With the cut,
+                // the group record (64 B: their keys, residuals and their children's
+                // largest residuals), or for a node whose children are all under the
+                // cut only the boxes they are tested against.
+                const int64_t c0 = level_offset(H.logn, l - 1) + 4 * (int64_t)m;
+                uint4 b01, b23;
+                if (CUT && (entry & kAllCut)) {
+                    const uint4* cb = l - 1 >= kOwnBoxLevel ? reinterpret_cast<const uint4*>(H.bbox_c + c0) : H.grp + c0;
+                    b01 = cb[0];
+                    b23 = cb[1];
+                    cut4 = 0xfu;
+                } else if (CUT) {
+                    const uint4* g = H.grp + c0;
+                    b01 = g[0];
+                    b23 = g[1];
+                    const float4 ce = __builtin_bit_cast(float4, g[2]), cm = __builtin_bit_cast(float4, g[3]);
                     cut4 = (uint32_t)(ce.x <= q.t) | ((uint32_t)(ce.y <= q.t) << 1) | ((uint32_t)(ce.z <= q.t) << 2) |
                            ((uint32_t)(ce.w <= q.t) << 3);
+                    all4 = (uint32_t)(cm.x <= q.t) | ((uint32_t)(cm.y <= q.t) << 1) | ((uint32_t)(cm.z <= q.t) << 2) |
+                           ((uint32_t)(cm.w <= q.t) << 3);
+                } else {
+                    const uint4* cb = reinterpret_cast<const uint4*>(H.bbox_k + c0);
+                    b01 = cb[0];
+                    b23 = cb[1];
                 }
                 uint32_t ov = 0xfu;  // children meeting the support box
                 cin = 0xfu;
@@ -625,10 +651,10 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 chm = ((uint32_t)key_in_box(q.hkey, b01.x, b01.y) | ((uint32_t)key_in_box(q.hkey, b01.z, b01.w) << 1) |
                        ((uint32_t)key_in_box(q.hkey, b23.x, b23.y) << 2) |
                        ((uint32_t)key_in_box(q.hkey, b23.z, b23.w) << 3)) & ov;
-                if (CUT && l - 1 >= kOwnBoxLevel && (chm & cut4)) {
+                if (CUT && !(entry & kAllCut) && l - 1 >= kOwnBoxLevel && (chm & cut4)) {
                     // children under the cut: the box of their own cluster triangles
                     // (inside the subtree's box) decides instead, another 32 B segment
-                    const uint4* cc = reinterpret_cast<const uint4*>(H.bbox_c + level_offset(H.logn, l - 1) + 4 * (int64_t)m);
+                    const uint4* cc = reinterpret_cast<const uint4*>(H.bbox_c + c0);
                     const uint4 c01 = cc[0], c23 = cc[1];
                     const uint32_t own = (uint32_t)key_in_box(q.hkey, c01.x, c01.y) |
                                          ((uint32_t)key_in_box(q.hkey, c01.z, c01.w) << 1) |
@@ -660,7 +686,8 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (chl & (1u << c))
-                        dst[pos + __popc(chl & ((1u << c) - 1u))] = (m4 + c) | ((cin >> c) & 1u ? kInside : 0u);
+                        dst[pos + __popc(chl & ((1u << c) - 1u))] =
+                            (m4 + c) | ((cin >> c) & 1u ? kInside : 0u) | ((all4 >> c) & 1u ? kAllCut : 0u);
                 acc.nodes += tested;
             }
             if (CUT) {

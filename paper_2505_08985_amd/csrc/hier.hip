@@ -450,11 +450,8 @@ hipError_t export_rowmajor(const void* src, void* dst, int m, int words, hipStre
 // order keys (half_key): a rounded box contains the exact one, so it prunes a little
 // less but never wrongly; four child boxes take 32 B instead of 64 and each test is
 // two packed 16-bit integer operations (the float32 boxes stay for the exports).
-__global__ void k_key_boxes(const float4* __restrict__ src, uint2* __restrict__ dst, int64_t n)
+__device__ __forceinline__ uint2 box_keys(float4 b)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float4 b = src[i];
     uint32_t x0 = __half_as_ushort(__float2half_rd(b.x)), y0 = __half_as_ushort(__float2half_rd(b.y));
     uint32_t x1 = __half_as_ushort(__float2half_ru(b.z)), y1 = __half_as_ushort(__float2half_ru(b.w));
     // the zeros: a minimum of +0 becomes -0, a maximum of -0 becomes +0
@@ -462,7 +459,36 @@ __global__ void k_key_boxes(const float4* __restrict__ src, uint2* __restrict__ 
     if (y0 == 0u) y0 = 0x8000u;
     if (x1 == 0x8000u) x1 = 0u;
     if (y1 == 0x8000u) y1 = 0u;
-    dst[i] = make_uint2(half_key(x0) | (half_key(y0) << 16), half_key(x1) | (half_key(y1) << 16));
+    return make_uint2(half_key(x0) | (half_key(y0) << 16), half_key(x1) | (half_key(y1) << 16));
+}
+
+__global__ void k_key_boxes(const float4* __restrict__ src, uint2* __restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = box_keys(src[i]);
+}
+
+// The cut traversal's sibling-group records (HierDev::grp) of one level: thread t
+// writes node t's words (its keys are those of bbox_all, as k_key_boxes forms them).
+__global__ void k_group_records(HierDev H, int level, uint32_t* __restrict__ grp)
+{
+    const int64_t m = (int64_t)(H.n >> level) * (H.n >> level);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t idx = level_offset(H.logn, level) + t;
+    uint32_t* w = grp + 4 * (idx & ~(int64_t)3);   // 16 words per group
+    const int c = (int)(idx & 3);
+    const uint2 k = box_keys(H.bbox_all[idx]);
+    w[2 * c] = k.x;
+    w[2 * c + 1] = k.y;
+    w[8 + c] = __float_as_uint(H.clu_e[idx]);
+    float emc = INFINITY;
+    if (level >= 2) {
+        const float* ce = H.clu_e + level_offset(H.logn, level - 1) + 4 * t;
+        emc = fmaxf(fmaxf(ce[0], ce[1]), fmaxf(ce[2], ce[3]));
+    }
+    w[12 + c] = __float_as_uint(emc);
 }
 
 hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
@@ -538,8 +564,13 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
         const unsigned g = (unsigned)((h->nodes + 255) / 256);
         hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox, h->bbox_k, h->nodes);
         if (h->cluster) {
-            hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_all, h->bbox_h, h->nodes);
             hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_clu, h->bbox_c, h->nodes);
+            // (the top level's group holds one node: its other words are never read)
+            for (int level = 1; level <= H.L; ++level) {
+                const int64_t m = (int64_t)(n >> level) * (n >> level);
+                hipLaunchKernelGGL(k_group_records, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, H, level,
+                                   reinterpret_cast<uint32_t*>(h->grp));
+            }
         }
         err = hipGetLastError();
     }

@@ -72,8 +72,12 @@ struct HierDev {
     const float4* bbox;     // all levels packed: min x, min y, max x, max y (map triangles)
     const float4* bbox_all; // same, extended by cluster triangles (nullptr without clusters)
     const uint2* bbox_k;    // bbox as order keys of halves rounded outward (min down, max up): see half_key
-    const uint2* bbox_h;    // bbox_all the same way: the cut traversal's boxes
     const uint2* bbox_c;    // the node's own two cluster triangles' box, the same way
+    // (clusters) one 64 B record per group of four sibling nodes 4k..4k+3, in 16 B
+    // words: their bbox_all as keys like bbox_k (two nodes per word), their e^l, and
+    // per node the largest e^l of its four children (+inf at level 1): what the cut
+    // traversal reads when it expands their parent
+    const uint4* grp;
     const float4* clu_n;    // 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x, N2.y, N3.x, N3.y)
     const float* clu_e;     // e^l per node
     const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
@@ -225,9 +229,9 @@ struct pndf_hier {
     float4* bbox = nullptr;
     float4* bbox_all = nullptr;
     uint2* bbox_k = nullptr;
-    uint2* bbox_h = nullptr;
     float4* bbox_clu = nullptr;   // box of the node's own cluster triangles (float32)
     uint2* bbox_c = nullptr;
+    uint4* grp = nullptr;
     float4* clu_n = nullptr;
     float* clu_e = nullptr;
     float2* clu_det = nullptr;
