@@ -71,7 +71,7 @@ def load_traffic(workload, algo, kernel="gaussian", sigma_to_r=3.0, queries=None
     import workloads
     if (t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload or t.get("algo") != algo
             or t.get("kernel", "gaussian") != kernel or sigma_to_r != 3.0
-            or queries != workloads.CONFIGS[workload]["queries"]["count"]):
+            or queries != workloads.CONFIGS[workload]["queries"]["count"] or t.get("queries") != queries):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -388,8 +388,17 @@ def sample_bench(args):
     count = args.queries or (1 << 24)
     nrm = workloads.make_map(**mc)
     q = workloads.uniform_queries(n, count, qc["seed"], qc["sigma"], qc["radius"])
-    print("[bench] sampling on %s: map %d^2, %d samples, tau %g, %s" % (args.workload, n, count, tau, kern),
-          file=sys.stderr, flush=True)
+    if args.sample_presorted:
+        # the stream as a renderer issues it, tile by tile: neighbouring samples have
+        # neighbouring footprint centres (sorted by a 64 x 64 Morton bucket, host-side,
+        # before the timed region)
+        b = np.clip((q[:, :2] / n * 64).astype(np.int64), 0, 63)
+        code = np.zeros(len(q), dtype=np.int64)
+        for bit in range(6):
+            code |= ((b[:, 0] >> bit) & 1) << (2 * bit) | ((b[:, 1] >> bit) & 1) << (2 * bit + 1)
+        q = np.ascontiguousarray(q[np.argsort(code, kind="stable")])
+    print("[bench] sampling on %s: map %d^2, %d samples, tau %g, %s%s" % (args.workload, n, count, tau, kern,
+          ", footprint centres in Morton order" if args.sample_presorted else ""), file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     mesh = P.build_mesh(torch.from_numpy(nrm).cuda())
     hier = P.build_hierarchy(mesh, cluster=tau > 0)
@@ -436,7 +445,7 @@ def sample_bench(args):
     try:
         t = json.load(open(SAMPLE_TRAFFIC_FILE))
         if (t.get("kernel_hash") == kernel_hash(SAMPLE_SRC) and t.get("samples") == count and tau == 0
-                and kern == "gaussian" and args.workload == "powerlaw2048"):
+                and kern == "gaussian" and args.workload == "powerlaw2048" and not args.sample_presorted):
             traffic = float(t["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         pass
@@ -444,7 +453,8 @@ def sample_bench(args):
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": args.workload + " sampling", "map": "%s %dx%d" % (mc["kind"], n, n),
-                       "samples": count, "tau": tau, "kernel": kern, "sigma_to_r": s2r, "attempts": attempts},
+                       "samples": count, "tau": tau, "kernel": kern, "sigma_to_r": s2r, "attempts": attempts,
+                       "sample_order": "morton" if args.sample_presorted else "random"},
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
             "kernel_ms": kernel_ms, "algorithmic_bytes_per_sample": per,
@@ -569,6 +579,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving benchmark (continuous batching)")
     ap.add_argument("--sample", action="store_true", help="sampling benchmark (pndf_sample_batch)")
     ap.add_argument("--sample-tau", type=float, default=0.0)
+    ap.add_argument("--sample-presorted", action="store_true",
+                    help="sampling: footprint centres in Morton order (as a renderer's tiles issue them)")
     ap.add_argument("--projarea", action="store_true", help="projected-area benchmark (pndf_projected_area)")
     ap.add_argument("--serve-tau", type=float, default=1e-3)
     ap.add_argument("--serve-tiles", type=int, default=200)

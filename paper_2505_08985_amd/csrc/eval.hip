@@ -1189,9 +1189,18 @@ __global__ void k_order_zero(uint32_t* hist, int nb)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) hist[i] = 0;
 }
 
+// The histogram and the scatter count in LDS first (bins < 4096: at most 64 x 64
+// Morton buckets), so the global counters see one atomic per non-empty bin per
+// workgroup instead of one per query; a workgroup takes a large strided share of
+// the batch (the grid is small, order_blocks).
+constexpr int kOrderMaxBins = 4096;
+
 __device__ __forceinline__ void order_hist(const pndf_query* __restrict__ q, int64_t nq, int n, int bshift,
                                            uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
 {
+    __shared__ uint32_t loc[kOrderMaxBins];
+    for (int b = threadIdx.x; b < kOrderMaxBins; b += blockDim.x) loc[b] = 0u;
+    __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float x = q[i].x, y = q[i].y;
@@ -1202,8 +1211,11 @@ __device__ __forceinline__ void order_hist(const pndf_query* __restrict__ q, int
             k = morton(cx, cy);
         }
         key[i] = k;
-        atomicAdd(&hist[k], 1u);
+        atomicAdd(&loc[k], 1u);
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kOrderMaxBins; b += blockDim.x)
+        if (loc[b]) atomicAdd(&hist[b], loc[b]);
 }
 
 // exclusive scan of nb <= 4096 counters by one workgroup of 1024 threads
@@ -1235,14 +1247,22 @@ __global__ __launch_bounds__(1024) void k_order_scan(uint32_t* hist, int nb)
     }
 }
 
+// Each workgroup reserves, per bin, a range of the exact size of its share's count
+// (one global atomic per non-empty bin), then places its queries in it.  Within a
+// bucket the order is whatever the atomics give: results do not depend on it.
 __device__ __forceinline__ void order_scatter(const uint32_t* __restrict__ key, int64_t nq,
                                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ order)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t pos = atomicAdd(&cursor[key[i]], 1u);
-        order[pos] = (uint32_t)i;
-    }
+    __shared__ uint32_t loc[kOrderMaxBins];
+    for (int b = threadIdx.x; b < kOrderMaxBins; b += blockDim.x) loc[b] = 0u;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < nq; i += stride) atomicAdd(&loc[key[i]], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kOrderMaxBins; b += blockDim.x)
+        if (loc[b]) loc[b] = atomicAdd(&cursor[b], loc[b]);
+    __syncthreads();
+    for (int64_t i = i0; i < nq; i += stride) order[atomicAdd(&loc[key[i]], 1u)] = (uint32_t)i;
 }
 
 __global__ void k_order_hist(const pndf_query* __restrict__ q, int64_t nq, int n, int bshift,
@@ -1280,6 +1300,13 @@ void order_shape(int logn, int* nb, int* bshift)
     *bshift = logn - bits;
 }
 
+// Workgroups (of 256) of the histogram and scatter passes: about 16k queries each,
+// at most 256 (one per compute unit), so the LDS counts absorb most atomics.
+static unsigned order_blocks(int64_t nq)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (nq + 16383) / 16384));
+}
+
 // The four passes of the spatial order into buf = order[nq] | key[nq] | hist[nb]
 // (the histogram is cleared by a kernel, never a memset node).
 static hipError_t order_passes(const HierDev& H, const pndf_query* q, int64_t nq, uint32_t* buf, hipStream_t s)
@@ -1288,7 +1315,7 @@ static hipError_t order_passes(const HierDev& H, const pndf_query* q, int64_t nq
     order_shape(H.logn, &nb, &bshift);
     uint32_t* key = buf + nq;
     uint32_t* hist = key + nq;
-    const unsigned g = (unsigned)std::min<int64_t>(2048, (nq + 255) / 256);
+    const unsigned g = order_blocks(nq);
     hipLaunchKernelGGL(k_order_zero, dim3(16), dim3(256), 0, s, hist, nb);
     hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, s, q, nq, H.n, bshift, key, hist);
     hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, hist, nb);
@@ -1413,10 +1440,7 @@ int persist_resident_blocks(const HierDev& H, const PersistPlan& P)
     return nb;
 }
 
-static unsigned order_grid(long long nq)
-{
-    return (unsigned)std::min<long long>(2048, (nq + 255) / 256 + 1);
-}
+
 
 // Kernel-node parameters of the three order passes (spatial order of the batch).
 static void order_params(PersistPlan& P, hipKernelNodeParams* hist, hipKernelNodeParams* scan,
@@ -1435,7 +1459,7 @@ static void order_params(PersistPlan& P, hipKernelNodeParams* hist, hipKernelNod
     P.cargs[3] = &P.order;
     *hist = hipKernelNodeParams{};
     hist->func = (void*)k_porder_hist;
-    hist->gridDim = dim3(order_grid(P.max_nq));
+    hist->gridDim = dim3(order_blocks(P.max_nq));
     hist->blockDim = dim3(256);
     hist->kernelParams = P.hargs;
     *scan = hipKernelNodeParams{};
@@ -1445,7 +1469,7 @@ static void order_params(PersistPlan& P, hipKernelNodeParams* hist, hipKernelNod
     scan->kernelParams = P.sargs;
     *scat = hipKernelNodeParams{};
     scat->func = (void*)k_porder_scatter;
-    scat->gridDim = dim3(order_grid(P.max_nq));
+    scat->gridDim = dim3(order_blocks(P.max_nq));
     scat->blockDim = dim3(256);
     scat->kernelParams = P.cargs;
 }
@@ -1527,10 +1551,10 @@ hipError_t persist_run(PersistPlan& P, const pndf_query* q, long long nq, float*
     hipLaunchKernelGGL(k_persist_reset, P.reset.gridDim, P.reset.blockDim, 0, s, P.ctl, P.acc, P.fexp,
                        q, nq, out, P.epoch, P.ohist, P.order_nb);
     if (P.order) {
-        hipLaunchKernelGGL(k_porder_hist, dim3(order_grid(P.max_nq)), dim3(256), 0, s, P.ctl, P.on,
+        hipLaunchKernelGGL(k_porder_hist, dim3(order_blocks(P.max_nq)), dim3(256), 0, s, P.ctl, P.on,
                            P.order_bshift, P.okey, P.ohist);
         hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, P.ohist, P.order_nb);
-        hipLaunchKernelGGL(k_porder_scatter, dim3(order_grid(P.max_nq)), dim3(256), 0, s, P.ctl, P.okey,
+        hipLaunchKernelGGL(k_porder_scatter, dim3(order_blocks(P.max_nq)), dim3(256), 0, s, P.ctl, P.okey,
                            P.ohist, P.order);
     }
     const size_t lds = sizeof(uint32_t) * 4 * wave_lds_words(P.H.L, P.tau > 0.f);
