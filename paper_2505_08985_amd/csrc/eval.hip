@@ -411,15 +411,44 @@ __device__ __forceinline__ bool key_in_box(uint32_t hk, uint32_t lo, uint32_t hi
     return (__builtin_bit_cast(uint32_t, a) == hk) & (__builtin_bit_cast(uint32_t, c) == hk);
 }
 
-// Cluster queue entry: level (4 bits) << 24 | Morton code of the node (< 2^24).
-
 // Nodes under the cut from this level up are tested against the box of their own
 // cluster triangles before their cluster test.  Below it that box is about as wide
 // as the subtree's (about 60 % of level-1 cluster nodes whose subtree box holds h
 // also hold it in their own box, under 25 % from level 3) and the extra 32 B read
 // does not pay: from level 1 the scratched 4096^2 map took 7 % longer than from 2.
 constexpr int kOwnBoxLevel = 2;
+
+// Cluster queue entry: level (4 bits) << 24 | Morton code of the node (< 2^24).
 constexpr int kCluShift = 24;
+
+// A wavefront's node lists in LDS (see list_words): 32-bit items for the levels below
+// S, 16-bit items (code in bits 0..13, the flags kAllCut and kInside in bits 14, 15)
+// from S up (only with the cut).  The level is wave-uniform wherever a list is read
+// or written.
+template <bool CUT>
+struct NodeLists {
+    uint32_t* w;
+    uint16_t* h;
+    int S;
+    __device__ NodeLists(uint32_t* lds, int L)
+        : w(lds), h(reinterpret_cast<uint16_t*>(lds + (size_t)(short_list_level(L, CUT) - 1) * kListCap)),
+          S(short_list_level(L, CUT))
+    {
+    }
+    __device__ __forceinline__ uint32_t get(int lev, int i) const
+    {
+        if (!CUT || lev < S) return w[(lev - 1) * kListCap + i];
+        const uint32_t v = h[(lev - S) * kListCap + i];
+        return (v & 0x3fffu) | ((v & 0xc000u) << 16);
+    }
+    __device__ __forceinline__ void put(int lev, int i, uint32_t item) const
+    {
+        if (!CUT || lev < S)
+            w[(lev - 1) * kListCap + i] = item;
+        else
+            h[(lev - S) * kListCap + i] = (uint16_t)((item & 0x3fffu) | ((item >> 16) & 0xc000u));
+    }
+};
 
 // The shared descent.  List items are nodes (Morton codes) whose box contains h,
 // whose region meets the support box and which are not under the cluster cut.  A
@@ -444,7 +473,8 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
 {
     static_assert(!SPAWN || MODE == kModeValue, "donation is only used by value-mode workers");
     const int lane = threadIdx.x & 63;
-    uint32_t* hq = lists + H.L * kListCap;  // hit queue
+    const NodeLists<CUT> nl(lists, H.L);
+    uint32_t* hq = lists + list_words(H.L, CUT);  // hit queue
     uint32_t* cq = hq + kHitCap;            // cluster queue (CUT)
     int hn = 0;                             // queued hits (wave-uniform)
     int cn = 0;                             // queued cluster nodes (wave-uniform)
@@ -485,7 +515,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             if (CUT && root_level >= 2 &&
                 __uint_as_float(reinterpret_cast<const uint32_t*>(H.grp)[4 * (idx & ~(int64_t)3) + 12 + (idx & 3)]) <= q.t)
                 item |= kAllCut;
-            lists[(root_level - 1) * kListCap + __popcll(bl & ((1ull << lane) - 1ull))] = item;
+            nl.put(root_level, __popcll(bl & ((1ull << lane) - 1ull)), item);
         }
         if (CUT) {
             const uint64_t bc = __ballot(cut);
@@ -562,7 +592,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 slot = uniform_u64(slot);
                 if (d > 0) {
                     if (lane < d) {
-                        const uint32_t mm = lists[(lh - 1) * kListCap + ch - 1 - lane] & kCodeMask;  // the top d items
+                        const uint32_t mm = nl.get(lh, ch - 1 - lane) & kCodeMask;  // the top d items
                         Q.tasks[slot + lane] = (qidx << 32) | ((unsigned long long)lh << 26) | (unsigned long long)mm;
                         // the release store orders the task word before its flag
                         __hip_atomic_store(&Q.flags[slot + lane], Q.ctl->epoch, __ATOMIC_RELEASE,
@@ -604,7 +634,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
         uint32_t all4 = 0;    // children whose own children are all under the cut (bit c)
         uint32_t entry = 0;   // the lane's list item (Morton code | kInside)
         if (lane < k) {
-            entry = lists[(l - 1) * kListCap + base + lane];
+            entry = nl.get(l, base + lane);
             const uint32_t m = entry & kCodeMask;
             const bool inside = (entry & kInside) != 0u;
             if (l == 1) {
@@ -680,14 +710,13 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             const int below = __builtin_amdgcn_readlane(cntv, l - 1);
             const bool back = nch > 0 && below + pos + nch > kListCap;
             const uint64_t bb = __ballot(back);
-            uint32_t* dst = lists + (l - 2) * kListCap + below;
             if (!back) {
-                // child c goes to pos + (number of list children before it)
+                // child c goes to below + pos + (number of list children before it)
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (chl & (1u << c))
-                        dst[pos + __popc(chl & ((1u << c) - 1u))] =
-                            (m4 + c) | ((cin >> c) & 1u ? kInside : 0u) | ((all4 >> c) & 1u ? kAllCut : 0u);
+                        nl.put(l - 1, below + pos + __popc(chl & ((1u << c) - 1u)),
+                               (m4 + c) | ((cin >> c) & 1u ? kInside : 0u) | ((all4 >> c) & 1u ? kAllCut : 0u));
                 acc.nodes += tested;
             }
             if (CUT) {
@@ -705,7 +734,7 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             if (pushed) nonempty |= 1u << (l - 1);
             if (bb) {
                 const int nb = __popcll(bb);
-                if (back) lists[(l - 1) * kListCap + base + __popcll(bb & ((1ull << lane) - 1ull))] = entry;
+                if (back) nl.put(l, base + __popcll(bb & ((1ull << lane) - 1ull)), entry);
                 if (lane == l) cntv = base + nb;
                 nonempty |= 1u << l;
             }
@@ -827,8 +856,8 @@ __global__ __launch_bounds__(256) void k_eval_brute(HierDev H, EvalArgs a)
 
 // ------------------------------------------------------------ hierarchical
 
-// One wavefront per workgroup (a long query holds only its own LDS).  LDS: L lists
-// of kListCap node entries (levels 1..L) + the leaf queue.
+// One wavefront per workgroup (a long query holds only its own LDS).  LDS: the node
+// lists of levels 1..L (NodeLists), the hit queue and, with the cut, the cluster queue.
 template <int MODE, bool CUT, int KER>
 __global__ __launch_bounds__(64) void k_eval_plain(HierDev H, EvalArgs a)
 {

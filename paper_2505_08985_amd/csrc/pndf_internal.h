@@ -45,11 +45,32 @@ constexpr int kHitCap = 128;
 // at most 64 x 4.
 constexpr int kCluCap = 64 + 4 * 64;
 
-// 32-bit LDS words per wavefront of the descent: one node list per level 1..L, the
+// With the cluster cut, list items of the levels from short_list_level(L, true) up
+// take 16 bits: a level-l Morton code is below 4^(L - l), so from l = L - 7 it fits
+// 14 bits beside the two flag bits.  Fewer LDS bytes per wavefront let more
+// wavefronts reside, which pays where LDS limits them (the cut kernel: powerlaw8192
+// 1169 -> 1015 ms); without the cut the kernel is not LDS-limited and the extra
+// registers of the 16-bit path cost a wavefront per SIMD, so all its lists stay
+// 32-bit (short level L + 1).
+__host__ __device__ inline int short_list_level(int L, bool cut)
+{
+    return !cut ? L + 1 : (L - 7 > 1 ? L - 7 : 1);
+}
+
+// 32-bit LDS words of a wavefront's node lists: 32-bit lists of levels 1..S-1, then
+// 16-bit lists of levels S..L.
+__host__ __device__ inline size_t list_words(int L, bool cut)
+{
+    const int S = short_list_level(L, cut);
+    return (size_t)(S - 1) * kListCap + (size_t)(L - S + 1) * (kListCap / 2);
+}
+static_assert(kListCap % 2 == 0, "16-bit lists fill whole words");
+
+// 32-bit LDS words per wavefront of the descent: the node lists of levels 1..L, the
 // hit queue, and with the cut the cluster queue.
 __host__ __device__ inline size_t wave_lds_words(int L, bool cut)
 {
-    return (size_t)L * kListCap + kHitCap + (cut ? kCluCap : 0);
+    return list_words(L, cut) + kHitCap + (cut ? kCluCap : 0);
 }
 
 // Level-1 leaf record: the 3 x 3 texel normals of a 2 x 2 cell block (row-major,
