@@ -144,10 +144,12 @@ def algorithmic_work(P, hier, q, tq, n, tau, s2r, kw, per_octave=512, seed=3):
             "clusters": mean[2], "hits": mean[3]}
     nodes, cells, clus, hits = tot
     abytes = 28.0 * len(q) + 16.0 * nodes + 8.0 * cells + 36.0 * clus
+    abytes_iso = 28.0 * len(q) + 16.0 * nodes + 32.0 * cells + 36.0 * clus   # every cell's 4 corners on their own
     aops = 12.0 * nodes + 40.0 * cells + 40.0 * clus + 30.0 * hits
     nq = float(len(q))
     return {"nodes_per_query": nodes / nq, "cells_per_query": cells / nq, "clusters_per_query": clus / nq,
             "hits_per_query": hits / nq, "algorithmic_bytes_per_launch": abytes,
+            "algorithmic_bytes_per_launch_isolated_cells": abytes_iso,
             "algorithmic_alu_ops_per_launch": aops,
             "kernel_counts_per_query": {"nodes": ktot[0] / nq, "cells": ktot[1] / nq, "clusters": ktot[2] / nq},
             "sample": "CPU counting pass on %d queries per sigma octave, extrapolated by octave population; "
@@ -644,7 +646,37 @@ def main():
     line["cpu_baseline"] = cpu
     line["serving"] = serving
     line["other_workloads"] = extras or None
+    line["hbm_achievable"] = stream_bandwidth()
     print(json.dumps(line), flush=True)
+
+
+def stream_bandwidth(mib=2048, reps=5):
+    """Achievable HBM bandwidth on this machine, as context for the 8 TB/s peak: a
+    device-to-device copy of 2 GiB (read + write bytes) and a read-only reduction of
+    the same buffer, best of a few runs, timed with HIP events."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        t = 1e30
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            t = min(t, e0.elapsed_time(e1))
+        return nbytes / (t * 1e-3) / 1e9
+
+    copy = best(lambda: dst.copy_(src), 2 * 4 * n)
+    read = best(lambda: src.sum(), 4 * n)
+    del src, dst
+    return {"copy_gbs": copy, "read_gbs": read, "peak_gbs": HBM_PEAK_GBS,
+            "method": "2 GiB float32: copy_ (read + write bytes) and sum (read bytes), best of %d, HIP events" % reps}
 
 
 def measure(P, workload, args, steps, warmup, algo="plain", octaves=True):
