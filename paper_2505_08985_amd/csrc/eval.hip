@@ -647,25 +647,26 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 // largest residuals), or for a node whose children are all under the
                 // cut only the boxes they are tested against.
                 const int64_t c0 = level_offset(H.logn, l - 1) + 4 * (int64_t)m;
-                uint4 b01, b23;
-                if (CUT && (entry & kAllCut)) {
-                    const uint4* cb = l - 1 >= kOwnBoxLevel ? reinterpret_cast<const uint4*>(H.bbox_c + c0) : H.grp + c0;
-                    b01 = cb[0];
-                    b23 = cb[1];
-                    cut4 = 0xfu;
-                } else if (CUT) {
-                    const uint4* g = H.grp + c0;
-                    b01 = g[0];
-                    b23 = g[1];
-                    const float4 ce = __builtin_bit_cast(float4, g[2]), cm = __builtin_bit_cast(float4, g[3]);
-                    cut4 = (uint32_t)(ce.x <= q.t) | ((uint32_t)(ce.y <= q.t) << 1) | ((uint32_t)(ce.z <= q.t) << 2) |
-                           ((uint32_t)(ce.w <= q.t) << 3);
-                    all4 = (uint32_t)(cm.x <= q.t) | ((uint32_t)(cm.y <= q.t) << 1) | ((uint32_t)(cm.z <= q.t) << 2) |
-                           ((uint32_t)(cm.w <= q.t) << 3);
-                } else {
-                    const uint4* cb = reinterpret_cast<const uint4*>(H.bbox_k + c0);
-                    b01 = cb[0];
-                    b23 = cb[1];
+                // every load is issued before any is used (one memory round trip per
+                // expansion): the boxes, then with the cut the residual words
+                const bool allc = CUT && (entry & kAllCut) != 0u;
+                const uint4* kp = !CUT ? reinterpret_cast<const uint4*>(H.bbox_k + c0)
+                                  : (allc && l - 1 >= kOwnBoxLevel) ? reinterpret_cast<const uint4*>(H.bbox_c + c0)
+                                                                    : H.grp + c0;
+                const uint4 b01 = kp[0], b23 = kp[1];
+                if (CUT) {
+                    uint4 w2 = make_uint4(0u, 0u, 0u, 0u), w3 = w2;
+                    if (!allc) {
+                        w2 = H.grp[c0 + 2];
+                        w3 = H.grp[c0 + 3];
+                    }
+                    const float4 ce = __builtin_bit_cast(float4, w2), cm = __builtin_bit_cast(float4, w3);
+                    cut4 = allc ? 0xfu
+                                : (uint32_t)(ce.x <= q.t) | ((uint32_t)(ce.y <= q.t) << 1) |
+                                      ((uint32_t)(ce.z <= q.t) << 2) | ((uint32_t)(ce.w <= q.t) << 3);
+                    all4 = allc ? 0u
+                                : (uint32_t)(cm.x <= q.t) | ((uint32_t)(cm.y <= q.t) << 1) |
+                                      ((uint32_t)(cm.z <= q.t) << 2) | ((uint32_t)(cm.w <= q.t) << 3);
                 }
                 uint32_t ov = 0xfu;  // children meeting the support box
                 cin = 0xfu;
