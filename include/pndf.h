@@ -251,7 +251,9 @@ pndf_status pndf_sample_batch(const pndf_hier* h, const pndf_query* d_q, int64_t
  *  d_P       device, nq floats: P(w); NaN for an invalid query (as for the
  *            evaluation) or w_x^2 + w_y^2 > 1.
  *  d_lambda  device, nq floats: Lambda(w) (+inf at w_z = 0); may be NULL.
- * Asynchronous on `stream`.
+ * Queries run heaviest first (by their number of included cells), which changes
+ * no result; the order's workspace (8 bytes per query) is allocated and freed
+ * stream-ordered.  Asynchronous on `stream`; deterministic.
  */
 pndf_status pndf_projected_area(const pndf_hier* h, const pndf_query* d_q, int64_t nq, const pndf_eval_opts* opts,
                                 float* d_P, float* d_lambda, void* stream);

@@ -374,7 +374,7 @@ pndf_status pndf_projected_area(const pndf_hier* h, const pndf_query* d_q, int64
     if (st != PNDF_OK) return st;
     st = check_sticky();
     if (st != PNDF_OK) return st;
-    ProjArgs a{d_q, nq, r.sigma_to_r, r.kernel, d_P, d_lambda};
+    ProjArgs a{d_q, nq, r.sigma_to_r, r.kernel, d_P, d_lambda, nullptr};
     const hipError_t e = launch_projected_area(h->dev, a, (hipStream_t)stream);
     return e == hipSuccess ? PNDF_OK : hip_fail(e, "pndf_projected_area");
 }

@@ -315,6 +315,7 @@ struct ProjArgs {
     int kernel;                // PNDF_KERNEL_*
     float* P;
     float* lambda;             // optional: P / w_z - 1
+    const uint32_t* order;     // processing order within the launch (heaviest first), or nullptr
 };
 hipError_t launch_projected_area(const HierDev& H, const ProjArgs& a, hipStream_t s);
 

@@ -267,8 +267,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 {
     __shared__ uint32_t clip_cell[kClipCap];
     __shared__ double clip_w[kClipCap];
-    const int64_t qi = (int64_t)blockIdx.x;
-    if (qi >= a.nq) return;
+    if ((int64_t)blockIdx.x >= a.nq) return;
+    const int64_t qi = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int lane = threadIdx.x & 63;
     const pndf_query qr = a.q[qi];
     const QuerySetup q = uniform_query(setup_query(qr, a.s2r, 0.f, H.L, H.eps, KER));
@@ -401,19 +401,97 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     }
 }
 
+// ---- heaviest-first order.  A query's cost grows with its number of included
+// cells; the launch takes queries in decreasing cost class, so the longest ones
+// start first and the batch does not end on a few long queries with the GPU
+// otherwise idle.  Counting sort on 64 classes of log2 of the cell count (half
+// octaves: up to 2^32 cells), in LDS per workgroup like the evaluation's spatial
+// order.
+constexpr int kCostBins = 64;
+
+__device__ __forceinline__ uint32_t cost_class(const pndf_query& qr, float s2r, int n, int kernel, float eps, int L)
+{
+    const QuerySetup q = setup_query(qr, s2r, 0.f, L, eps, kernel);
+    if (!q.valid) return 0u;
+    const double cx = fmin((double)(q.cxhi - q.cxlo + 1), (double)n), cy = fmin((double)(q.cyhi - q.cylo + 1), (double)n);
+    const int c = (int)floor(2.0 * log2(cx * cy));
+    return (uint32_t)min(max(c, 0), kCostBins - 1);
+}
+
+__global__ void k_cost_hist(const pndf_query* __restrict__ q, int64_t nq, float s2r, int kernel, HierDev H,
+                            uint32_t* __restrict__ key, uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t loc[kCostBins];
+    if (threadIdx.x < kCostBins) loc[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = (kCostBins - 1) - cost_class(q[i], s2r, H.n, kernel, H.eps, H.L);  // heaviest first
+        key[i] = k;
+        atomicAdd(&loc[k], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCostBins && loc[threadIdx.x]) atomicAdd(&hist[threadIdx.x], loc[threadIdx.x]);
+}
+
+// exclusive scan of the 64 counters, one wavefront
+__global__ void k_cost_scan(uint32_t* hist)
+{
+    const int t = threadIdx.x;
+    uint32_t v = hist[t], run = v;
+    for (int o = 1; o < kCostBins; o <<= 1) {
+        const uint32_t u = __shfl_up(run, o);
+        if (t >= o) run += u;
+    }
+    hist[t] = run - v;
+}
+
+__global__ void k_cost_scatter(const uint32_t* __restrict__ key, int64_t nq, uint32_t* __restrict__ cursor,
+                               uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t loc[kCostBins];
+    if (threadIdx.x < kCostBins) loc[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < nq; i += stride) atomicAdd(&loc[key[i]], 1u);
+    __syncthreads();
+    if (threadIdx.x < kCostBins && loc[threadIdx.x]) loc[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], loc[threadIdx.x]);
+    __syncthreads();
+    for (int64_t i = i0; i < nq; i += stride) order[atomicAdd(&loc[key[i]], 1u)] = (uint32_t)i;
+}
+
+__global__ void k_cost_zero(uint32_t* hist)
+{
+    if (threadIdx.x < kCostBins) hist[threadIdx.x] = 0u;
+}
+
 }  // namespace
 
 hipError_t launch_projected_area(const HierDev& H, const ProjArgs& a, hipStream_t s)
 {
     // one wavefront-sized workgroup per query, in launches of at most launch_chunk()
-    // workgroups (2^24 x 64 = 2^30 work-items)
+    // workgroups (2^24 x 64 = 2^30 work-items), each in heaviest-first order
+    // (workspace: order, keys and counters of one launch, stream-ordered)
     const int64_t chunk = launch_chunk();
+    const int64_t most = std::min(chunk, a.nq);
+    uint32_t* buf = nullptr;
+    if (most > 0) {
+        const hipError_t e = hipMallocAsync((void**)&buf, sizeof(uint32_t) * (2 * (size_t)most + kCostBins), s);
+        if (e != hipSuccess) return e;
+    }
     for (int64_t off = 0; off < a.nq; off += chunk) {
         ProjArgs c = a;
         c.q = a.q + off;
         c.P = a.P + off;
         if (a.lambda) c.lambda = a.lambda + off;
         c.nq = std::min(chunk, a.nq - off);
+        uint32_t* key = buf + most;
+        uint32_t* hist = key + most;
+        const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (c.nq + 4095) / 4096));
+        hipLaunchKernelGGL(k_cost_zero, dim3(1), dim3(64), 0, s, hist);
+        hipLaunchKernelGGL(k_cost_hist, dim3(g), dim3(256), 0, s, c.q, c.nq, c.s2r, c.kernel, H, key, hist);
+        hipLaunchKernelGGL(k_cost_scan, dim3(1), dim3(kCostBins), 0, s, hist);
+        hipLaunchKernelGGL(k_cost_scatter, dim3(g), dim3(256), 0, s, key, c.nq, hist, buf);
+        c.order = buf;
         const dim3 grid((unsigned)c.nq), block(64);
         if (a.kernel == PNDF_KERNEL_DISK)
             hipLaunchKernelGGL(k_projected_area<PNDF_KERNEL_DISK>, grid, block, 0, s, H, c);
@@ -422,9 +500,12 @@ hipError_t launch_projected_area(const HierDev& H, const ProjArgs& a, hipStream_
         else
             hipLaunchKernelGGL(k_projected_area<PNDF_KERNEL_GAUSSIAN>, grid, block, 0, s, H, c);
         const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(buf, s);
+            return e;
+        }
     }
-    return hipSuccess;
+    return buf ? hipFreeAsync(buf, s) : hipSuccess;
 }
 
 }  // namespace pndf
