@@ -13,8 +13,11 @@ namespace pndf {
 
 static thread_local std::string g_last_error;
 
-// Batches at least this large are evaluated in spatial order (results do not depend
-// on the order; only cache locality does).
+// Batches from this size on are evaluated in spatial order (results do not depend on
+// the order; only cache locality does).  A random batch of 16384 queries runs 7 %
+// faster without the order passes, but render tiles served side by side need the
+// order's locality: with 32768 as the threshold a served stream of 16384-query tiles
+// lost a quarter of its throughput, though each tile alone ran faster.
 constexpr int64_t kOrderMin = 4096;
 
 void set_error(const std::string& msg) { g_last_error = msg; }

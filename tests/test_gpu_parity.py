@@ -541,3 +541,21 @@ def test_launches_split_into_chunks(P, oracle_mod):
         for x, y in (zip(a, b) if isinstance(a, tuple) else [(a, b)]):
             assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), key
     assert np.isfinite(one["plain"]).all() and (one["plain"] > 0).sum() > 500
+
+
+@pytest.mark.parametrize("nq", [4095, 4096, 40000])
+def test_spatial_order_changes_no_bit(P, nq):
+    """Batches from 4096 queries on run in spatial order, smaller ones in input order:
+    either way every result equals the input-order evaluation bit for bit (the sums
+    are exact), at and around the threshold, with and without the cut."""
+    import torch
+    import workloads
+    announce("spatial order vs input order, %d queries" % nq)
+    nrm = workloads.make_map("powerlaw", 256, 61)
+    _, hier = gpu_build(P, nrm, cluster=True)
+    q = torch.from_numpy(workloads.uniform_queries(256, nq, 62, (0.5, 64.0), 0.4)).cuda()
+    for tau in (0.0, 1e-3):
+        a = P.eval_batch(hier, q, tau=tau).cpu().numpy()
+        b = P.eval_batch(hier, q, tau=tau, input_order=True).cpu().numpy()
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+        assert np.isfinite(a).all() and (a > 0).mean() > 0.05
