@@ -13,7 +13,9 @@
  * tested) when h lies inside its box, which from level 2 up is that of its own two
  * cluster triangles; otherwise it stops when h lies outside its box, at level 1
  * counts its cells that meet the range, and above visits its children that meet
- * the range.  The boxes are those of the map's triangles (tau = 0) or of the map's
+ * the range -- except that a node of level 3 or more reached from its parent (not
+ * a root) whose children are all under the cut stops when h lies outside the union
+ * of its children's own boxes (none of their cluster tests could hit).  The boxes are those of the map's triangles (tau = 0) or of the map's
  * and cluster triangles beneath the node (tau > 0), as the hierarchy stores them
  * in float32.
  *
@@ -48,7 +50,27 @@ static int axis_meets(long start, long s, long lo, long hi, long n)
     return start + p * n <= hi;
 }
 
-static void visit(const hier_t* h, walk_t* w, int l, long I, long J)
+static int inside_box(const float* b, float x, float y)
+{
+    return x >= b[0] && y >= b[1] && x <= b[2] && y <= b[3];
+}
+
+/* a node of level l >= 3 whose four children are all under the cut, and none of
+ * whose children's own boxes holds h */
+static int children_all_cut_and_missed(const hier_t* h, const walk_t* w, int l, long I, long J)
+{
+    const long mc = (long)h->n >> (l - 1);
+    int all = 1, any = 0;
+    for (int dj = 0; dj < 2; dj++)
+        for (int di = 0; di < 2; di++) {
+            const long kc = h->off[l - 1] + (2 * J + dj) * mc + 2 * I + di;
+            all &= h->e[kc] <= w->t;
+            any |= inside_box(h->own + 4 * kc, w->hx, w->hy);
+        }
+    return all && !any;
+}
+
+static void visit(const hier_t* h, walk_t* w, int l, long I, long J, int root)
 {
     const long m = (long)h->n >> l;
     const long k = h->off[l] + J * m + I;
@@ -60,6 +82,7 @@ static void visit(const hier_t* h, walk_t* w, int l, long I, long J)
         return;
     }
     if (!(w->hx >= b[0] && w->hy >= b[1] && w->hx <= b[2] && w->hy <= b[3])) return;
+    if (w->cut && !root && l >= 3 && children_all_cut_and_missed(h, w, l, I, J)) return;
     const long s = 1L << (l - 1);
     for (int dj = 0; dj < 2; dj++)
         for (int di = 0; di < 2; di++) {
@@ -69,7 +92,7 @@ static void visit(const hier_t* h, walk_t* w, int l, long I, long J)
             if (l == 1)
                 w->cells++;
             else
-                visit(h, w, l - 1, ci, cj);
+                visit(h, w, l - 1, ci, cj, 0);
         }
 }
 
@@ -132,7 +155,7 @@ int wc_count(int n, const float* box, const float* own, const float* e, const fl
                     if (l0 == 0)
                         w.cells++;
                     else
-                        visit(&h, &w, l0, I, J);
+                        visit(&h, &w, l0, I, J, 1);
                 }
             }
         }

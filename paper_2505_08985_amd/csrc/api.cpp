@@ -76,6 +76,7 @@ static void fill_view(pndf_hier* h)
     d.clu_det = h->clu_det;
     d.clu_deg = h->clu_deg;
     d.bbox_c = h->bbox_c;
+    d.bbox_u = h->bbox_u;
     d.grp = h->grp;
     d.bbox_k = h->bbox_k;
     d.quad = h->quad;
@@ -246,6 +247,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         if (e == hipSuccess) e = hipMalloc(&h->clu_deg, nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_clu, sizeof(float4) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_c, sizeof(uint2) * nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->bbox_u, sizeof(uint2) * nodes);
         // whole groups of four (the top level's single node fills one)
         if (e == hipSuccess) e = hipMalloc(&h->grp, sizeof(uint4) * ((nodes + 3) & ~(int64_t)3));
     }
@@ -255,7 +257,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 16 + 8 + 16 + 32 + 4 + 8 + 1 : 0)) +
+    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 16 + 8 + 8 + 16 + 32 + 4 + 8 + 1 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
@@ -273,6 +275,7 @@ void pndf_destroy_hierarchy(pndf_hier* h)
     (void)hipFree(h->clu_deg);
     (void)hipFree(h->bbox_clu);
     (void)hipFree(h->bbox_c);
+    (void)hipFree(h->bbox_u);
     (void)hipFree(h->grp);
     (void)hipFree(h->bbox_k);
     mesh_release(h->mesh);

@@ -654,11 +654,19 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                                   : (allc && l - 1 >= kOwnBoxLevel) ? reinterpret_cast<const uint4*>(H.bbox_c + c0)
                                                                     : H.grp + c0;
                 const uint4 b01 = kp[0], b23 = kp[1];
+                uint4 u01 = make_uint4(0u, 0xffffffffu, 0u, 0xffffffffu), u23 = u01;
                 if (CUT) {
                     uint4 w2 = make_uint4(0u, 0u, 0u, 0u), w3 = w2;
                     if (!allc) {
                         w2 = H.grp[c0 + 2];
                         w3 = H.grp[c0 + 3];
+                        if (l - 1 >= 3) {
+                            // the children's union boxes, for those whose own children
+                            // all turn out to be under the cut
+                            const uint4* up = reinterpret_cast<const uint4*>(H.bbox_u + c0);
+                            u01 = up[0];
+                            u23 = up[1];
+                        }
                     }
                     const float4 ce = __builtin_bit_cast(float4, w2), cm = __builtin_bit_cast(float4, w3);
                     cut4 = allc ? 0xfu
@@ -682,6 +690,16 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                 chm = ((uint32_t)key_in_box(q.hkey, b01.x, b01.y) | ((uint32_t)key_in_box(q.hkey, b01.z, b01.w) << 1) |
                        ((uint32_t)key_in_box(q.hkey, b23.x, b23.y) << 2) |
                        ((uint32_t)key_in_box(q.hkey, b23.z, b23.w) << 3)) & ov;
+                if (CUT && all4) {
+                    // a child whose children are all under the cut, none of whose
+                    // children's own boxes holds h, would only test clusters that
+                    // cannot hit: it is not pushed
+                    const uint32_t uin = (uint32_t)key_in_box(q.hkey, u01.x, u01.y) |
+                                         ((uint32_t)key_in_box(q.hkey, u01.z, u01.w) << 1) |
+                                         ((uint32_t)key_in_box(q.hkey, u23.x, u23.y) << 2) |
+                                         ((uint32_t)key_in_box(q.hkey, u23.z, u23.w) << 3);
+                    chm &= ~(all4 & ~cut4 & ~uin);
+                }
                 if (CUT && !(entry & kAllCut) && l - 1 >= kOwnBoxLevel && (chm & cut4)) {
                     // children under the cut: the box of their own cluster triangles
                     // (inside the subtree's box) decides instead, another 32 B segment

@@ -469,6 +469,30 @@ __global__ void k_key_boxes(const float4* __restrict__ src, uint2* __restrict__ 
     dst[i] = box_keys(src[i]);
 }
 
+// Keys of a box that contains every normal (minimum key 0, maximum key 0xffff).
+__global__ void k_fill_keys_all(uint2* __restrict__ dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = make_uint2(0u, 0xffffffffu);
+}
+
+// Union keys (HierDev::bbox_u) of one level l >= 3: the box of the node's four
+// children's own cluster triangles.  A node whose children are all under the cut
+// is skipped when this box misses h: none of their cluster tests could hit.
+__global__ void k_union_keys(HierDev H, int level, const float4* __restrict__ bbox_clu, uint2* __restrict__ dst)
+{
+    const int64_t m = (int64_t)(H.n >> level) * (H.n >> level);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const float4* c = bbox_clu + level_offset(H.logn, level - 1) + 4 * t;
+    float4 u = c[0];
+    box_union(u, c[1]);
+    box_union(u, c[2]);
+    box_union(u, c[3]);
+    dst[level_offset(H.logn, level) + t] = box_keys(u);
+}
+
 // The cut traversal's sibling-group records (HierDev::grp) of one level: thread t
 // writes node t's words (its keys are those of bbox_all, as k_key_boxes forms them).
 __global__ void k_group_records(HierDev H, int level, uint32_t* __restrict__ grp)
@@ -565,6 +589,14 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
         hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox, h->bbox_k, h->nodes);
         if (h->cluster) {
             hipLaunchKernelGGL(k_key_boxes, dim3(g), dim3(256), 0, s, h->bbox_clu, h->bbox_c, h->nodes);
+            // (levels 1 and 2 keep the all-inclusive box: their children's own boxes are
+            // not what those children are tested against)
+            hipLaunchKernelGGL(k_fill_keys_all, dim3(g), dim3(256), 0, s, h->bbox_u, h->nodes);
+            for (int level = 3; level <= H.L; ++level) {
+                const int64_t m = (int64_t)(n >> level) * (n >> level);
+                hipLaunchKernelGGL(k_union_keys, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, H, level,
+                                   h->bbox_clu, h->bbox_u);
+            }
             // (the top level's group holds one node: its other words are never read)
             for (int level = 1; level <= H.L; ++level) {
                 const int64_t m = (int64_t)(n >> level) * (n >> level);

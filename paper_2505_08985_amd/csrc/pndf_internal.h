@@ -94,6 +94,7 @@ struct HierDev {
     const float4* bbox_all; // same, extended by cluster triangles (nullptr without clusters)
     const uint2* bbox_k;    // bbox as order keys of halves rounded outward (min down, max up): see half_key
     const uint2* bbox_c;    // the node's own two cluster triangles' box, the same way
+    const uint2* bbox_u;    // from level 3: the union of its four children's own boxes (bbox_c), the same way
     // (clusters) one 64 B record per group of four sibling nodes 4k..4k+3, in 16 B
     // words: their bbox_all as keys like bbox_k (two nodes per word), their e^l, and
     // per node the largest e^l of its four children (+inf at level 1): what the cut
@@ -252,6 +253,7 @@ struct pndf_hier {
     uint2* bbox_k = nullptr;
     float4* bbox_clu = nullptr;   // box of the node's own cluster triangles (float32)
     uint2* bbox_c = nullptr;
+    uint2* bbox_u = nullptr;
     uint4* grp = nullptr;
     float4* clu_n = nullptr;
     float* clu_e = nullptr;

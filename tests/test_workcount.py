@@ -2,7 +2,9 @@
 of the same rules on small random hierarchies: entry level and roots from the
 support box, one box test per visited node, a node under the cut counted as a
 cluster node when h lies in its box (from level 2 up the box of its own cluster
-triangles), cells counted at level 1.  CPU only."""
+triangles), cells counted at level 1, and a non-root node of level 3 or more whose
+children are all under the cut left unexpanded when none of their own boxes holds
+h.  CPU only."""
 import math
 
 import numpy as np
@@ -11,7 +13,7 @@ import pytest
 import bench
 
 
-def walk(n, box, own, e, q, tau, s2r):
+def walk(n, box, own, e, q, tau, s2r, union_skip=True):
     L = int(math.log2(n))
     off = {}
     o = 0
@@ -34,7 +36,7 @@ def walk(n, box, own, e, q, tau, s2r):
 
     cnt = [0, 0, 0]
 
-    def visit(l, I, J):
+    def visit(l, I, J, root=False):
         m = n >> l
         k = off[l] + J * m + I
         cnt[0] += 1
@@ -45,6 +47,11 @@ def walk(n, box, own, e, q, tau, s2r):
             return
         if not inside(box[k], np.float32(hx), np.float32(hy)):
             return
+        if union_skip and cut and not root and l >= 3:
+            mc = n >> (l - 1)
+            kids = [off[l - 1] + (2 * J + dj) * mc + 2 * I + di for dj in range(2) for di in range(2)]
+            if all(e[kc] <= t for kc in kids) and not any(inside(own[kc], np.float32(hx), np.float32(hy)) for kc in kids):
+                return
         s = 1 << (l - 1)
         for dj in range(2):
             for di in range(2):
@@ -70,26 +77,33 @@ def walk(n, box, own, e, q, tau, s2r):
             if l0 == 0:
                 cnt[1] += 1
             else:
-                visit(l0, I, J)
+                visit(l0, I, J, root=True)
     return cnt
 
 
-@pytest.mark.parametrize("tau", [0.0, 0.02, 1.0])
+@pytest.mark.parametrize("tau", [0.0, 0.005, 0.02])
 def test_counting_pass_matches_a_direct_walk(tau):
     rng = np.random.default_rng(11)
-    n = 16
-    nodes = sum((n >> l) ** 2 for l in range(1, 5))
+    n = 32
+    nodes = sum((n >> l) ** 2 for l in range(1, 6))
     c = rng.uniform(-0.5, 0.5, (nodes, 2)).astype(np.float32)
     w = rng.uniform(0.05, 0.6, (nodes, 2)).astype(np.float32)
     box = np.concatenate([c - w, c + w], axis=1).astype(np.float32)
-    shrink = rng.uniform(0.0, 1.0, (nodes, 1)).astype(np.float32)
+    shrink = rng.uniform(0.0, 0.5, (nodes, 1)).astype(np.float32)
     own = np.concatenate([c - w * shrink, c + w * shrink], axis=1).astype(np.float32)
-    e = rng.uniform(0.0, 3.0, nodes).astype(np.float32)
-    q = np.stack([rng.uniform(0, n, 300), rng.uniform(0, n, 300), np.exp(rng.uniform(np.log(0.3), np.log(8.0), 300)),
-                  np.exp(rng.uniform(np.log(0.3), np.log(8.0), 300)), rng.uniform(-0.6, 0.6, 300),
-                  rng.uniform(-0.6, 0.6, 300)], axis=1).astype(np.float32)
+    # residuals grow about 4x per level, as fits of a rough map do
+    lev = np.concatenate([np.full((n >> l) ** 2, l) for l in range(1, 6)])
+    e = (rng.uniform(0.5, 2.0, nodes) * 0.01 * 4.0 ** lev).astype(np.float32)
+    nq = 400
+    q = np.stack([rng.uniform(0, n, nq), rng.uniform(0, n, nq), np.exp(rng.uniform(np.log(0.3), np.log(16.0), nq)),
+                  np.exp(rng.uniform(np.log(0.3), np.log(16.0), nq)), rng.uniform(-0.6, 0.6, nq),
+                  rng.uniform(-0.6, 0.6, nq)], axis=1).astype(np.float32)
     got = bench.count_work(n, np.ascontiguousarray(box.reshape(-1)), np.ascontiguousarray(own.reshape(-1)) if tau > 0 else None,
                            np.ascontiguousarray(e) if tau > 0 else None, q, tau, 3.0)
     want = np.array([walk(n, box, own, e, qq, tau, 3.0) for qq in q], dtype=np.float64)
     np.testing.assert_array_equal(got, want)
     assert want[:, 0].sum() > 0 and (tau == 0 or want[:, 2].sum() > 0)
+    if tau > 0:
+        # the union rule is exercised: without it more nodes would be visited
+        full = np.array([walk(n, box, own, e, qq, tau, 3.0, union_skip=False) for qq in q], dtype=np.float64)
+        assert (full[:, 0] > want[:, 0]).any()
