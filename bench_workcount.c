@@ -14,8 +14,9 @@
  * cluster triangles; otherwise it stops when h lies outside its box, at level 1
  * counts its cells that meet the range, and above visits its children that meet
  * the range -- except that a node of level 3 or more reached from its parent (not
- * a root) whose children are all under the cut stops when h lies outside the union
- * of its children's own boxes (none of their cluster tests could hit).  The boxes are those of the map's triangles (tau = 0) or of the map's
+ * a root) whose children are all under the cut takes a second box test, the union
+ * of its children's own boxes, and stops when h lies outside it (none of their
+ * cluster tests could hit).  The boxes are those of the map's triangles (tau = 0) or of the map's
  * and cluster triangles beneath the node (tau > 0), as the hierarchy stores them
  * in float32.
  *
@@ -55,19 +56,25 @@ static int inside_box(const float* b, float x, float y)
     return x >= b[0] && y >= b[1] && x <= b[2] && y <= b[3];
 }
 
-/* a node of level l >= 3 whose four children are all under the cut, and none of
- * whose children's own boxes holds h */
-static int children_all_cut_and_missed(const hier_t* h, const walk_t* w, int l, long I, long J)
+/* are the four children of node (l, I) all under the cut */
+static int children_all_cut(const hier_t* h, const walk_t* w, int l, long I, long J)
 {
     const long mc = (long)h->n >> (l - 1);
-    int all = 1, any = 0;
+    int all = 1;
     for (int dj = 0; dj < 2; dj++)
-        for (int di = 0; di < 2; di++) {
-            const long kc = h->off[l - 1] + (2 * J + dj) * mc + 2 * I + di;
-            all &= h->e[kc] <= w->t;
-            any |= inside_box(h->own + 4 * kc, w->hx, w->hy);
-        }
-    return all && !any;
+        for (int di = 0; di < 2; di++) all &= h->e[h->off[l - 1] + (2 * J + dj) * mc + 2 * I + di] <= w->t;
+    return all;
+}
+
+/* does the union of the four children's own boxes hold h */
+static int children_own_hold(const hier_t* h, const walk_t* w, int l, long I, long J)
+{
+    const long mc = (long)h->n >> (l - 1);
+    int any = 0;
+    for (int dj = 0; dj < 2; dj++)
+        for (int di = 0; di < 2; di++)
+            any |= inside_box(h->own + 4 * (h->off[l - 1] + (2 * J + dj) * mc + 2 * I + di), w->hx, w->hy);
+    return any;
 }
 
 static void visit(const hier_t* h, walk_t* w, int l, long I, long J, int root)
@@ -82,7 +89,10 @@ static void visit(const hier_t* h, walk_t* w, int l, long I, long J, int root)
         return;
     }
     if (!(w->hx >= b[0] && w->hy >= b[1] && w->hx <= b[2] && w->hy <= b[3])) return;
-    if (w->cut && !root && l >= 3 && children_all_cut_and_missed(h, w, l, I, J)) return;
+    if (w->cut && !root && l >= 3 && children_all_cut(h, w, l, I, J)) {
+        w->nodes++;  /* a second box test: the union of the children's own boxes */
+        if (!children_own_hold(h, w, l, I, J)) return;
+    }
     const long s = 1L << (l - 1);
     for (int dj = 0; dj < 2; dj++)
         for (int di = 0; di < 2; di++) {

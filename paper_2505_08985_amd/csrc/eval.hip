@@ -698,7 +698,10 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
                                          ((uint32_t)key_in_box(q.hkey, u01.z, u01.w) << 1) |
                                          ((uint32_t)key_in_box(q.hkey, u23.x, u23.y) << 2) |
                                          ((uint32_t)key_in_box(q.hkey, u23.z, u23.w) << 3);
-                    chm &= ~(all4 & ~cut4 & ~uin);
+                    // (from level 3, where the union keys are read: a second box test each)
+                    const uint32_t utested = l - 1 >= 3 ? all4 & ~cut4 & chm : 0u;
+                    tested += (uint32_t)__popc(utested);
+                    chm &= ~(utested & ~uin);
                 }
                 if (CUT && !(entry & kAllCut) && l - 1 >= kOwnBoxLevel && (chm & cut4)) {
                     // children under the cut: the box of their own cluster triangles

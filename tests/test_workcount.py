@@ -3,8 +3,8 @@ of the same rules on small random hierarchies: entry level and roots from the
 support box, one box test per visited node, a node under the cut counted as a
 cluster node when h lies in its box (from level 2 up the box of its own cluster
 triangles), cells counted at level 1, and a non-root node of level 3 or more whose
-children are all under the cut left unexpanded when none of their own boxes holds
-h.  CPU only."""
+children are all under the cut tested a second time, against the union of their
+own boxes, and left unexpanded when it misses h.  CPU only."""
 import math
 
 import numpy as np
@@ -50,8 +50,10 @@ def walk(n, box, own, e, q, tau, s2r, union_skip=True):
         if union_skip and cut and not root and l >= 3:
             mc = n >> (l - 1)
             kids = [off[l - 1] + (2 * J + dj) * mc + 2 * I + di for dj in range(2) for di in range(2)]
-            if all(e[kc] <= t for kc in kids) and not any(inside(own[kc], np.float32(hx), np.float32(hy)) for kc in kids):
-                return
+            if all(e[kc] <= t for kc in kids):
+                cnt[0] += 1   # the union box is a second box test
+                if not any(inside(own[kc], np.float32(hx), np.float32(hy)) for kc in kids):
+                    return
         s = 1 << (l - 1)
         for dj in range(2):
             for di in range(2):
@@ -106,4 +108,4 @@ def test_counting_pass_matches_a_direct_walk(tau):
     if tau > 0:
         # the union rule is exercised: without it more nodes would be visited
         full = np.array([walk(n, box, own, e, qq, tau, 3.0, union_skip=False) for qq in q], dtype=np.float64)
-        assert (full[:, 0] > want[:, 0]).any()
+        assert (full[:, 0] != want[:, 0]).any() and (full[:, 1:] == want[:, 1:]).all()
