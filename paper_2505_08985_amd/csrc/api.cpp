@@ -71,10 +71,9 @@ static void fill_view(pndf_hier* h)
     d.det = m->det;
     d.bbox = h->bbox;
     d.bbox_all = h->bbox_all;
-    d.clu_n = h->clu_n;
+    d.clu_t = h->clu_t;
     d.clu_e = h->clu_e;
     d.clu_det = h->clu_det;
-    d.clu_deg = h->clu_deg;
     d.bbox_c = h->bbox_c;
     d.bbox_u = h->bbox_u;
     d.grp = h->grp;
@@ -244,7 +243,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         if (e == hipSuccess) e = hipMalloc(&h->clu_n, sizeof(float4) * 2 * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_e, sizeof(float) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->clu_det, sizeof(float2) * nodes);
-        if (e == hipSuccess) e = hipMalloc(&h->clu_deg, nodes);
+        if (e == hipSuccess) e = hipMalloc(&h->clu_t, sizeof(float4) * 2 * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_clu, sizeof(float4) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_c, sizeof(uint2) * nodes);
         if (e == hipSuccess) e = hipMalloc(&h->bbox_u, sizeof(uint2) * nodes);
@@ -257,7 +256,7 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
-    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 16 + 8 + 8 + 16 + 32 + 4 + 8 + 1 : 0)) +
+    h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 16 + 8 + 8 + 16 + 32 + 32 + 4 + 8 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
     return PNDF_OK;
@@ -272,7 +271,7 @@ void pndf_destroy_hierarchy(pndf_hier* h)
     (void)hipFree(h->clu_n);
     (void)hipFree(h->clu_e);
     (void)hipFree(h->clu_det);
-    (void)hipFree(h->clu_deg);
+    (void)hipFree(h->clu_t);
     (void)hipFree(h->bbox_clu);
     (void)hipFree(h->bbox_c);
     (void)hipFree(h->bbox_u);

@@ -294,8 +294,8 @@ __device__ __forceinline__ uint32_t leaf_quad_mask(const HierDev& H, const Query
 __device__ __forceinline__ uint32_t cluster_mask(const HierDev& H, const QuerySetup& q, int lev, int64_t idx,
                                                  Acc& acc)
 {
-    const float4 a = H.clu_n[2 * idx], b = H.clu_n[2 * idx + 1];
-    const uint32_t dg = H.clu_deg[idx];
+    const float4 a = H.clu_t[2 * idx], b = H.clu_t[2 * idx + 1];
+    const uint32_t dg = clamp_bits(a, b);
     const float rho = H.rho * (float)(1 << lev);
     const float cx = 0.5f * (a.z + b.x), cy = 0.5f * (a.w + b.y);
     float vl[6], vu[6];
@@ -323,10 +323,10 @@ __device__ __forceinline__ void hit_entry(const HierDev& H, const QuerySetup& q,
         const int64_t idx = level_offset(H.logn, lev) + m;
         I = (int)morton_compact(m);
         J = (int)morton_compact(m >> 1);
-        const float4 a = H.clu_n[2 * idx], b = H.clu_n[2 * idx + 1];
+        const float4 a = H.clu_t[2 * idx], b = H.clu_t[2 * idx + 1];
         const float2 dd = H.clu_det[idx];
         det_used = half ? dd.y : dd.x;
-        if (H.clu_deg[idx] & (1u << half)) {
+        if (clamp_bits(a, b) & (1u << half)) {
             eqtri_f64(0.5 * ((double)a.z + (double)b.x), 0.5 * ((double)a.w + (double)b.y),
                       (double)(H.rho * (float)(1 << lev)), v);
         } else if (half == 0) {
@@ -500,7 +500,11 @@ __device__ void descend(const HierDev& H, const QuerySetup& q, uint32_t* lists, 
             ok = key_in_box(q.hkey, b.x, b.y);
         }
         bool cut = false;
-        if (CUT && ok && H.clu_e[idx] <= q.t) {
+        // (e^l from the node's group record, the one the root's key test reads; taking it
+        // there rather than from the per-node e^l array keeps one array pointer out of the
+        // kernel, whose scalar registers are at their limit)
+        if (CUT && ok &&
+            __uint_as_float(reinterpret_cast<const uint32_t*>(H.grp)[4 * (idx & ~(int64_t)3) + 8 + (idx & 3)]) <= q.t) {
             cut = true;
             if (root_level >= kOwnBoxLevel) {
                 // under the cut only the node's own two cluster triangles are tested:

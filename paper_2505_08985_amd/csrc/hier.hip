@@ -207,15 +207,15 @@ struct LevelOut {
     float4* bbox_all;
     float4* bbox_clu;
     float4* clu_n;
+    float4* clu_t;
     float* clu_e;
     float2* clu_det;
-    uint8_t* clu_deg;
 };
 
 // Store the fitted normals of node idx (level side s): float32 normals, the cluster
-// triangles' Jacobians and clamp bits (FP64 from the stored float32 normals, as the
-// evaluation uses them), the FP64 normals for the residual pass; returns the box of
-// the cluster triangles.
+// triangles' Jacobians and clamp decisions (FP64 from the stored float32 normals, as
+// the evaluation uses them) with the test record that carries them, the FP64 normals
+// for the residual pass; returns the box of the cluster triangles.
 __device__ float4 store_cluster(const HierDev& H, const LevelOut& o, int64_t idx, int s, const double N[4][2],
                                 double* __restrict__ nfit)
 {
@@ -231,7 +231,9 @@ __device__ float4 store_cluster(const HierDev& H, const LevelOut& o, int64_t idx
     const double eps = (double)H.eps;
     const bool cl = dl < eps, cu = du < eps;
     o.clu_det[idx] = make_float2(cl ? H.eps : (float)dl, cu ? H.eps : (float)du);
-    o.clu_deg[idx] = (uint8_t)((cl ? 1 : 0) | (cu ? 2 : 0));
+    const float qnan = __int_as_float(0x7fc00000);
+    o.clu_t[2 * idx] = make_float4(cl ? qnan : f[0].x, f[0].y, f[1].x, f[1].y);
+    o.clu_t[2 * idx + 1] = make_float4(f[2].x, f[2].y, cu ? qnan : f[3].x, f[3].y);
     float4 b = empty_box();
     const float cx = 0.5f * (f[1].x + f[2].x), cy = 0.5f * (f[1].y + f[2].y);
     const float rho = H.rho * (float)s;
@@ -552,8 +554,8 @@ hipError_t build_hierarchy_levels(pndf_hier* h, hipStream_t s)
         o.bbox_clu = h->cluster ? h->bbox_clu + off : nullptr;
         o.clu_n = h->cluster ? h->clu_n + 2 * off : nullptr;
         o.clu_e = h->cluster ? h->clu_e + off : nullptr;
+        o.clu_t = h->cluster ? h->clu_t + 2 * off : nullptr;
         o.clu_det = h->cluster ? h->clu_det + off : nullptr;
-        o.clu_deg = h->cluster ? h->clu_deg + off : nullptr;
         return o;
     };
     auto residual = [&](int level) {

@@ -100,15 +100,26 @@ struct HierDev {
     // per node the largest e^l of its four children (+inf at level 1): what the cut
     // traversal reads when it expands their parent
     const uint4* grp;
-    const float4* clu_n;    // 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x, N2.y, N3.x, N3.y)
+    // the cluster test record, 2 float4 per node: (N0.x, N0.y, N1.x, N1.y), (N2.x,
+    // N2.y, N3.x, N3.y), except that a clamped triangle's free vertex (N0 of the
+    // lower, N3 of the upper: its replacement is built from the shared edge N1 N2
+    // alone) holds NaN, so the record carries the clamp bits (clamp_bits)
+    const float4* clu_t;
     const float* clu_e;     // e^l per node
     const float2* clu_det;  // cluster triangle Jacobians (lower, upper), eps when clamped
-    const uint8_t* clu_deg; // cluster clamp bits
     const QuadRec* quad;    // level-1 leaf records (Morton order)
     int n, L, logn;
     float eps;
     float rho;              // circumradius of the clamp replacement triangle (area eps / 2)
 };
+
+// Clamp bits of a cluster test record (a, b) = clu_t[2 idx], clu_t[2 idx + 1]: bit 0
+// the lower triangle (N0 stored as NaN), bit 1 the upper (N3 stored as NaN).  (The
+// build keeps IEEE semantics, so x != x is the NaN test.)
+__device__ __forceinline__ uint32_t clamp_bits(float4 a, float4 b)
+{
+    return (a.x != a.x ? 1u : 0u) | (b.z != b.z ? 2u : 0u);
+}
 
 // Order key of a half-precision value (IEEE binary16 bits): unsigned keys compare
 // like the values (negative values mirrored below 0x8000, zero signs aside), so a
@@ -255,10 +266,10 @@ struct pndf_hier {
     uint2* bbox_c = nullptr;
     uint2* bbox_u = nullptr;
     uint4* grp = nullptr;
-    float4* clu_n = nullptr;
+    float4* clu_n = nullptr;      // the fitted normals as float32 (exported; the kernels read clu_t)
+    float4* clu_t = nullptr;
     float* clu_e = nullptr;
     float2* clu_det = nullptr;
-    uint8_t* clu_deg = nullptr;
     pndf::QuadRec* quad = nullptr;
     int64_t bytes = 0;
     pndf::HierDev dev;

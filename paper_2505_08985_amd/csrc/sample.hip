@@ -134,10 +134,10 @@ __global__ __launch_bounds__(256) void k_sample(HierDev H, SampleArgs a)
             clamped = (r->deg[2 * dj + di] >> half) & 1u;
         } else {
             const int64_t ix = level_offset(H.logn, lev) + morton((uint32_t)I, (uint32_t)J);
-            const float4 ca = H.clu_n[2 * ix], cb = H.clu_n[2 * ix + 1];
+            const float4 ca = H.clu_t[2 * ix], cb = H.clu_t[2 * ix + 1];
             n0 = make_float2(ca.x, ca.y); n1 = make_float2(ca.z, ca.w);
             n2 = make_float2(cb.x, cb.y); n3 = make_float2(cb.z, cb.w);
-            clamped = (H.clu_deg[ix] >> half) & 1u;
+            clamped = (clamp_bits(ca, cb) >> half) & 1u;
         }
         double v[6];
         if (clamped) {

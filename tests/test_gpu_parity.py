@@ -253,6 +253,55 @@ def test_cluster_cut(P, oracle_mod, name, tau):
     assert st["cut_ambiguous"] <= 20
 
 
+def flat_patch_map(n, seed, patches):
+    """A random-disk map with square flat patches (texels [a, a + w) on both axes, one
+    normal v each): every cell inside a patch, and every node whose cluster fit covers
+    only patch texels (an exact fit, e^l = 0), has zero-area normal triangles."""
+    nrm = random_disk_map(n, seed, 0.45)
+    for a, w, v in patches:
+        nrm[a:a + w, a:a + w] = v
+    return nrm
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-2])
+def test_cluster_cut_on_clamped_cluster_triangles(P, oracle_mod, tau):
+    """Nodes inside a flat patch are under the cut for any tau > 0 (e^l = 0) and both
+    of their cluster triangles have zero area, so both are replaced by the small
+    equilateral triangle about the shared edge's midpoint (section on preventing the
+    Jacobian singularity).  Query normals at the patch normal lie inside those
+    replacements: the cut evaluation must hit them (a zero-area triangle tested as
+    stored would miss) and agree with the oracle."""
+    announce("eval cut tau=%g on clamped cluster triangles (flat patches, 32^2)" % tau)
+    patches = [(8, 6, (0.2, -0.1)), (20, 6, (-0.15, 0.25))]
+    nrm = flat_patch_map(32, 5, patches)
+    rng = np.random.default_rng(17)
+    nq = 301
+    q = np.zeros((nq, 6), dtype=np.float32)
+    which = rng.integers(0, len(patches), nq)
+    for j, (a, w, v) in enumerate(patches):
+        sel = which == j
+        q[sel, 0:2] = a + 0.5 * w + rng.uniform(-1.0, 1.0, (int(sel.sum()), 2))
+        q[sel, 4:6] = np.asarray(v, dtype=np.float32) + rng.uniform(-2e-5, 2e-5, (int(sel.sum()), 2))
+    q[:, 2] = rng.uniform(0.8, 3.0, nq)
+    q[:, 3] = q[:, 2] * np.exp(rng.uniform(-0.3, 0.3, nq))
+    _, hier = gpu_build(P, nrm, cluster=True)
+    st = run_parity(P, oracle_mod, nrm, q, tau=tau, hier=hier)
+    print(st)
+    assert st["nonzero"] >= 0.9 * nq and st["cut_ambiguous"] == 0, st
+    # some hits are cluster triangles of flat nodes (four equal fitted normals)
+    _, _, ids, _ = gpu_hits(P, hier, q, tau=tau)
+    lev, I, J, _ = oracle_mod.decode_id(ids)
+    flat_hits = 0
+    for level in sorted(set(lev[lev > 0].tolist())):
+        cn = P.hier_export_level(hier, level)["clu_n"].cpu().numpy()
+        assert np.isfinite(cn).all()      # the export holds the fitted normals themselves
+        sel = lev == level
+        v = cn[J[sel], I[sel]]            # (hits, 4, 2); patches are symmetric in I, J
+        flat_hits += int((v == v[:, :1]).all(axis=(1, 2)).sum())
+    print("cluster hits on flat nodes:", flat_hits)
+    assert flat_hits > 0
+
+
 def test_edge_cases(P, oracle_mod):
     import torch
     announce("eval edge cases")
