@@ -431,8 +431,8 @@ def sample_bench(args):
     mm = m.cpu().numpy()
     assert np.isfinite(mm).mean() > 0.999
     # algorithmic bytes per sample: query 24, one uniform pair 16, the sample 8, the
-    # unit's four corner normals 32 and clamp byte 1; with the cut, 4 per residual read
-    # (entry level down to the unit) and 1 for the cluster clamp byte instead
+    # unit's four corner normals 32 and its clamp bits 1 (a byte, for a cell or a
+    # cluster node alike); with the cut, 4 per residual read (entry level down to the unit)
     _, tri, _ = P.sample_batch(hier, tq, xi, tau=tau, sigma_to_r=s2r, kernel=kern)
     lev = (tri.cpu().numpy().view(np.uint64) >> np.uint64(58)).astype(np.int64)
     per = 81.0

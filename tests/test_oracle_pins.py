@@ -67,6 +67,48 @@ def test_flat_map_is_a_delta_at_its_normal(oracle_mod):
     assert out["D"][0] == 0.0 and out["nhit"][0] == 0
 
 
+@pytest.mark.parametrize("x,y,sx,sy", [(7.3, 8.6, 1.25, 1.25), (3.9, 12.2, 0.9, 2.1), (5.5, 9.25, 3.0, 3.0)])
+def test_flat_map_under_the_cut(oracle_mod, x, y, sx, sy):
+    """With the cut on a flat map every node's fit is exact (e^l = 0 <= t), so the
+    query stops at its entry level l0 = ceil(log2 max(r_x, r_y)) (supplement, 'Entry
+    level'): each node image whose closed square meets [x - r, x + r] (node-granular
+    images) answers with its two cluster triangles.  Both have zero area, so both are
+    replaced by the equilateral triangle of Jacobian eps about (N1 + N2) / 2, the map
+    normal (section 'Preventing Jacobian singularity', applied to clusters).  At that
+    normal the barycentrics are (1/3, 1/3, 1/3): the lower triangle adds k at the node
+    corner + (S/3, S/3), the upper at + (2S/3, 2S/3), S = 2^l0, each divided by eps."""
+    n, L = 16, 4
+    ns = np.array([0.125, -0.0625], dtype=np.float32)
+    nrm = np.broadcast_to(ns, (n, n, 2)).copy()
+    x, y, sx, sy = np.float32(x), np.float32(y), np.float32(sx), np.float32(sy)
+    rx, ry = np.float32(3) * sx, np.float32(3) * sy
+    l0 = min(L, max(0, math.ceil(math.log2(max(float(rx), float(ry))))))
+    assert l0 >= 1
+    S = 1 << l0
+
+    def origins(c, r):
+        lo, hi = float(np.float32(c) - r), float(np.float32(c) + r)
+        return [k * S for k in range(math.floor(lo / S) - 1, math.floor(hi / S) + 2)
+                if k * S + S >= lo and k * S <= hi]
+    ref = 0.0
+    nodes = set()   # a hit is one triangle; its term sums over the included images
+    m = n // S
+    for U0 in origins(x, rx):
+        for V0 in origins(y, ry):
+            nodes.add(((U0 // S) % m, (V0 // S) % m))
+            for o in (1.0 / 3.0, 2.0 / 3.0):
+                ref += gauss(U0 + o * S - float(x), V0 + o * S - float(y), float(sx), float(sy))
+    ref /= EPS
+    res = oracle_mod.evaluate(nrm, qrow(x, y, sx, sy, ns[0], ns[1]), tau=1e-3, records=True)
+    lev, I, J, half = oracle_mod.decode_id(res["hit_id"])
+    assert (lev == l0).all() and res["nhit"][0] == 2 * len(nodes)
+    assert set(zip(I.tolist(), J.tolist())) == nodes
+    assert res["D"][0] == pytest.approx(ref, rel=1e-10)
+    # the cells alone (no cut) give a different value at the same normal
+    cells = oracle_mod.evaluate(nrm, qrow(x, y, sx, sy, ns[0], ns[1]))
+    assert cells["nhit"][0] > res["nhit"][0] and cells["D"][0] != pytest.approx(ref, rel=1e-3)
+
+
 def test_flat_map_mass(oracle_mod):
     """Integral of D over the EqTri equals the footprint mass of the included cells."""
     n = 8
