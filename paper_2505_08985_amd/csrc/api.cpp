@@ -256,6 +256,8 @@ pndf_status pndf_build_hierarchy(const pndf_mesh* mesh, const pndf_hier_opts* op
         pndf_destroy_hierarchy(h);
         return hip_fail(e, "pndf_build_hierarchy");
     }
+    // per node: bbox 16, bbox_k 8; with clusters bbox_all 16, bbox_clu 16, bbox_c 8, bbox_u 8,
+    // grp 16, clu_n 32, clu_t 32, clu_e 4, clu_det 8; plus the level-1 leaf records
     h->bytes = (int64_t)nodes * (16 + 8 + (cluster ? 16 + 16 + 8 + 8 + 16 + 32 + 32 + 4 + 8 : 0)) +
                (int64_t)sizeof(QuadRec) * (m->n >> 1) * (m->n >> 1);
     *out = h;
